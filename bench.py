@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Throughput of the fast direct high-order FEM solve on one MI355X.
+
+Workload large_2d: -Lap u = f on [0,1]^2 with Dirichlet data, Lagrange order
+n = 9, K = 1024 elements per axis, (9*1024-1)^2 = 84,916,225 unknowns, f^h
+i.i.d. uniform[-1,1) (seed 0), resident in HBM before timing starts.
+
+A step is one whole solve (every pass of algorithm (a)).  `value` is the
+FP64 solve's unknowns/s; the FP32-transform solve with FP64 iterative
+refinement (3 steps by default) and the unrefined FP32 solve are timed the
+same way and reported beside it, with their relative l2 distance to the FP64
+solution.  Per-pass durations come from HIP events the library records
+around each kernel on the stream it runs on; `roofline` reports the pass
+that takes most time.  `cpu_baseline` times the CPU oracle (dense
+eigenvector products along both axes) on the host and, since it produces the
+exact solution, also yields the FP64 parity figure of the run.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+
+
+def kernel_sha():
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "capi.hip"):
+        with open(os.path.join(ROOT, "paper_1609_07758_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, kind):
+    """HBM bytes per launch of the dominant pass from the committed rocprofv3
+    counter summary, if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_sha") != kernel_sha():
+        return None
+    entry = d.get("passes", {}).get(kind)
+    return None if entry is None else entry.get("hbm_bytes_per_launch")
+
+
+def time_solves(torch, solve, steps, warmup):
+    for _ in range(warmup):
+        solve()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        solve()
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / steps
+
+
+def cpu_baseline(cfg, f_host, u_gpu64, u_ir):
+    """Time the oracle's dense solve on the host; return the record and the
+    parity of the GPU solutions against it."""
+    import numpy as np
+    from oracle import solve as osolve, spectral
+
+    t0 = time.perf_counter()
+    for n, K in zip(cfg["orders"], cfg["Ks"]):
+        spectral.basis(n, K)             # eigen data (cached) and dense V
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ref = osolve.solve(f_host, cfg["orders"], cfg["Ks"], cfg["X"], cfg["alpha"])
+    t_apply = time.perf_counter() - t0
+    M = ref.size
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((p.get("num_threads", 0) for p in threadpool_info()), default=cores)
+    except Exception:
+        threads = cores
+    nref = np.linalg.norm(ref)
+    par64 = float(np.linalg.norm(u_gpu64 - ref) / nref)
+    parir = float(np.linalg.norm(u_ir - ref) / nref)
+    rec = {"value": M / t_apply, "unit": "unknowns/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"whole {cfg['name']} right-hand side through the oracle's dense "
+                     f"eigenvector products (FP64, {t_apply:.1f} s); eigen data and dense V "
+                     f"construction timed apart: {t_setup:.1f} s"}
+    return rec, par64, parir
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="large_2d")
+    ap.add_argument("--ir-iters", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1609_07758_amd as H
+    import workloads
+
+    cfg = dict(workloads.CONFIGS[args.workload])
+    cfg["name"] = args.workload
+    shp = workloads.shape(cfg["orders"], cfg["Ks"])
+    M = int(np.prod(shp))
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    f_host = workloads.uniform_rhs(shp, seed=0)
+    f64 = torch.from_numpy(f_host).to(dev)
+    f32 = f64.float()
+    S = H.Solver(cfg["orders"], cfg["Ks"], cfg["X"], cfg["alpha"])
+    u64 = torch.empty_like(f64)
+    uir = torch.empty_like(f64)
+    u32 = torch.empty_like(f32)
+    ws = S.workspace("fp32_ir")
+    torch.cuda.synchronize()
+
+    # FP64 solve (the headline figure), with per-pass event timing.
+    S.set_timing(True)
+    for _ in range(args.warmup):
+        S.solve(f64, u64, mode="fp64")
+    S.pass_times()
+    ms64 = time_solves(torch, lambda: S.solve(f64, u64, mode="fp64"), args.steps, 0)
+    passes64 = S.pass_times()
+    S.set_timing(False)
+
+    # FP32 transforms + FP64 refinement, fixed number of steps (no host sync).
+    S.set_timing(True)
+    ms_ir = time_solves(torch, lambda: S.solve(f64, uir, mode="fp32_ir", ws=ws,
+                                               max_iter=args.ir_iters, tol=0.0),
+                        args.steps, args.warmup)
+    passes_ir = S.pass_times()
+    S.set_timing(False)
+    ms32 = time_solves(torch, lambda: S.solve(f32, u32, mode="fp32"), args.steps, args.warmup)
+
+    nrm = torch.linalg.vector_norm(u64)
+    ir_vs_64 = float(torch.linalg.vector_norm(uir - u64) / nrm)
+    f32_vs_64 = float(torch.linalg.vector_norm(u32.double() - u64) / nrm)
+    # refinement history: distance to the FP64 solution after 0..4 steps
+    hist = []
+    tmp = torch.empty_like(f64)
+    for it in range(0, 5):
+        S.solve(f64, tmp, mode="fp32_ir", ws=ws, max_iter=it, tol=0.0)
+        hist.append(float(torch.linalg.vector_norm(tmp - u64) / nrm))
+    torch.cuda.synchronize()
+
+    dom = max(passes64, key=lambda p: p["ms"])
+    avg_ms = dom["ms"] / dom["launches"]
+    achieved = dom["bytes"] / (avg_ms * 1e-3) / 1e9
+    kind = f"{dom['kind']}_axis{dom['axis']}_fp64"
+    traffic = measured_traffic(args.workload, kind)
+
+    record = {
+        "metric": "unknowns/s, 2D n=9 K=2^10: FP64 vs FP32+refine @1e-12 rel L2; % HBM peak",
+        "value": M / (ms64 * 1e-3),
+        "unit": "unknowns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms64,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "N": len(shp), "order_n": cfg["orders"][0],
+                   "K_per_axis": cfg["Ks"][0], "unknowns": M, "rhs": "uniform[-1,1) seed 0",
+                   "alpha": cfg["alpha"]},
+        "fp32_refined": {"unknowns_per_s": M / (ms_ir * 1e-3), "ms_per_step": ms_ir,
+                         "refinement_steps": args.ir_iters,
+                         "speedup_vs_fp64": ms64 / ms_ir,
+                         "rel_l2_vs_fp64_gpu": ir_vs_64,
+                         "rel_l2_vs_fp64_gpu_by_steps": hist},
+        "fp32_unrefined": {"unknowns_per_s": M / (ms32 * 1e-3), "ms_per_step": ms32,
+                           "rel_l2_vs_fp64_gpu": f32_vs_64},
+        "passes_fp64": [dict(p, avg_ms=p["ms"] / p["launches"],
+                             gbs=p["bytes"] / (p["ms"] / p["launches"] * 1e-3) / 1e9)
+                        for p in passes64],
+        "passes_fp32_refined": [dict(p, avg_ms=p["ms"] / p["launches"]) for p in passes_ir],
+        "roofline": {"bound": "hbm", "kernel": kind, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": dom["bytes"], "avg_launch_ms": avg_ms},
+        "kernel_sha": kernel_sha(),
+    }
+    if not args.no_cpu_baseline:
+        rec, par64, parir = cpu_baseline(cfg, f_host, u64.cpu().numpy(), uir.cpu().numpy())
+        record["cpu_baseline"] = rec
+        record["parity_vs_oracle"] = {"fp64_rel_l2": par64, "fp32_refined_rel_l2": parir}
+    else:
+        record["cpu_baseline"] = None
+    print(json.dumps(record), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,213 @@
+/*
+ * hofem.h -- C ABI of the MI355X (gfx950) fast direct solver for nth-order
+ * Lagrange finite elements on rectangular boxes with Dirichlet data.
+ *
+ * The method is that of A. Zlotnik and I. Zlotnik, "A direct fast FFT-based
+ * implementation for high order finite element method on rectangular
+ * parallelepipeds for PDE" (arXiv:1609.07758), Section 2:
+ *
+ *   (sum_i 4 h_i^-2 A_i (x)_{j!=i} C_j + alpha (x)_j C_j) v = f^h       eq. (bvp glob 2)
+ *
+ * is solved by expanding f^h in the C-orthogonal eigenvectors of the 1D
+ * pencils A_i v = lambda C_i v (Theorem 1), dividing by the sums of scaled
+ * eigenvalues (eq. (decomp v 2)) and transforming back (algorithm (a)).  The
+ * direct and inverse transforms along an axis use n sine transforms of
+ * length K-1 coupled by n x n blocks per wave number (transform theorem).
+ *
+ * Conventions shared by all calls
+ * ------------------------------
+ * Grid layout.  Per axis i the unknowns are the values at the m_i = n_i K_i - 1
+ * interior points q h_i / n_i (q = 1..m_i, h_i = X_i / K_i): mesh nodes and
+ * element-interior Lagrange nodes, in physical order; the Dirichlet zeros are
+ * implicit.  An N-D grid is dense C order [nrhs][m_0]...[m_{N-1}] (the last
+ * axis is contiguous).  The right-hand side is the algebraic f^h of
+ * eq. (bvp glob 2): the load vector int f phi divided by prod_i (h_i / 2).
+ *
+ * Memory.  Pointers named *_dev are device pointers on the current HIP
+ * device, owned by the caller.  Pointers named *_host are host memory owned
+ * by the caller.  Handles are owned by the library and released by the
+ * matching destroy call.  Solver creation allocates the solver's device
+ * tables (a few MB at most) with hipMalloc on the current device; no other
+ * call allocates device memory: temporary storage is the caller's
+ * workspace, sized by hofem_solver_workspace_bytes.
+ *
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = default
+ * stream).  Calls enqueue work and return without synchronising, except
+ * where `info` is non-NULL (the call then waits for the stream to read the
+ * iteration statistics back).
+ *
+ * Errors.  Every int-returning call returns HOFEM_OK or a negative status.
+ * Argument errors are detected before any work is enqueued and leave all
+ * outputs untouched.  HOFEM_EHIP reports a failed HIP runtime call; its code
+ * is available from hofem_last_hip_error().
+ */
+#ifndef HOFEM_H
+#define HOFEM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum hofem_status {
+  HOFEM_OK = 0,
+  HOFEM_EINVAL = -1,        /* invalid argument (null pointer, size, ...) */
+  HOFEM_EUNSUPPORTED = -2,  /* valid but unsupported parameters (n, K, N) */
+  HOFEM_ENOTPOSDEF = -3,    /* alpha makes the operator indefinite */
+  HOFEM_ENOCONV = -4,       /* refinement did not reach the tolerance */
+  HOFEM_EHIP = -5,          /* HIP runtime failure */
+  HOFEM_ENOMEM = -6         /* host or device allocation failed */
+};
+
+/* Arithmetic of a solve. */
+enum hofem_mode {
+  HOFEM_MODE_FP64 = 0,     /* FP64 transforms; f, u are double */
+  HOFEM_MODE_FP32 = 1,     /* FP32 transforms with FP32 accumulation; f, u are float */
+  HOFEM_MODE_FP32_IR = 2   /* FP32 transforms + FP64 iterative refinement; f, u are double */
+};
+
+typedef struct hofem_plan1d_s* hofem_plan1d;
+typedef struct hofem_solver_s* hofem_solver;
+
+/* Statistics of the last solve (filled when `info` is non-NULL). */
+typedef struct {
+  int iterations;          /* refinement steps taken (0 for direct modes) */
+  double rel_update;       /* ||last correction||_2 / ||u||_2 */
+} hofem_info;
+
+/* ---- 1D eigen data (host) -------------------------------------------- */
+
+/* Eigen data of the 1D pencil A v = lambda C v of eq. (eig_glob) for order
+ * n and K elements (Section 2, paragraphs 1-3): the n roots of eq. (theta)
+ * for every theta_k = cos(pi k / K), the vectors p_k^(l) of Lemma 2, the
+ * norms ||s_k^(l)||_C^2 of the transform theorem, and the interior-node
+ * eigenpairs of eq. (eig_elem).  Computed on the host in binary128 and
+ * rounded once.  1 <= n <= 9 (simple element spectra are verified up to 9),
+ * K a power of two with 2 <= K <= 1024.  Returns HOFEM_EUNSUPPORTED
+ * otherwise.  Plans are immutable and may be shared between threads. */
+int hofem_plan1d_create(int n, int K, hofem_plan1d* out);
+void hofem_plan1d_destroy(hofem_plan1d plan);
+
+/* Number of unknowns m = nK - 1 of the plan's axis. */
+int hofem_plan1d_dim(hofem_plan1d plan, int* m);
+
+/* Host copies of the plan's tables, for inspection and tests.  `which`:
+ *   0  scaled eigenvalues lambda in coefficient order (m values)
+ *   1  p_k^(l): index ((k-1) n + l-1) (n-1) + i          ((K-1) n (n-1) values)
+ *   2  1 / ||s_k^(l)||_C^2: index (k-1) n + l-1          ((K-1) n values)
+ *   3  e^(l) as columns: index i (n-1) + l-1              ((n-1)^2 values)
+ *   4  local stiffness A on [-1, 1], row major           ((n+1)^2 values)
+ *   5  local mass C on [-1, 1], row major                ((n+1)^2 values)
+ * The coefficient index of a line is q = l-1 for k = 0 (l = 1..n-1) and
+ * q = n k - 1 + l-1 for k = 1..K-1 (l = 1..n).  `len` must equal the count;
+ * otherwise HOFEM_EINVAL. */
+int hofem_plan1d_table(hofem_plan1d plan, int which, double* out_host, size_t len);
+
+/* ---- N-D solver (device) ---------------------------------------------- */
+
+/* Solver for eq. (bvp glob 2) on (0,X_0) x ... x (0,X_{N-1}), 1 <= N <= 3,
+ * with one plan per axis (plans[i] for axis i; the same plan may be used for
+ * several axes) and the constant alpha.  Checks that every denominator
+ * alpha + sum_i 4 h_i^-2 lambda_i is positive (the condition on alpha of
+ * eq. (diff bvp pr2)), else HOFEM_ENOTPOSDEF.  Allocates and uploads the
+ * FP64 and FP32 tables on the current device.  The plans may be destroyed
+ * after this call. */
+int hofem_solver_create(int N, const hofem_plan1d* plans, const double* X, double alpha,
+                        hofem_solver* out);
+void hofem_solver_destroy(hofem_solver solver);
+
+/* Total number of unknowns prod_i m_i of one right-hand side. */
+int hofem_solver_size(hofem_solver solver, size_t* unknowns);
+
+/* Workspace bytes that hofem_solve needs for `mode` and `nrhs`. */
+int hofem_solver_workspace_bytes(hofem_solver solver, int mode, int nrhs, size_t* bytes);
+
+/* Solve eq. (bvp glob 2) for nrhs right-hand sides by algorithm (a):
+ * direct transforms along axes N-1..1, then along axis 0 the direct
+ * transform, the division by alpha + sum_i 4 h_i^-2 lambda_i and the
+ * inverse transform in one pass, then inverse transforms along axes 1..N-1.
+ * Step (1) of algorithm (a) (the mass solve) is not performed: applying the
+ * direct transforms to f^h itself gives the same coefficients, because the
+ * transforms take y = C w as their input.
+ *   f_dev, u_dev : [nrhs][m_0]..[m_{N-1}], double (FP64, FP32_IR) or float
+ *                  (FP32).  u_dev == f_dev (in place) is allowed for FP64
+ *                  and FP32, not for FP32_IR.
+ *   ws_dev       : workspace of at least hofem_solver_workspace_bytes
+ *                  (may be NULL when that is 0).
+ *   max_iter,tol : FP32_IR only: at most max_iter refinement steps after the
+ *                  first FP32 solve, stopping once ||delta||_2 <= tol ||u||_2
+ *                  (tol <= 0: exactly max_iter steps).  Each step computes
+ *                  the residual f^h - L u in FP64 with the stiffness in
+ *                  difference form and adds the FP32 solve of it to u.
+ *                  Returns HOFEM_ENOCONV (u holds the last iterate) when
+ *                  tol > 0 and the tolerance was not reached; detecting
+ *                  this needs `info` or tol > 0 (the call then waits).
+ * Calls that overlap on one solver must use the same stream. */
+int hofem_solve(hofem_solver solver, int mode, const void* f_dev, void* u_dev, int nrhs,
+                void* ws_dev, size_t ws_bytes, int max_iter, double tol, void* stream,
+                hofem_info* info);
+
+/* Direct F_n-transforms along every axis (step (2) of algorithm (a)):
+ * out = coefficients w_{k l} of eq. (decomp phi 2) of C^-1 in, in coefficient
+ * order per axis (see hofem_plan1d_table).  mode FP64 (double) or FP32
+ * (float).  in_dev == out_dev allowed. */
+int hofem_forward(hofem_solver solver, int mode, const void* in_dev, void* out_dev, int nrhs,
+                  void* stream);
+
+/* Inverse F_n-transforms along every axis (step (3) of algorithm (a)):
+ * out = sum of coefficient * eigenvector products.  in_dev == out_dev allowed. */
+int hofem_inverse(hofem_solver solver, int mode, const void* in_dev, void* out_dev, int nrhs,
+                  void* stream);
+
+/* out = L u with L the operator of eq. (bvp glob 2), FP64, matrix-free,
+ * element by element, the stiffness factors in difference form
+ * sum_{l != k} A_kl (v_l - v_k) so that constants are exactly in their
+ * kernel.  u_dev != out_dev. */
+int hofem_apply_operator(hofem_solver solver, const double* u_dev, double* out_dev, int nrhs,
+                         void* stream);
+
+/* ---- per-pass timing (profiling aid) ----------------------------------- */
+
+/* Kinds of device work the solver enqueues. */
+enum hofem_pass_kind {
+  HOFEM_PASS_FORWARD = 0,   /* direct transform along one axis */
+  HOFEM_PASS_INVERSE = 1,   /* inverse transform along one axis */
+  HOFEM_PASS_FUSED = 2,     /* direct transform, division, inverse transform */
+  HOFEM_PASS_OPERATOR = 3,  /* FP64 residual / operator apply */
+  HOFEM_PASS_UPDATE = 4     /* refinement update and norms */
+};
+
+typedef struct {
+  int kind;                 /* hofem_pass_kind */
+  int axis;                 /* axis of a transform pass, -1 otherwise */
+  int fp64;                 /* 1: FP64 arithmetic, 0: FP32 */
+  long long launches;       /* launches recorded since the last read */
+  double ms;                /* their summed duration (HIP events, milliseconds) */
+  double bytes;             /* algorithmic bytes of one launch: one read and one
+                               write of every value the pass streams */
+} hofem_pass_time;
+
+/* When enabled, every kernel launch of this solver is bracketed by HIP events
+ * recorded on the call's stream (event objects only: no device allocation).
+ * At most 4096 launches are recorded between two reads; later launches are
+ * not timed. */
+int hofem_solver_set_timing(hofem_solver solver, int enable);
+
+/* Waits for the recorded events, writes up to `max_entries` aggregates (one
+ * per kind, axis and precision, in first-launch order) to out_host, sets
+ * *count to their number and clears the record. */
+int hofem_solver_pass_times(hofem_solver solver, hofem_pass_time* out_host, int max_entries,
+                            int* count);
+
+/* Human-readable name of a status code (static string). */
+const char* hofem_status_string(int status);
+
+/* hipError_t of the last failed HIP call in this thread (0 if none). */
+int hofem_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HOFEM_H */

@@ -124,9 +124,10 @@ def interior_eigen(n, dps=40):
 
     Returns (lam0, E): lam0 ascending (n-1 mpf values), E an (n-1)x(n-1)
     mpmath matrix whose column l is e^(l) with C~ e^(l) . e^(l) = 1.  The
-    sign of each column is fixed so that its first entry of largest
-    magnitude is positive (any sign is admissible: the basis only enters the
-    solve through products that contain it twice).
+    sign of each column is fixed so that its lowest-index entry of magnitude
+    at least half the largest is positive (Lemma 1 leaves the sign free; the
+    basis only enters the solve through products that contain it twice, and
+    a rule with a margin does not depend on rounding).
     """
     with mp.workdps(dps):
         A, C = local_matrices(n)
@@ -135,8 +136,9 @@ def interior_eigen(n, dps=40):
         lam, X = generalized_eigh_mp(to_mp(At), to_mp(Ct))
         X = mp.matrix([[mp.re(X[i, j]) for j in range(X.cols)] for i in range(X.rows)])
         for j in range(X.cols):
-            big = max(range(X.rows), key=lambda i: abs(X[i, j]))
-            if X[big, j] < 0:
+            top = max(abs(X[i, j]) for i in range(X.rows))
+            lead = next(i for i in range(X.rows) if abs(X[i, j]) >= top / 2)
+            if X[lead, j] < 0:
                 for i in range(X.rows):
                     X[i, j] = -X[i, j]
         return lam, X

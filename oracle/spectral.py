@@ -41,7 +41,7 @@ from .assembly import assemble_1d, assemble_1d_sparse, dim
 # mpmath working precision (decimal digits) of the structured route; quad
 # precision is about 34 digits.
 DPS = 40
-_CACHE_VERSION = 1
+_CACHE_VERSION = 3
 
 
 def eigen_dense(n, K):

@@ -1,0 +1,309 @@
+"""Python binding of libhofem, the MI355X fast direct solver for nth-order
+Lagrange FEM on boxes (Zlotnik & Zlotnik, arXiv:1609.07758, Section 2).
+
+The functions below carry the names of the C entry points declared in
+include/hofem.h and only marshal arguments: every step of a solve runs in the
+library's HIP kernels.  Device buffers are torch tensors on the current HIP
+device (torch provides memory and streams only).  The library must have been
+built (``python paper_1609_07758_amd/csrc/build.py``); importing the binding
+without it raises ImportError, and there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhofem.so")
+
+HOFEM_OK = 0
+HOFEM_EINVAL = -1
+HOFEM_EUNSUPPORTED = -2
+HOFEM_ENOTPOSDEF = -3
+HOFEM_ENOCONV = -4
+HOFEM_EHIP = -5
+HOFEM_ENOMEM = -6
+
+MODES = {"fp64": 0, "fp32": 1, "fp32_ir": 2}
+TABLES = {"lam": 0, "p": 1, "inorm": 2, "E": 3, "A": 4, "C": 5}
+
+# Names and signatures of every entry point of include/hofem.h.
+_c_int, _c_double, _c_size, _vp = ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p
+
+
+class hofem_info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("rel_update", ctypes.c_double)]
+
+
+class hofem_pass_time(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("axis", ctypes.c_int), ("fp64", ctypes.c_int),
+                ("launches", ctypes.c_longlong), ("ms", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+PASS_KINDS = {0: "forward", 1: "inverse", 2: "fused", 3: "operator", 4: "update"}
+
+
+SIGNATURES = {
+    "hofem_plan1d_create": (_c_int, [_c_int, _c_int, ctypes.POINTER(_vp)]),
+    "hofem_plan1d_destroy": (None, [_vp]),
+    "hofem_plan1d_dim": (_c_int, [_vp, ctypes.POINTER(_c_int)]),
+    "hofem_plan1d_table": (_c_int, [_vp, _c_int, ctypes.POINTER(_c_double), _c_size]),
+    "hofem_solver_create": (_c_int, [_c_int, ctypes.POINTER(_vp), ctypes.POINTER(_c_double), _c_double,
+                                     ctypes.POINTER(_vp)]),
+    "hofem_solver_destroy": (None, [_vp]),
+    "hofem_solver_size": (_c_int, [_vp, ctypes.POINTER(_c_size)]),
+    "hofem_solver_workspace_bytes": (_c_int, [_vp, _c_int, _c_int, ctypes.POINTER(_c_size)]),
+    "hofem_solve": (_c_int, [_vp, _c_int, _vp, _vp, _c_int, _vp, _c_size, _c_int, _c_double, _vp,
+                             ctypes.POINTER(hofem_info)]),
+    "hofem_forward": (_c_int, [_vp, _c_int, _vp, _vp, _c_int, _vp]),
+    "hofem_inverse": (_c_int, [_vp, _c_int, _vp, _vp, _c_int, _vp]),
+    "hofem_apply_operator": (_c_int, [_vp, _vp, _vp, _c_int, _vp]),
+    "hofem_solver_set_timing": (_c_int, [_vp, _c_int]),
+    "hofem_solver_pass_times": (_c_int, [_vp, ctypes.POINTER(hofem_pass_time), _c_int,
+                                         ctypes.POINTER(_c_int)]),
+    "hofem_status_string": (ctypes.c_char_p, [_c_int]),
+    "hofem_last_hip_error": (_c_int, []),
+}
+
+
+class HofemError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = _lib.hofem_status_string(status).decode() if _lib else str(status)
+        if status == HOFEM_EHIP and _lib:
+            msg += f" (hipError {_lib.hofem_last_hip_error()})"
+        super().__init__(f"{where}: {msg} [{status}]")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "'python paper_1609_07758_amd/csrc/build.py'")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def _check(status, where):
+    if status != HOFEM_OK:
+        raise HofemError(status, where)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+# ---- C entry points, same names ------------------------------------------
+
+def hofem_plan1d_create(n, K):
+    h = ctypes.c_void_p()
+    _check(_lib.hofem_plan1d_create(int(n), int(K), ctypes.byref(h)), "hofem_plan1d_create")
+    return h
+
+
+def hofem_plan1d_destroy(plan):
+    _lib.hofem_plan1d_destroy(plan)
+
+
+def hofem_plan1d_dim(plan):
+    m = ctypes.c_int()
+    _check(_lib.hofem_plan1d_dim(plan, ctypes.byref(m)), "hofem_plan1d_dim")
+    return m.value
+
+
+def hofem_plan1d_table(plan, which, count):
+    out = np.zeros(count, dtype=np.float64)
+    w = TABLES[which] if isinstance(which, str) else int(which)
+    _check(_lib.hofem_plan1d_table(plan, w, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   out.size), "hofem_plan1d_table")
+    return out
+
+
+def hofem_solver_create(plans, X, alpha):
+    N = len(plans)
+    arr = (ctypes.c_void_p * N)(*[p.value if isinstance(p, ctypes.c_void_p) else p for p in plans])
+    xs = (ctypes.c_double * N)(*[float(x) for x in X])
+    h = ctypes.c_void_p()
+    _check(_lib.hofem_solver_create(N, arr, xs, float(alpha), ctypes.byref(h)), "hofem_solver_create")
+    return h
+
+
+def hofem_solver_destroy(solver):
+    _lib.hofem_solver_destroy(solver)
+
+
+def hofem_solver_size(solver):
+    s = ctypes.c_size_t()
+    _check(_lib.hofem_solver_size(solver, ctypes.byref(s)), "hofem_solver_size")
+    return s.value
+
+
+def hofem_solver_workspace_bytes(solver, mode, nrhs=1):
+    s = ctypes.c_size_t()
+    _check(_lib.hofem_solver_workspace_bytes(solver, MODES[mode], int(nrhs), ctypes.byref(s)),
+           "hofem_solver_workspace_bytes")
+    return s.value
+
+
+def hofem_solve(solver, mode, f, u, nrhs=1, ws=None, max_iter=0, tol=0.0, stream=None,
+                want_info=False, raise_noconv=True):
+    info = hofem_info() if want_info else None
+    wsb = 0 if ws is None else ws.numel() * ws.element_size()
+    st = _lib.hofem_solve(solver, MODES[mode], _ptr(f), _ptr(u), int(nrhs), _ptr(ws), wsb,
+                          int(max_iter), float(tol), _stream(stream),
+                          ctypes.byref(info) if info is not None else None)
+    if st == HOFEM_ENOCONV and not raise_noconv:
+        return info, st
+    _check(st, "hofem_solve")
+    return info, st
+
+
+def hofem_forward(solver, mode, x, y, nrhs=1, stream=None):
+    _check(_lib.hofem_forward(solver, MODES[mode], _ptr(x), _ptr(y), int(nrhs), _stream(stream)),
+           "hofem_forward")
+
+
+def hofem_inverse(solver, mode, x, y, nrhs=1, stream=None):
+    _check(_lib.hofem_inverse(solver, MODES[mode], _ptr(x), _ptr(y), int(nrhs), _stream(stream)),
+           "hofem_inverse")
+
+
+def hofem_apply_operator(solver, u, out, nrhs=1, stream=None):
+    _check(_lib.hofem_apply_operator(solver, _ptr(u), _ptr(out), int(nrhs), _stream(stream)),
+           "hofem_apply_operator")
+
+
+def hofem_solver_set_timing(solver, enable):
+    _check(_lib.hofem_solver_set_timing(solver, 1 if enable else 0), "hofem_solver_set_timing")
+
+
+def hofem_solver_pass_times(solver, max_entries=64):
+    arr = (hofem_pass_time * max_entries)()
+    cnt = ctypes.c_int()
+    _check(_lib.hofem_solver_pass_times(solver, arr, max_entries, ctypes.byref(cnt)),
+           "hofem_solver_pass_times")
+    return [dict(kind=PASS_KINDS.get(a.kind, str(a.kind)), axis=a.axis, fp64=bool(a.fp64),
+                 launches=a.launches, ms=a.ms, bytes=a.bytes) for a in arr[:cnt.value]]
+
+
+# ---- convenience wrappers -------------------------------------------------
+
+class Plan1D:
+    """1D eigen data for order n and K elements (host, binary128 precompute)."""
+
+    def __init__(self, n, K):
+        self.n, self.K = int(n), int(K)
+        self.handle = hofem_plan1d_create(n, K)
+        self.m = hofem_plan1d_dim(self.handle)
+
+    def table(self, which):
+        n, K = self.n, self.K
+        counts = {"lam": self.m, "p": (K - 1) * n * (n - 1), "inorm": (K - 1) * n,
+                  "E": (n - 1) ** 2, "A": (n + 1) ** 2, "C": (n + 1) ** 2}
+        return hofem_plan1d_table(self.handle, which, counts[which])
+
+    def close(self):
+        if self.handle is not None:
+            hofem_plan1d_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Solver:
+    """Solver of (sum_i 4 h_i^-2 A_i (x) C_others + alpha (x)C) v = f^h on a box."""
+
+    def __init__(self, orders, Ks, X, alpha=0.0):
+        self.orders = [int(n) for n in orders]
+        self.Ks = [int(k) for k in Ks]
+        self.X = [float(x) for x in X]
+        self.alpha = float(alpha)
+        plans = [Plan1D(n, K) for n, K in zip(self.orders, self.Ks)]
+        self.shape = tuple(p.m for p in plans)
+        self.handle = hofem_solver_create([p.handle for p in plans], self.X, self.alpha)
+        for p in plans:
+            p.close()
+        self.size = hofem_solver_size(self.handle)
+
+    def workspace(self, mode, nrhs=1, device="cuda"):
+        import torch
+        b = hofem_solver_workspace_bytes(self.handle, mode, nrhs)
+        if b == 0:
+            return None
+        return torch.empty(b, dtype=torch.uint8, device=device)
+
+    def _check_grid(self, t, dtype, nrhs, name):
+        import torch
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous device tensor")
+        if t.dtype != dtype:
+            raise ValueError(f"{name} must be {dtype}")
+        if t.numel() != self.size * nrhs:
+            raise ValueError(f"{name} has {t.numel()} elements, expected {self.size * nrhs}")
+        return t
+
+    def solve(self, f, u=None, mode="fp64", nrhs=1, max_iter=3, tol=0.0, ws=None, stream=None,
+              want_info=False, raise_noconv=True):
+        import torch
+        dt = torch.float32 if mode == "fp32" else torch.float64
+        self._check_grid(f, dt, nrhs, "f")
+        if u is None:
+            u = torch.empty_like(f)
+        self._check_grid(u, dt, nrhs, "u")
+        if mode == "fp32_ir" and ws is None:
+            ws = self.workspace(mode, nrhs, f.device)
+        info, st = hofem_solve(self.handle, mode, f, u, nrhs, ws, max_iter, tol, stream, want_info,
+                               raise_noconv)
+        return (u, info, st) if want_info else u
+
+    def forward(self, x, y=None, mode="fp64", nrhs=1, stream=None):
+        import torch
+        y = torch.empty_like(x) if y is None else y
+        hofem_forward(self.handle, mode, x, y, nrhs, stream)
+        return y
+
+    def inverse(self, x, y=None, mode="fp64", nrhs=1, stream=None):
+        import torch
+        y = torch.empty_like(x) if y is None else y
+        hofem_inverse(self.handle, mode, x, y, nrhs, stream)
+        return y
+
+    def apply_operator(self, u, out=None, nrhs=1, stream=None):
+        import torch
+        out = torch.empty_like(u) if out is None else out
+        hofem_apply_operator(self.handle, u, out, nrhs, stream)
+        return out
+
+    def set_timing(self, enable=True):
+        hofem_solver_set_timing(self.handle, enable)
+
+    def pass_times(self):
+        return hofem_solver_pass_times(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            hofem_solver_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,526 @@
+// C ABI of the solver: plans, device tables, pass schedule, refinement loop.
+//
+// Pass schedule of algorithm (a) (Section 2, paragraph 4) for N axes
+// (axis N-1 contiguous): direct transforms along N-1, ..., 1; along axis 0
+// one fused pass (direct transform, division by alpha + sum_i 4 h_i^-2
+// lambda_i, inverse transform); inverse transforms along 1, ..., N-1.  Each
+// pass reads and writes the grid once.  Step (1) of the algorithm (the mass
+// solve) is not needed: the direct transform takes y = C w as its input, and
+// f^h is exactly that y for w = phi^h.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "hofem.h"
+#include "kernels.h"
+#include "plan1d.h"
+
+using namespace hofem;
+
+struct hofem_plan1d_s {
+  Plan1DData d;
+};
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+int hip_fail(hipError_t e) {
+  g_last_hip = (int)e;
+  return HOFEM_EHIP;
+}
+
+#define HIPCHK(x)                               \
+  do {                                          \
+    hipError_t e_ = (x);                        \
+    if (e_ != hipSuccess) return hip_fail(e_);  \
+  } while (0)
+
+struct DevAxis {
+  int n = 0, K = 0, m = 0;
+  double X = 0, scale = 0;
+  AxisTab t64{}, t32{};
+  const double* A = nullptr;
+  const double* C = nullptr;
+};
+
+// Packs host arrays into one byte buffer with 256-byte aligned offsets.
+struct Packer {
+  std::vector<unsigned char> bytes;
+  size_t add(const void* src, size_t n) {
+    size_t off = (bytes.size() + 255) & ~size_t(255);
+    bytes.resize(off + std::max<size_t>(n, 8), 0);
+    if (n) std::memcpy(bytes.data() + off, src, n);
+    return off;
+  }
+  size_t add_f64(const std::vector<double>& v) { return add(v.data(), v.size() * sizeof(double)); }
+  size_t add_f32(const std::vector<double>& v) {
+    std::vector<float> f(v.size());
+    for (size_t i = 0; i < v.size(); ++i) f[i] = (float)v[i];
+    return add(f.data(), f.size() * sizeof(float));
+  }
+};
+
+constexpr int kNormParts = 1024;
+
+}  // namespace
+
+struct TimedLaunch {
+  int kind, axis, fp64;
+  double bytes;
+  hipEvent_t start, stop;
+};
+
+struct hofem_solver_s {
+  int N = 0;
+  double alpha = 0;
+  int device = 0;
+  DevAxis ax[3];
+  void* mem = nullptr;
+  size_t per_rhs = 0;
+  // per-pass timing
+  bool timing = false;
+  std::vector<hipEvent_t> event_pool;
+  std::vector<TimedLaunch> records;
+};
+
+namespace {
+
+constexpr size_t kMaxRecords = 4096;
+
+// Brackets one launch with events when timing is enabled.
+struct LaunchTimer {
+  hofem_solver_s* S;
+  hipStream_t st;
+  TimedLaunch rec{};
+  bool on = false;
+  LaunchTimer(hofem_solver_s* s, hipStream_t stream, int kind, int axis, int fp64, double bytes)
+      : S(s), st(stream) {
+    if (!S->timing || S->records.size() >= kMaxRecords) return;
+    const size_t need = 2 * (S->records.size() + 1);
+    while (S->event_pool.size() < need) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      S->event_pool.push_back(e);
+    }
+    rec = TimedLaunch{kind, axis, fp64, bytes, S->event_pool[need - 2], S->event_pool[need - 1]};
+    on = hipEventRecord(rec.start, st) == hipSuccess;
+  }
+  void done() {
+    if (on && hipEventRecord(rec.stop, st) == hipSuccess) S->records.push_back(rec);
+    on = false;
+  }
+};
+
+struct PassSpec {
+  int axis, kind;
+};
+
+PassArgs make_args(const hofem_solver_s* S, int axis, int kind, bool f64, const void* in, void* out,
+                   int nrhs) {
+  PassArgs a{};
+  a.in = in;
+  a.out = out;
+  const DevAxis& X = S->ax[axis];
+  a.tab = f64 ? X.t64 : X.t32;
+  long long inner = 1, others = 1;
+  for (int i = 0; i < S->N; ++i) {
+    if (i > axis) inner *= S->ax[i].m;
+    if (i != axis) others *= S->ax[i].m;
+  }
+  a.inner = inner;
+  a.nlines = others * nrhs;
+  size_t lds = 0;
+  pass_shape(X.n, X.K, f64 ? 1 : 0, a.nlines, inner, &a.cb, &lds);
+  if (kind == PASS_FUSED) {
+    a.alpha = S->alpha;
+    a.scale = X.scale;
+    a.nother = 0;
+    for (int i = 0; i < S->N; ++i) {
+      if (i == axis) continue;
+      long long div = 1;
+      for (int j = i + 1; j < S->N; ++j)
+        if (j != axis) div *= S->ax[j].m;
+      a.olam[a.nother] = S->ax[i].t64.lam;
+      a.oscale[a.nother] = S->ax[i].scale;
+      a.odiv[a.nother] = div;
+      a.omod[a.nother] = S->ax[i].m;
+      ++a.nother;
+    }
+  }
+  return a;
+}
+
+// Runs a list of passes: the first reads in0, the last writes outl, the
+// others work in place on buf.  dt codes as in launch_pass.
+int run_list(hofem_solver_s* S, const std::vector<PassSpec>& list, bool f64, const void* in0,
+             void* buf, void* outl, int dt_first, int dt_mid, int dt_last, int dt_single, int nrhs,
+             hipStream_t st) {
+  for (size_t i = 0; i < list.size(); ++i) {
+    const void* in = (i == 0) ? in0 : buf;
+    void* out = (i + 1 == list.size()) ? outl : buf;
+    int dt;
+    if (list.size() == 1) dt = dt_single;
+    else if (i == 0) dt = dt_first;
+    else if (i + 1 == list.size()) dt = dt_last;
+    else dt = dt_mid;
+    PassArgs a = make_args(S, list[i].axis, list[i].kind, f64, in, out, nrhs);
+    if (a.nlines == 0) continue;
+    static const int in_bytes[6] = {8, 4, 8, 4, 4, 8}, out_bytes[6] = {8, 4, 4, 8, 16, 8};
+    const double bytes = (double)S->per_rhs * nrhs * (in_bytes[dt] + out_bytes[dt]);
+    LaunchTimer tm(S, st, list[i].kind, list[i].axis, f64 ? 1 : 0, bytes);
+    HIPCHK(launch_pass(list[i].kind, dt, a, st));
+    tm.done();
+  }
+  return HOFEM_OK;
+}
+
+std::vector<PassSpec> solve_list(int N) {
+  std::vector<PassSpec> l;
+  for (int a = N - 1; a >= 1; --a) l.push_back({a, PASS_FWD});
+  l.push_back({0, PASS_FUSED});
+  for (int a = 1; a < N; ++a) l.push_back({a, PASS_INV});
+  return l;
+}
+
+size_t ir_workspace(const hofem_solver_s* S, int nrhs) {
+  size_t b = S->per_rhs * (size_t)nrhs * sizeof(float);
+  b = (b + 255) & ~size_t(255);
+  b += (2 * kNormParts + 2) * sizeof(double);
+  return b;
+}
+
+OpArgs make_op(const hofem_solver_s* S, const double* u, const double* f, void* out, int out_f32,
+               int nrhs) {
+  OpArgs o{};
+  o.u = u;
+  o.f = f;
+  o.out = out;
+  o.out_f32 = out_f32;
+  o.N = S->N;
+  for (int i = 0; i < S->N; ++i) {
+    o.n[i] = S->ax[i].n;
+    o.K[i] = S->ax[i].K;
+    o.m[i] = S->ax[i].m;
+    o.scale[i] = S->ax[i].scale;
+    o.A[i] = S->ax[i].A;
+    o.C[i] = S->ax[i].C;
+  }
+  o.alpha = S->alpha;
+  o.nrhs = nrhs;
+  return o;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hofem_status_string(int status) {
+  switch (status) {
+    case HOFEM_OK: return "ok";
+    case HOFEM_EINVAL: return "invalid argument";
+    case HOFEM_EUNSUPPORTED: return "unsupported parameters";
+    case HOFEM_ENOTPOSDEF: return "operator not positive definite for this alpha";
+    case HOFEM_ENOCONV: return "refinement did not converge";
+    case HOFEM_EHIP: return "HIP runtime error";
+    case HOFEM_ENOMEM: return "out of memory";
+    default: return "unknown status";
+  }
+}
+
+int hofem_last_hip_error(void) { return g_last_hip; }
+
+int hofem_plan1d_create(int n, int K, hofem_plan1d* out) {
+  if (!out) return HOFEM_EINVAL;
+  if (n < 1 || n > 9 || K < 2 || K > 1024 || (K & (K - 1)) != 0) return HOFEM_EUNSUPPORTED;
+  hofem_plan1d p = new (std::nothrow) hofem_plan1d_s;
+  if (!p) return HOFEM_ENOMEM;
+  if (plan1d_build(n, K, &p->d) != 0) {
+    delete p;
+    return HOFEM_EUNSUPPORTED;
+  }
+  *out = p;
+  return HOFEM_OK;
+}
+
+void hofem_plan1d_destroy(hofem_plan1d plan) { delete plan; }
+
+int hofem_plan1d_dim(hofem_plan1d plan, int* m) {
+  if (!plan || !m) return HOFEM_EINVAL;
+  *m = plan->d.m;
+  return HOFEM_OK;
+}
+
+int hofem_plan1d_table(hofem_plan1d plan, int which, double* out_host, size_t len) {
+  if (!plan || !out_host) return HOFEM_EINVAL;
+  const Plan1DData& d = plan->d;
+  const int n = d.n, K = d.K;
+  const std::vector<double>* v = nullptr;
+  size_t count = 0;
+  switch (which) {
+    case 0: v = &d.lam; count = d.m; break;
+    case 1: v = &d.p; count = (size_t)(K - 1) * n * (n - 1); break;
+    case 2: v = &d.inorm; count = (size_t)(K - 1) * n; break;
+    case 3: v = &d.E; count = (size_t)(n - 1) * (n - 1); break;
+    case 4: v = &d.A; count = (size_t)(n + 1) * (n + 1); break;
+    case 5: v = &d.C; count = (size_t)(n + 1) * (n + 1); break;
+    default: return HOFEM_EINVAL;
+  }
+  if (len != count) return HOFEM_EINVAL;
+  if (count) std::memcpy(out_host, v->data(), count * sizeof(double));
+  return HOFEM_OK;
+}
+
+int hofem_solver_create(int N, const hofem_plan1d* plans, const double* X, double alpha,
+                        hofem_solver* out) {
+  if (!out || !plans || !X) return HOFEM_EINVAL;
+  if (N < 1 || N > 3) return HOFEM_EUNSUPPORTED;
+  if (!std::isfinite(alpha)) return HOFEM_EINVAL;
+  for (int i = 0; i < N; ++i) {
+    if (!plans[i]) return HOFEM_EINVAL;
+    if (!(X[i] > 0) || !std::isfinite(X[i])) return HOFEM_EINVAL;
+  }
+  // Every denominator alpha + sum_i 4 h_i^-2 lambda_i must be positive; the
+  // smallest is alpha + sum_i 4 h_i^-2 min lambda_i.
+  double dmin = alpha;
+  for (int i = 0; i < N; ++i) {
+    const Plan1DData& d = plans[i]->d;
+    const double h = X[i] / d.K;
+    dmin += 4.0 / (h * h) * *std::min_element(d.lam.begin(), d.lam.end());
+  }
+  if (!(dmin > 0)) return HOFEM_ENOTPOSDEF;
+
+  hofem_solver S = new (std::nothrow) hofem_solver_s;
+  if (!S) return HOFEM_ENOMEM;
+  S->N = N;
+  S->alpha = alpha;
+  S->per_rhs = 1;
+  hipError_t e = hipGetDevice(&S->device);
+  if (e != hipSuccess) {
+    delete S;
+    return hip_fail(e);
+  }
+  Packer pk;
+  struct Off {
+    size_t lam, p64, in64, E64, tw64, sn64, p32, in32, E32, tw32, sn32, A, C;
+  } off[3];
+  for (int i = 0; i < N; ++i) {
+    const Plan1DData& d = plans[i]->d;
+    DevAxis& ax = S->ax[i];
+    ax.n = d.n;
+    ax.K = d.K;
+    ax.m = d.m;
+    ax.X = X[i];
+    const double h = X[i] / d.K;
+    ax.scale = 4.0 / (h * h);
+    S->per_rhs *= (size_t)d.m;
+    off[i].lam = pk.add_f64(d.lam);
+    off[i].p64 = pk.add_f64(d.p);
+    off[i].in64 = pk.add_f64(d.inorm);
+    off[i].E64 = pk.add_f64(d.E);
+    off[i].tw64 = pk.add_f64(d.tw);
+    off[i].sn64 = pk.add_f64(d.sn);
+    off[i].p32 = pk.add_f32(d.p);
+    off[i].in32 = pk.add_f32(d.inorm);
+    off[i].E32 = pk.add_f32(d.E);
+    off[i].tw32 = pk.add_f32(d.tw);
+    off[i].sn32 = pk.add_f32(d.sn);
+    off[i].A = pk.add_f64(d.A);
+    off[i].C = pk.add_f64(d.C);
+  }
+  void* mem = nullptr;
+  e = hipMalloc(&mem, pk.bytes.size());
+  if (e != hipSuccess) {
+    delete S;
+    return e == hipErrorOutOfMemory ? HOFEM_ENOMEM : hip_fail(e);
+  }
+  e = hipMemcpy(mem, pk.bytes.data(), pk.bytes.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(mem);
+    delete S;
+    return hip_fail(e);
+  }
+  S->mem = mem;
+  unsigned char* b = static_cast<unsigned char*>(mem);
+  for (int i = 0; i < N; ++i) {
+    DevAxis& ax = S->ax[i];
+    const double* lam = reinterpret_cast<const double*>(b + off[i].lam);
+    ax.t64 = AxisTab{b + off[i].p64, b + off[i].in64, b + off[i].E64, b + off[i].tw64,
+                     b + off[i].sn64, lam, ax.n, ax.K, ax.m};
+    ax.t32 = AxisTab{b + off[i].p32, b + off[i].in32, b + off[i].E32, b + off[i].tw32,
+                     b + off[i].sn32, lam, ax.n, ax.K, ax.m};
+    ax.A = reinterpret_cast<const double*>(b + off[i].A);
+    ax.C = reinterpret_cast<const double*>(b + off[i].C);
+  }
+  *out = S;
+  return HOFEM_OK;
+}
+
+void hofem_solver_destroy(hofem_solver solver) {
+  if (!solver) return;
+  for (hipEvent_t e : solver->event_pool) (void)hipEventDestroy(e);
+  if (solver->mem) (void)hipFree(solver->mem);
+  delete solver;
+}
+
+int hofem_solver_set_timing(hofem_solver S, int enable) {
+  if (!S) return HOFEM_EINVAL;
+  S->timing = enable != 0;
+  return HOFEM_OK;
+}
+
+int hofem_solver_pass_times(hofem_solver S, hofem_pass_time* out_host, int max_entries,
+                            int* count) {
+  if (!S || !count || max_entries < 0 || (max_entries > 0 && !out_host)) return HOFEM_EINVAL;
+  std::vector<hofem_pass_time> agg;
+  for (const TimedLaunch& r : S->records) {
+    HIPCHK(hipEventSynchronize(r.stop));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, r.start, r.stop));
+    auto it = std::find_if(agg.begin(), agg.end(), [&](const hofem_pass_time& a) {
+      return a.kind == r.kind && a.axis == r.axis && a.fp64 == r.fp64;
+    });
+    if (it == agg.end()) {
+      agg.push_back(hofem_pass_time{r.kind, r.axis, r.fp64, 0, 0.0, r.bytes});
+      it = agg.end() - 1;
+    }
+    it->launches += 1;
+    it->ms += ms;
+  }
+  S->records.clear();
+  const int n = std::min<int>((int)agg.size(), max_entries);
+  for (int i = 0; i < n; ++i) out_host[i] = agg[i];
+  *count = n;
+  return HOFEM_OK;
+}
+
+int hofem_solver_size(hofem_solver solver, size_t* unknowns) {
+  if (!solver || !unknowns) return HOFEM_EINVAL;
+  *unknowns = solver->per_rhs;
+  return HOFEM_OK;
+}
+
+int hofem_solver_workspace_bytes(hofem_solver solver, int mode, int nrhs, size_t* bytes) {
+  if (!solver || !bytes || nrhs < 1) return HOFEM_EINVAL;
+  switch (mode) {
+    case HOFEM_MODE_FP64:
+    case HOFEM_MODE_FP32: *bytes = 0; return HOFEM_OK;
+    case HOFEM_MODE_FP32_IR: *bytes = ir_workspace(solver, nrhs); return HOFEM_OK;
+    default: return HOFEM_EINVAL;
+  }
+}
+
+int hofem_solve(hofem_solver S, int mode, const void* f_dev, void* u_dev, int nrhs, void* ws_dev,
+                size_t ws_bytes, int max_iter, double tol, void* stream, hofem_info* info) {
+  if (!S || !f_dev || !u_dev || nrhs < 1) return HOFEM_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const std::vector<PassSpec> list = solve_list(S->N);
+  if (mode == HOFEM_MODE_FP64 || mode == HOFEM_MODE_FP32) {
+    const bool f64 = mode == HOFEM_MODE_FP64;
+    const int dt = f64 ? 0 : 1;
+    int rc = run_list(S, list, f64, f_dev, u_dev, u_dev, dt, dt, dt, dt, nrhs, st);
+    if (rc != HOFEM_OK) return rc;
+    if (info) {
+      info->iterations = 0;
+      info->rel_update = 0.0;
+    }
+    return HOFEM_OK;
+  }
+  if (mode != HOFEM_MODE_FP32_IR) return HOFEM_EINVAL;
+  if (max_iter < 0 || !std::isfinite(tol)) return HOFEM_EINVAL;
+  if (f_dev == u_dev) return HOFEM_EINVAL;
+  const size_t need = ir_workspace(S, nrhs);
+  if (!ws_dev || ws_bytes < need) return HOFEM_EINVAL;
+  const long long count = (long long)S->per_rhs * nrhs;
+  float* r32 = static_cast<float*>(ws_dev);
+  size_t roff = (S->per_rhs * (size_t)nrhs * sizeof(float) + 255) & ~size_t(255);
+  double* partial = reinterpret_cast<double*>(static_cast<unsigned char*>(ws_dev) + roff);
+  double* sums = partial + 2 * kNormParts;
+  // First FP32 solve: f^h (FP64) -> u (FP64).
+  int rc = run_list(S, list, false, f_dev, r32, u_dev, 2, 1, 3, 5, nrhs, st);
+  if (rc != HOFEM_OK) return rc;
+  const int parts = (int)std::max<long long>(1, std::min<long long>(kNormParts, (count + 255) / 256));
+  int it = 0;
+  bool converged = tol <= 0;
+  double host[2] = {0.0, 0.0};
+  bool have = false;
+  for (; it < max_iter;) {
+    OpArgs o = make_op(S, static_cast<const double*>(u_dev), static_cast<const double*>(f_dev), r32,
+                       1, nrhs);
+    {
+      LaunchTimer tm(S, st, HOFEM_PASS_OPERATOR, -1, 1, (double)count * (8 + 8 + 4));
+      HIPCHK(launch_operator(o, st));
+      tm.done();
+    }
+    rc = run_list(S, list, false, r32, r32, r32, 1, 1, 1, 1, nrhs, st);
+    if (rc != HOFEM_OK) return rc;
+    {
+      LaunchTimer tm(S, st, HOFEM_PASS_UPDATE, -1, 1, (double)count * (4 + 8 + 8));
+      HIPCHK(launch_norms(r32, static_cast<double*>(u_dev), count, partial, parts, sums, st));
+      tm.done();
+    }
+    ++it;
+    have = false;
+    if (tol > 0) {
+      HIPCHK(hipMemcpyAsync(host, sums, sizeof(host), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      have = true;
+      const double rel = host[1] > 0 ? std::sqrt(host[0] / host[1]) : 0.0;
+      if (rel <= tol) {
+        converged = true;
+        break;
+      }
+    }
+  }
+  if (info) {
+    info->iterations = it;
+    info->rel_update = 0.0;
+    if (it > 0) {
+      if (!have) {
+        HIPCHK(hipMemcpyAsync(host, sums, sizeof(host), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+      }
+      info->rel_update = host[1] > 0 ? std::sqrt(host[0] / host[1]) : 0.0;
+    }
+  }
+  return converged ? HOFEM_OK : HOFEM_ENOCONV;
+}
+
+int hofem_forward(hofem_solver S, int mode, const void* in_dev, void* out_dev, int nrhs,
+                  void* stream) {
+  if (!S || !in_dev || !out_dev || nrhs < 1) return HOFEM_EINVAL;
+  if (mode != HOFEM_MODE_FP64 && mode != HOFEM_MODE_FP32) return HOFEM_EINVAL;
+  const bool f64 = mode == HOFEM_MODE_FP64;
+  const int dt = f64 ? 0 : 1;
+  std::vector<PassSpec> l;
+  for (int a = S->N - 1; a >= 0; --a) l.push_back({a, PASS_FWD});
+  return run_list(S, l, f64, in_dev, out_dev, out_dev, dt, dt, dt, dt, nrhs,
+                  static_cast<hipStream_t>(stream));
+}
+
+int hofem_inverse(hofem_solver S, int mode, const void* in_dev, void* out_dev, int nrhs,
+                  void* stream) {
+  if (!S || !in_dev || !out_dev || nrhs < 1) return HOFEM_EINVAL;
+  if (mode != HOFEM_MODE_FP64 && mode != HOFEM_MODE_FP32) return HOFEM_EINVAL;
+  const bool f64 = mode == HOFEM_MODE_FP64;
+  const int dt = f64 ? 0 : 1;
+  std::vector<PassSpec> l;
+  for (int a = 0; a < S->N; ++a) l.push_back({a, PASS_INV});
+  return run_list(S, l, f64, in_dev, out_dev, out_dev, dt, dt, dt, dt, nrhs,
+                  static_cast<hipStream_t>(stream));
+}
+
+int hofem_apply_operator(hofem_solver S, const double* u_dev, double* out_dev, int nrhs,
+                         void* stream) {
+  if (!S || !u_dev || !out_dev || nrhs < 1 || u_dev == out_dev) return HOFEM_EINVAL;
+  OpArgs o = make_op(S, u_dev, nullptr, out_dev, 0, nrhs);
+  HIPCHK(launch_operator(o, static_cast<hipStream_t>(stream)));
+  return HOFEM_OK;
+}
+
+}  // extern "C"

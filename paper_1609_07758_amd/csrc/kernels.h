@@ -1,0 +1,77 @@
+// Internal interface between the solver (capi.hip) and the device kernels
+// (kernels.hip).  Plain structs of device pointers and sizes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace hofem {
+
+// Device tables of one axis in one precision (T = float or double).
+struct AxisTab {
+  const void* p;       // p_k^(l) vectors, ((k-1) n + l-1) (n-1) + i
+  const void* inorm;   // 1 / ||s_k^(l)||^2, (k-1) n + l-1
+  const void* E;       // e^(l) columns, i (n-1) + l-1
+  const void* tw;      // cos, sin (2 pi t / K) interleaved, t < K
+  const void* sn;      // sin(pi t / K), t < K
+  const double* lam;   // scaled eigenvalues in coefficient order (FP64)
+  int n, K, m;
+};
+
+enum PassKind { PASS_FWD = 0, PASS_INV = 1, PASS_FUSED = 2 };
+
+// Arguments of one line pass along one axis of a C-order grid.
+struct PassArgs {
+  const void* in;
+  void* out;
+  AxisTab tab;
+  long long inner;     // stride of the axis (product of the later extents)
+  long long nlines;    // number of lines (total elements / m)
+  int cb;              // lines per workgroup
+  // Denominator of the fused pass: alpha + scale * lam[q] + sum over the
+  // other axes of oscale[i] * olam[i][(t / odiv[i]) % omod[i]], t = line % inner.
+  double alpha;
+  double scale;
+  int nother;
+  const double* olam[2];
+  double oscale[2];
+  long long odiv[2];
+  long long omod[2];
+};
+
+// Launch one pass.  dt: 0 = FP64 compute (double in/out),
+// 1 = FP32 compute with float in/out, 2 = FP32 compute, double in, float out,
+// 3 = FP32 compute, float in, double out (stored), 4 = FP32 compute, float
+// in, double out accumulated (out += result), 5 = FP32 compute, double in,
+// double out (stored).
+hipError_t launch_pass(int kind, int dt, const PassArgs& a, hipStream_t s);
+
+// Workgroup size / lines per workgroup / LDS bytes chosen for (n, K, dtype).
+void pass_shape(int n, int K, int is_f64, long long nlines, long long inner, int* cb,
+                size_t* lds_bytes);
+
+// FP64 matrix-free operator r = f - L u (f may be NULL: r = L u), N = 1..3.
+struct OpArgs {
+  const double* u;
+  const double* f;
+  void* out;           // double (out_f32 == 0) or float (out_f32 == 1)
+  int out_f32;
+  int N;
+  int n[3], K[3], m[3];
+  double scale[3];     // 4 h_i^-2
+  double alpha;
+  const double* A[3];  // local stiffness (n_i+1)^2, device
+  const double* C[3];  // local mass (n_i+1)^2, device
+  int nrhs;
+};
+hipError_t launch_operator(const OpArgs& a, hipStream_t s);
+
+// u += delta over `count` elements with per-workgroup partial sums of
+// delta^2 and u^2 (nparts workgroups), reduced to out[0..1] by a second
+// launch (fixed order: deterministic).
+hipError_t launch_norms(const float* delta, double* u, long long count, double* partial,
+                        int nparts, double* out, hipStream_t s);
+
+// u += (double) delta, elementwise.
+hipError_t launch_axpy(const float* delta, double* u, long long count, hipStream_t s);
+
+}  // namespace hofem

@@ -1,0 +1,359 @@
+// Host precompute of the 1D eigen data of the nth-order FEM pencil, in
+// binary128 (__float128, libquadmath), rounded once to FP64 and FP32.
+//
+// Route (Section 2, paragraphs 1-3 of the paper):
+//   * local stiffness/mass on [-1, 1] (Lagrange basis on the equispaced nodes
+//     -1 + 2k/n) by (n+1)-point Gauss-Legendre quadrature, which integrates
+//     the degree-2n integrands exactly;
+//   * the interior-node eigenproblem A~ e = lam C~ e of eq. (eig_elem) by a
+//     Cholesky reduction and cyclic Jacobi, normalised C~ e . e = 1;
+//   * for every wave number k = 1..K-1 the n roots of the secular equation
+//     eq. (theta) at theta_k = cos(pi k / K), written with the expansion
+//     coefficients a^(l), c^(l) of Lemma 2.  Its poles are the interior
+//     eigenvalues lam_0^(l) and its n roots interlace with them (the roots are
+//     the eigenvalues of a Hermitian pencil whose interior block is
+//     (A~, C~)), one root in each of (0, lam_0^(1)), ..., (lam_0^(n-1), inf);
+//   * p_k^(l) by the expansion formula of Lemma 2, and the norms
+//     ||s_k^(l)||_C^2 = K (b0 + bn theta_k) of the transform theorem.
+//
+// Nothing here runs on the GPU; the tables are uploaded by the solver.
+
+#include <quadmath.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "plan1d.h"
+
+namespace hofem {
+namespace {
+
+typedef __float128 q128;
+
+q128 qabs(q128 x) { return x < 0 ? -x : x; }
+
+// Legendre polynomial P_npts(z) and its derivative by the three-term recurrence.
+void legendre(int npts, q128 z, q128& p, q128& dp) {
+  q128 p0 = 1, p1 = z;
+  for (int k = 2; k <= npts; ++k) {
+    q128 p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+    p0 = p1;
+    p1 = p2;
+  }
+  p = p1;
+  dp = npts * (z * p1 - p0) / (z * z - 1);
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1] by Newton on P_npts (npts >= 2).
+void gauss_legendre(int npts, std::vector<q128>& x, std::vector<q128>& w) {
+  x.assign(npts, 0);
+  w.assign(npts, 0);
+  for (int i = 0; i < npts; ++i) {
+    q128 z = cosq(M_PIq * (i + 0.75Q) / (npts + 0.5Q)), p, dp;
+    for (int it = 0; it < 100; ++it) {
+      legendre(npts, z, p, dp);
+      q128 dz = p / dp;
+      z -= dz;
+      if (qabs(dz) < 1e-34Q) break;
+    }
+    legendre(npts, z, p, dp);
+    x[i] = z;
+    w[i] = 2 / ((1 - z * z) * dp * dp);
+  }
+}
+
+// Local matrices of the order-n Lagrange element on [-1, 1].
+void local_matrices(int n, std::vector<q128>& A, std::vector<q128>& C) {
+  const int nb = n + 1;
+  std::vector<q128> xi(nb);
+  for (int k = 0; k <= n; ++k) xi[k] = -1 + (q128)(2 * k) / n;
+  std::vector<q128> gx, gw;
+  gauss_legendre(n + 1, gx, gw);
+  A.assign(nb * nb, 0);
+  C.assign(nb * nb, 0);
+  std::vector<q128> e(nb), de(nb);
+  for (size_t g = 0; g < gx.size(); ++g) {
+    const q128 x = gx[g];
+    for (int l = 0; l <= n; ++l) {
+      q128 v = 1;
+      for (int m = 0; m <= n; ++m)
+        if (m != l) v *= (x - xi[m]) / (xi[l] - xi[m]);
+      e[l] = v;
+      // derivative by the product rule, without dividing by (x - xi_m)
+      q128 d = 0;
+      for (int m = 0; m <= n; ++m) {
+        if (m == l) continue;
+        q128 t = 1 / (xi[l] - xi[m]);
+        for (int r = 0; r <= n; ++r)
+          if (r != l && r != m) t *= (x - xi[r]) / (xi[l] - xi[r]);
+        d += t;
+      }
+      de[l] = d;
+    }
+    for (int r = 0; r <= n; ++r)
+      for (int s = 0; s <= n; ++s) {
+        A[r * nb + s] += gw[g] * de[r] * de[s];
+        C[r * nb + s] += gw[g] * e[r] * e[s];
+      }
+  }
+  // Symmetrise exactly (the quadrature is symmetric up to rounding).
+  for (int r = 0; r <= n; ++r)
+    for (int s = r + 1; s <= n; ++s) {
+      q128 a = (A[r * nb + s] + A[s * nb + r]) / 2, c = (C[r * nb + s] + C[s * nb + r]) / 2;
+      A[r * nb + s] = A[s * nb + r] = a;
+      C[r * nb + s] = C[s * nb + r] = c;
+    }
+}
+
+// Cyclic Jacobi eigen-decomposition of a symmetric d x d matrix (row major).
+// On return B holds the eigenvalues on its diagonal and Q the eigenvectors
+// (columns).
+void jacobi(int d, std::vector<q128>& B, std::vector<q128>& Q) {
+  Q.assign(d * d, 0);
+  for (int i = 0; i < d; ++i) Q[i * d + i] = 1;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    q128 off = 0, tot = 0;
+    for (int i = 0; i < d; ++i)
+      for (int j = 0; j < d; ++j) {
+        q128 v = B[i * d + j] * B[i * d + j];
+        tot += v;
+        if (i != j) off += v;
+      }
+    if (off <= 1e-70Q * tot) break;
+    for (int p = 0; p < d; ++p)
+      for (int q = p + 1; q < d; ++q) {
+        q128 apq = B[p * d + q];
+        if (apq == 0) continue;
+        q128 app = B[p * d + p], aqq = B[q * d + q];
+        q128 tau = (aqq - app) / (2 * apq);
+        q128 t = (tau >= 0 ? 1 : -1) / (qabs(tau) + sqrtq(1 + tau * tau));
+        q128 c = 1 / sqrtq(1 + t * t), s = t * c;
+        for (int k = 0; k < d; ++k) {  // columns p, q
+          q128 bkp = B[k * d + p], bkq = B[k * d + q];
+          B[k * d + p] = c * bkp - s * bkq;
+          B[k * d + q] = s * bkp + c * bkq;
+        }
+        for (int k = 0; k < d; ++k) {  // rows p, q
+          q128 bpk = B[p * d + k], bqk = B[q * d + k];
+          B[p * d + k] = c * bpk - s * bqk;
+          B[q * d + k] = s * bpk + c * bqk;
+        }
+        for (int k = 0; k < d; ++k) {
+          q128 qkp = Q[k * d + p], qkq = Q[k * d + q];
+          Q[k * d + p] = c * qkp - s * qkq;
+          Q[k * d + q] = s * qkp + c * qkq;
+        }
+      }
+  }
+}
+
+// Interior pencil (At, Ct) of order d: eigenvalues ascending, C~-normalised
+// eigenvectors as columns of E (row major d x d).
+void interior_eigen(int d, const std::vector<q128>& At, const std::vector<q128>& Ct,
+                    std::vector<q128>& lam0, std::vector<q128>& E) {
+  lam0.assign(d, 0);
+  E.assign(d * d, 0);
+  if (d == 0) return;
+  // Cholesky Ct = L L^T
+  std::vector<q128> L(d * d, 0);
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j <= i; ++j) {
+      q128 s = Ct[i * d + j];
+      for (int k = 0; k < j; ++k) s -= L[i * d + k] * L[j * d + k];
+      L[i * d + j] = (i == j) ? sqrtq(s) : s / L[j * d + j];
+    }
+  // Li = L^-1 (lower triangular)
+  std::vector<q128> Li(d * d, 0);
+  for (int col = 0; col < d; ++col) {
+    for (int i = 0; i < d; ++i) {
+      q128 s = (i == col) ? 1 : 0;
+      for (int k = 0; k < i; ++k) s -= L[i * d + k] * Li[k * d + col];
+      Li[i * d + col] = s / L[i * d + i];
+    }
+  }
+  // B = Li At Li^T
+  std::vector<q128> T(d * d, 0), B(d * d, 0);
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) {
+      q128 s = 0;
+      for (int k = 0; k < d; ++k) s += Li[i * d + k] * At[k * d + j];
+      T[i * d + j] = s;
+    }
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) {
+      q128 s = 0;
+      for (int k = 0; k < d; ++k) s += T[i * d + k] * Li[j * d + k];
+      B[i * d + j] = s;
+    }
+  for (int i = 0; i < d; ++i)
+    for (int j = i + 1; j < d; ++j) B[i * d + j] = B[j * d + i] = (B[i * d + j] + B[j * d + i]) / 2;
+  std::vector<q128> Q;
+  jacobi(d, B, Q);
+  std::vector<int> order(d);
+  for (int i = 0; i < d; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return B[a * d + a] < B[b * d + b]; });
+  for (int l = 0; l < d; ++l) {
+    int o = order[l];
+    lam0[l] = B[o * d + o];
+    // e = Li^T y
+    std::vector<q128> e(d, 0);
+    for (int i = 0; i < d; ++i) {
+      q128 s = 0;
+      for (int k = 0; k < d; ++k) s += Li[k * d + i] * Q[k * d + o];
+      e[i] = s;
+    }
+    // Sign: the lowest-index entry with |e_i| >= max|e| / 2 is positive.
+    q128 mx = 0;
+    for (int i = 0; i < d; ++i) mx = std::max(mx, qabs(e[i]));
+    int lead = 0;
+    while (qabs(e[lead]) < mx / 2) ++lead;
+    q128 sg = e[lead] < 0 ? -1 : 1;
+    for (int i = 0; i < d; ++i) E[i * d + l] = sg * e[i];
+  }
+}
+
+struct Secular {
+  int d;                       // n - 1
+  q128 a0, c0, an, cn;
+  std::vector<q128> al, cl, alc, clc, lam0;  // a^(l), c^(l), a-check^(l), c-check^(l)
+  // F(lam) = (a0 - lam c0) + sum (a^(l) - lam c^(l))^2 / (lam - lam0_l)
+  //        + theta [(an - lam cn) + sum (ac^(l) - lam cc^(l))(a^(l) - lam c^(l)) / (lam - lam0_l)]
+  void eval(q128 lam, q128 th, q128& F, q128& dF) const {
+    F = (a0 - lam * c0) + th * (an - lam * cn);
+    dF = -c0 - th * cn;
+    for (int l = 0; l < d; ++l) {
+      q128 u = al[l] - lam * cl[l], v = alc[l] - lam * clc[l];
+      q128 r = 1 / (lam - lam0[l]);
+      q128 num = u * u + th * v * u;
+      F += num * r;
+      // d/dlam [num r] = num' r - num r^2
+      q128 dnum = -2 * cl[l] * u + th * (-clc[l] * u - cl[l] * v);
+      dF += dnum * r - num * r * r;
+    }
+  }
+};
+
+// One root of F in the open interval (lo, hi), with F > 0 just right of lo
+// and F < 0 just left of hi: safeguarded Newton on bisection brackets.
+q128 root_in(const Secular& S, q128 th, q128 lo, q128 hi) {
+  q128 x = (lo + hi) / 2;
+  for (int it = 0; it < 400; ++it) {
+    q128 F, dF;
+    S.eval(x, th, F, dF);
+    if (F > 0) lo = x; else hi = x;
+    if (F == 0) return x;
+    q128 xn = x - F / dF;
+    if (!(xn > lo && xn < hi) || dF == 0) xn = (lo + hi) / 2;
+    if (qabs(xn - x) <= 1e-33Q * qabs(xn) || hi - lo <= 1e-33Q * qabs(x)) return xn;
+    x = xn;
+  }
+  return x;
+}
+
+}  // namespace
+
+int plan1d_build(int n, int K, Plan1DData* out) {
+  if (n < 1 || n > 9 || K < 2 || (K & (K - 1)) != 0 || K > 65536) return -1;
+  const int nb = n + 1, d = n - 1, m = n * K - 1;
+  std::vector<q128> A, C;
+  local_matrices(n, A, C);
+  auto Aat = [&](int r, int s) { return A[r * nb + s]; };
+  auto Cat = [&](int r, int s) { return C[r * nb + s]; };
+  std::vector<q128> At(d * d), Ct(d * d);
+  for (int r = 0; r < d; ++r)
+    for (int s = 0; s < d; ++s) {
+      At[r * d + s] = Aat(r + 1, s + 1);
+      Ct[r * d + s] = Cat(r + 1, s + 1);
+    }
+  std::vector<q128> lam0, E;
+  interior_eigen(d, At, Ct, lam0, E);
+
+  Secular S;
+  S.d = d;
+  S.a0 = Aat(0, 0); S.c0 = Cat(0, 0); S.an = Aat(0, n); S.cn = Cat(0, n);
+  S.al.assign(d, 0); S.cl.assign(d, 0); S.alc.assign(d, 0); S.clc.assign(d, 0);
+  S.lam0 = lam0;
+  for (int l = 0; l < d; ++l)
+    for (int i = 0; i < d; ++i) {
+      q128 e = E[i * d + l];
+      S.al[l] += Aat(i + 1, 0) * e;
+      S.cl[l] += Cat(i + 1, 0) * e;
+      S.alc[l] += Aat(i + 1, n) * e;
+      S.clc[l] += Cat(i + 1, n) * e;
+    }
+
+  out->n = n;
+  out->K = K;
+  out->m = m;
+  out->A.assign(nb * nb, 0);
+  out->C.assign(nb * nb, 0);
+  for (int i = 0; i < nb * nb; ++i) {
+    out->A[i] = (double)A[i];
+    out->C[i] = (double)C[i];
+  }
+  out->lam.assign(m, 0);
+  out->p.assign((size_t)(K - 1) * n * std::max(d, 1), 0);
+  out->inorm.assign((size_t)(K - 1) * n, 0);
+  out->E.assign(std::max(d * d, 1), 0);
+  out->lam0.assign(std::max(d, 1), 0);
+  for (int i = 0; i < d * d; ++i) out->E[i] = (double)E[i];
+  for (int l = 0; l < d; ++l) {
+    out->lam0[l] = (double)lam0[l];
+    out->lam[l] = (double)lam0[l];
+  }
+
+  std::vector<q128> lroots(n), p(d);
+  for (int k = 1; k < K; ++k) {
+    const q128 th = cosq(M_PIq * k / K);
+    // brackets: (0, lam0_1), (lam0_1, lam0_2), ..., (lam0_{n-1}, hi)
+    q128 top = d ? lam0[d - 1] : 0;
+    q128 hi = 2 * top + 16;
+    for (int it = 0; it < 200; ++it) {
+      q128 F, dF;
+      S.eval(hi, th, F, dF);
+      if (F < 0) break;
+      hi *= 2;
+    }
+    for (int l = 0; l < n; ++l) {
+      q128 lo = (l == 0) ? 0 : lam0[l - 1];
+      q128 up = (l == d) ? hi : lam0[l];
+      lroots[l] = root_in(S, th, lo, up);
+    }
+    for (int l = 0; l < n; ++l) {
+      const q128 lam = lroots[l];
+      // Lemma 2: p = sum_m (a^(m) - lam c^(m)) / (lam - lam0_m) e^(m)
+      for (int i = 0; i < d; ++i) p[i] = 0;
+      for (int mm = 0; mm < d; ++mm) {
+        q128 coef = (S.al[mm] - lam * S.cl[mm]) / (lam - lam0[mm]);
+        for (int i = 0; i < d; ++i) p[i] += coef * E[i * d + mm];
+      }
+      // ||s||^2 = K (b0 + bn theta), b0 = c0 + (C~p + 2c).p, bn = cn + (C~p + 2c).Pp
+      q128 b0 = S.c0, bn = S.cn;
+      for (int i = 0; i < d; ++i) {
+        q128 w = 2 * Cat(i + 1, 0);
+        for (int j = 0; j < d; ++j) w += Ct[i * d + j] * p[j];
+        b0 += w * p[i];
+        bn += w * p[d - 1 - i];
+      }
+      q128 norm2 = K * (b0 + bn * th);
+      size_t base = ((size_t)(k - 1) * n + l);
+      out->inorm[base] = (double)(1 / norm2);
+      for (int i = 0; i < d; ++i) out->p[base * d + i] = (double)p[i];
+      out->lam[n * k - 1 + l] = (double)lam;
+    }
+  }
+  // FFT support: twiddles exp(2 pi i t / K) and sin(pi t / K), t = 0..K-1.
+  out->tw.assign(2 * K, 0);
+  out->sn.assign(K, 0);
+  for (int t = 0; t < K; ++t) {
+    out->tw[2 * t] = (double)cosq(2 * M_PIq * t / K);
+    out->tw[2 * t + 1] = (double)sinq(2 * M_PIq * t / K);
+    out->sn[t] = (double)sinq(M_PIq * t / K);
+  }
+  return 0;
+}
+
+}  // namespace hofem

@@ -1,0 +1,27 @@
+// Internal interface of the binary128 host precompute (plan1d.cpp).
+#pragma once
+
+#include <vector>
+
+namespace hofem {
+
+// FP64 tables of the 1D eigen data for one (n, K), each value rounded once
+// from binary128.  Coefficient index q of a line (length m = nK - 1):
+//   k = 0, l = 1..n-1      ->  q = l - 1
+//   k = 1..K-1, l = 1..n   ->  q = n k - 1 + (l - 1)
+struct Plan1DData {
+  int n = 0, K = 0, m = 0;
+  std::vector<double> A, C;      // local stiffness / mass on [-1,1], (n+1)^2 row major
+  std::vector<double> lam;       // scaled eigenvalues in coefficient order (m)
+  std::vector<double> p;         // p_k^(l): [(k-1) n + (l-1)] * (n-1) + i, i = 0..n-2
+  std::vector<double> inorm;     // 1 / ||s_k^(l)||_C^2: [(k-1) n + (l-1)]
+  std::vector<double> E;         // e^(l) as columns: E[i (n-1) + (l-1)]
+  std::vector<double> lam0;      // interior eigenvalues (n-1)
+  std::vector<double> tw;        // cos, sin of 2 pi t / K, t = 0..K-1 (interleaved)
+  std::vector<double> sn;        // sin(pi t / K), t = 0..K-1
+};
+
+// Returns 0 on success, -1 for unsupported (n, K).
+int plan1d_build(int n, int K, Plan1DData* out);
+
+}  // namespace hofem

@@ -1,0 +1,89 @@
+"""Host-side tests of the C ABI (no GPU needed).
+
+The library loads, exports every entry point that include/hofem.h declares,
+rejects invalid arguments with the documented codes, and its binary128 host
+precompute reproduces the oracle's high-precision eigen data.
+"""
+import ctypes
+import os
+import re
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import assembly, element, spectral
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hofem.h")
+
+H = pytest.importorskip("paper_1609_07758_amd")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hofem_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(H.LIB_PATH)
+    names = declared_symbols()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(H.SIGNATURES)
+
+
+@pytest.mark.parametrize("n,K", [(0, 16), (10, 16), (2, 3), (2, 1), (2, 2048), (-1, 8)])
+def test_plan_rejects_unsupported(n, K):
+    h = ctypes.c_void_p()
+    assert H._lib.hofem_plan1d_create(n, K, ctypes.byref(h)) == H.HOFEM_EUNSUPPORTED
+
+
+def test_null_and_size_errors():
+    assert H._lib.hofem_plan1d_create(2, 16, None) == H.HOFEM_EINVAL
+    p = H.Plan1D(3, 8)
+    out = np.zeros(5)
+    ptr = out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert H._lib.hofem_plan1d_table(p.handle, 0, ptr, 5) == H.HOFEM_EINVAL     # wrong length
+    assert H._lib.hofem_plan1d_table(p.handle, 9, ptr, 5) == H.HOFEM_EINVAL     # bad table id
+    assert H._lib.hofem_solver_create(0, None, None, 0.0, None) == H.HOFEM_EINVAL
+    arr = (ctypes.c_void_p * 1)(p.handle.value)
+    xs = (ctypes.c_double * 1)(1.0)
+    h = ctypes.c_void_p()
+    assert H._lib.hofem_solver_create(4, arr, xs, 0.0, ctypes.byref(h)) == H.HOFEM_EUNSUPPORTED
+    bad = (ctypes.c_double * 1)(-1.0)
+    assert H._lib.hofem_solver_create(1, arr, bad, 0.0, ctypes.byref(h)) == H.HOFEM_EINVAL
+    # alpha below -pi^2 / X^2 (scaled): the smallest denominator is negative
+    assert H._lib.hofem_solver_create(1, arr, xs, -1e4, ctypes.byref(h)) == H.HOFEM_ENOTPOSDEF
+    assert H._lib.hofem_solve(None, 0, None, None, 1, None, 0, 0, 0.0, None, None) == H.HOFEM_EINVAL
+    assert H.hofem_solver_size is not None
+    assert H._lib.hofem_status_string(H.HOFEM_ENOCONV) == b"refinement did not converge"
+
+
+@pytest.mark.parametrize("n,K", [(1, 16), (2, 16), (3, 8), (4, 32), (6, 16), (9, 8), (9, 64)])
+def test_plan_tables_match_oracle(n, K):
+    p = H.Plan1D(n, K)
+    o = spectral.eigen_structured(n, K)
+    lam = np.concatenate([o["lam0"], o["lam"].ravel()])
+    # both sides round high-precision values once: equal up to one rounding
+    assert np.allclose(p.table("lam"), lam, rtol=2.3e-16, atol=0)
+    if n > 1:
+        assert np.allclose(p.table("p").reshape(K - 1, n, n - 1), o["p"], rtol=0, atol=4e-16 * np.abs(o["p"]).max())
+        assert np.allclose(p.table("E").reshape(n - 1, n - 1), o["E"], rtol=0, atol=4e-16 * np.abs(o["E"]).max())
+    # norms against the direct C-norm of the oracle's eigenvectors
+    S, _ = spectral.eigenvectors_structured(n, K, o)
+    _, Cs = assembly.assemble_1d_sparse(n, K)
+    direct = np.einsum("ij,ij->j", S, Cs @ S)[n - 1:]
+    assert np.allclose(p.table("inorm"), 1.0 / direct, rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("n", range(1, 10))
+def test_local_matrices_match_exact(n):
+    p = H.Plan1D(n, 4)
+    A, C = element.local_matrices(n)
+    Af = np.array([[float(x) for x in r] for r in A]).ravel()
+    Cf = np.array([[float(x) for x in r] for r in C]).ravel()
+    assert np.allclose(p.table("A"), Af, rtol=4.5e-16, atol=1e-300)
+    assert np.allclose(p.table("C"), Cf, rtol=4.5e-16, atol=1e-300)

@@ -1,0 +1,32 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle
+checks.  Random numbers and problem definitions only: nothing in this module
+computes any part of the solve.
+
+Configurations (per axis: order n, elements K, box length X):
+  small_2d    N=2, n=2, K=16, X=(1,1), alpha=0          (31^2 = 961 unknowns)
+  large_2d    N=2, n=9, K=1024, X=(1,1), alpha=0        (9215^2 = 84,916,225 unknowns)
+  cube_3d     N=3, n=4, K=128, X=(1,1,1), alpha=0       (511^3 = 133,432,831 unknowns)
+Right-hand sides of the random kind are i.i.d. uniform[-1, 1) values of f^h
+drawn in C order with numpy's default generator (PCG64) from the seed.
+"""
+import numpy as np
+
+CONFIGS = {
+    "small_2d": dict(orders=(2, 2), Ks=(16, 16), X=(1.0, 1.0), alpha=0.0),
+    "large_2d": dict(orders=(9, 9), Ks=(1024, 1024), X=(1.0, 1.0), alpha=0.0),
+    "cube_3d": dict(orders=(4, 4, 4), Ks=(128, 128, 128), X=(1.0, 1.0, 1.0), alpha=0.0),
+}
+
+
+def shape(orders, Ks):
+    return tuple(n * K - 1 for n, K in zip(orders, Ks))
+
+
+def uniform_rhs(shp, seed=0, dtype=np.float64):
+    """f^h with i.i.d. uniform[-1, 1) entries."""
+    return np.random.default_rng(seed).uniform(-1.0, 1.0, shp).astype(dtype)
+
+
+def normal_noise(shp, sigma, seed=0):
+    """i.i.d. N(0, sigma^2) entries (sigma is the standard deviation)."""
+    return np.random.default_rng(seed).normal(0.0, sigma, shp)
