@@ -6,14 +6,17 @@
 
 namespace hofem {
 
-// Device tables of one axis in one precision (T = float or double).
+// Device tables of one axis in one precision (T = float or double).  The
+// per-wave-number tables are stored with k fastest so that lanes handling
+// consecutive k read consecutive addresses.
 struct AxisTab {
-  const void* p;       // p_k^(l) vectors, ((k-1) n + l-1) (n-1) + i
-  const void* inorm;   // 1 / ||s_k^(l)||^2, (k-1) n + l-1
+  const void* p;       // component i of p_k^(l) at ((l-1) (n-1) + i) (K-1) + k-1
+  const void* inorm;   // 1 / ||s_k^(l)||^2 at (l-1) (K-1) + k-1
   const void* E;       // e^(l) columns, i (n-1) + l-1
   const void* tw;      // cos, sin (2 pi t / K) interleaved, t < K
   const void* sn;      // sin(pi t / K), t < K
   const double* lam;   // scaled eigenvalues in coefficient order (FP64)
+  const double* lamk;  // lambda_k^(l) at (l-1) (K-1) + k-1 (FP64)
   int n, K, m;
 };
 
