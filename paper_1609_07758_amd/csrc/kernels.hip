@@ -46,7 +46,7 @@ namespace hofem {
 namespace {
 
 constexpr int kMaxCB = 64;      // lines per workgroup (upper bound)
-constexpr int kMaxThreads = 1024;
+constexpr int kMaxThreads = 512;  // 8 waves: up to 256 VGPRs per lane
 constexpr int kMinThreads = 512;  // lanes for the load, block and scatter phases
 constexpr int kUnroll = 8;        // global loads in flight per lane
 constexpr unsigned kXcds = 8;     // accelerator complex dies of an MI355X
@@ -238,7 +238,10 @@ __device__ __forceinline__ void task_post(cx<T>* buf, int j) {
   using S = FftShape<LOG2K>;
   constexpr int K = S::K, G = S::G;
   constexpr int C = (K / 2) / G;
-  cx<T> ev[C], rv[C];
+  // The running sums are carried in FP64 whatever T is: in FP32 their
+  // rounding error would grow with K and vary smoothly along k.
+  cx<T> ev[C];
+  cx<double> rv[C];
 #pragma unroll
   for (int i = 0; i < C; ++i) {
     const int k = j * C + i;
@@ -247,33 +250,34 @@ __device__ __forceinline__ void task_post(cx<T>* buf, int j) {
     // Y^a_k = (W_k + conj W_{K-k}) / 2, Y^b_k = (W_k - conj W_{K-k}) / (2i):
     // even outputs X_{2k} = -Im Y_k, running-sum terms R_k = Re Y_k.
     ev[i] = {T(0.5) * (b.y - a.y), T(0.5) * (a.x - b.x)};
-    rv[i] = {T(0.5) * (a.x + b.x), T(0.5) * (a.y + b.y)};
+    rv[i] = {0.5 * ((double)a.x + (double)b.x), 0.5 * ((double)a.y + (double)b.y)};
     if (k == 0) {
       ev[i] = {T(0), T(0)};
-      rv[i] = {T(0.5) * a.x, T(0.5) * a.y};   // X_1 = Re Y_0 / 2
+      rv[i] = {0.5 * (double)a.x, 0.5 * (double)a.y};   // X_1 = Re Y_0 / 2
     }
   }
 #pragma unroll
   for (int i = 1; i < C; ++i) rv[i] = cadd(rv[i], rv[i - 1]);
   // segmented inclusive scan of the lane totals over the G lanes of the task
-  cx<T> incl = rv[C - 1];
-  const cx<T> tot = incl;
+  cx<double> incl = rv[C - 1];
+  const cx<double> tot = incl;
 #pragma unroll
   for (int off = 1; off < G; off <<= 1) {
-    const T ux = __shfl_up(incl.x, off, G);
-    const T uy = __shfl_up(incl.y, off, G);
+    const double ux = __shfl_up(incl.x, off, G);
+    const double uy = __shfl_up(incl.y, off, G);
     if (j >= off) {
       incl.x += ux;
       incl.y += uy;
     }
   }
-  const cx<T> excl = csub(incl, tot);
+  const cx<double> excl = csub(incl, tot);
   wave_sync();
 #pragma unroll
   for (int i = 0; i < C; ++i) {
     const int k = j * C + i;
     buf[sw(2 * k)] = ev[i];
-    buf[sw(2 * k + 1)] = cadd(rv[i], excl);
+    const cx<double> o = cadd(rv[i], excl);
+    buf[sw(2 * k + 1)] = cx<T>{(T)o.x, (T)o.y};
   }
   wave_sync();
 }
@@ -339,14 +343,15 @@ __device__ __forceinline__ void fwd_block(const T* __restrict__ P, const T* __re
   const int nm1 = n - 1, cmax = n > 1 ? n - 2 : 0;
   const size_t ks = (size_t)(K - 1);
 #pragma unroll
-  for (int l = 0; l < 9; ++l) {
-    const int lc = min(l, n - 1);
-    const T* pl = P + (size_t)lc * nm1 * ks + (k - 1);
-    T a = x[0];
+  for (int l = 0; l < 9; ++l) acc[l] = x[0];
 #pragma unroll
-    for (int s = 1; s < 9; ++s) a += pl[(size_t)min(s - 1, cmax) * ks] * x[s];
-    acc[l] = a * IN[(size_t)lc * ks + (k - 1)];
+  for (int s = 1; s < 9; ++s) {
+    const T* ps = P + (size_t)min(s - 1, cmax) * ks + (k - 1);
+#pragma unroll
+    for (int l = 0; l < 9; ++l) acc[l] += ps[(size_t)min(l, n - 1) * nm1 * ks] * x[s];
   }
+#pragma unroll
+  for (int l = 0; l < 9; ++l) acc[l] *= IN[(size_t)min(l, n - 1) * ks + (k - 1)];
 }
 
 // Inverse-transform combination at k >= 1 from coefficients w[l] (zero for
@@ -356,15 +361,16 @@ __device__ __forceinline__ void inv_block(const T* __restrict__ P, int n, int K,
                                           const T (&w)[9], T (&y)[9]) {
   const int nm1 = n - 1, cmax = n > 1 ? n - 2 : 0;
   const size_t ks = (size_t)(K - 1);
+  y[0] = T(0);
 #pragma unroll
-  for (int s = 0; s < 9; ++s) y[s] = T(0);
+  for (int l = 0; l < 9; ++l) y[0] += w[l];
 #pragma unroll
-  for (int l = 0; l < 9; ++l) {
-    const int lc = min(l, n - 1);
-    const T* pl = P + (size_t)lc * nm1 * ks + (k - 1);
-    y[0] += w[l];
+  for (int s = 1; s < 9; ++s) {
+    const T* ps = P + (size_t)min(s - 1, cmax) * ks + (k - 1);
+    T a = T(0);
 #pragma unroll
-    for (int s = 1; s < 9; ++s) y[s] += w[l] * pl[(size_t)min(s - 1, cmax) * ks];
+    for (int l = 0; l < 9; ++l) a += w[l] * ps[(size_t)min(l, n - 1) * nm1 * ks];
+    y[s] = a;
   }
 }
 
@@ -379,7 +385,8 @@ __global__ __launch_bounds__(kMaxThreads) void line_pass(PassArgs a) {
   const int NP = (n + 1) >> 1;
   const int LS = NP * K;                        // complex slots per line
   const long long inner = a.inner;
-  const int cb = a.cb;
+  const int cb = a.cb;            // a power of two
+  const int lcb = __builtin_ctz(cb);
   // Workgroups are dealt round-robin to the 8 XCDs (each with its own L2):
   // renumber them so that every XCD walks one contiguous range of lines, and
   // the lines that share cache lines (neighbouring columns of a strided
@@ -427,29 +434,44 @@ __global__ __launch_bounds__(kMaxThreads) void line_pass(PassArgs a) {
   __syncthreads();
 
   // ---- load the cv lines (physical or coefficient order) ------------------
-  // Flat index i = q cv + c (strided axis: adjacent lines are adjacent in
-  // memory) or i = c m + q (contiguous axis); kUnroll loads in flight per lane.
-  {
-    const int total = cv * m;
-    for (int i0 = tid; i0 < total; i0 += kUnroll * nthr) {
-      TIN r[kUnroll];
+  // Strided axis: lane (q, c) with c = tid mod cb, so adjacent lanes read
+  // adjacent lines (adjacent in memory); contiguous axis: all lanes sweep one
+  // line after the other.  kUnroll loads in flight per lane, no divisions.
+  if (cfast) {
+    const int c = tid & (cb - 1);
+    const int qs = nthr >> lcb;
+    if (c < cv) {
+      const TIN* s = src + base[c];
+      T* d = lines + (size_t)c * 2 * LS;
+      for (int q0 = tid >> lcb; q0 < m; q0 += kUnroll * qs) {
+        TIN r[kUnroll];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int i = i0 + u * nthr;
-        const int ic = i < total ? i : 0;
-        int c, q;
-        if (cfast) { q = ic / cv; c = ic - q * cv; }
-        else { c = ic / m; q = ic - c * m; }
-        r[u] = src[base[c] + (long long)q * inner];
+        for (int u = 0; u < kUnroll; ++u) {
+          const int q = q0 + u * qs;
+          r[u] = s[(long long)(q < m ? q : 0) * inner];
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int q = q0 + u * qs;
+          if (q < m) d[q] = (T)r[u];
+        }
       }
+    }
+  } else {
+    for (int c = 0; c < cv; ++c) {
+      const TIN* s = src + base[c];
+      T* d = lines + (size_t)c * 2 * LS;
+      for (int q0 = tid; q0 < m; q0 += kUnroll * nthr) {
+        TIN r[kUnroll];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int i = i0 + u * nthr;
-        if (i < total) {
-          int c, q;
-          if (cfast) { q = i / cv; c = i - q * cv; }
-          else { c = i / m; q = i - c * m; }
-          lines[(size_t)c * 2 * LS + q] = (T)r[u];
+        for (int u = 0; u < kUnroll; ++u) {
+          const int q = q0 + u * nthr;
+          r[u] = s[q < m ? q : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const int q = q0 + u * nthr;
+          if (q < m) d[q] = (T)r[u];
         }
       }
     }
@@ -478,8 +500,11 @@ __global__ __launch_bounds__(kMaxThreads) void line_pass(PassArgs a) {
         const int c = task0 / (n - 1), s = task0 - c * (n - 1) + 1;
         const T* ln = lines + (size_t)c * 2 * LS;
         T acc = T(0);
-        for (int jj = 1 + lane; jj <= K; jj += 64)
-          acc += (jj & 1) ? ln[n * (jj - 1) + s - 1] : -ln[n * (jj - 1) + (n - s) - 1];
+        for (int jj = 1 + lane; jj <= K; jj += 64) {
+          const bool odd = jj & 1;
+          const T v = ln[n * (jj - 1) + (odd ? s : n - s) - 1];
+          acc += odd ? v : -v;
+        }
         acc = wave_sum(acc);
         if (lane == 0) s0[c * 8 + s - 1] = acc;
       }
@@ -493,16 +518,13 @@ __global__ __launch_bounds__(kMaxThreads) void line_pass(PassArgs a) {
 
     if (MODE == PASS_FWD) {
       // ---- forward block, coefficients to global -------------------------
-      const int items = cv * (K - 1);
-      for (int i = tid; i < items; i += nthr) {
-        int c, k;
-        if (cfast) {
-          k = i / cv + 1;
-          c = i - (k - 1) * cv;
-        } else {
-          c = i / (K - 1);
-          k = i - c * (K - 1) + 1;
-        }
+      // strided axis: lane (k, c) with c = tid mod cb; contiguous: lines in turn
+      const int c_first = cfast ? (tid & (cb - 1)) : 0;
+      const int c_step = cfast ? cb : 1;
+      const int k_first = (cfast ? (tid >> lcb) : tid) + 1;
+      const int k_step = cfast ? (nthr >> lcb) : nthr;
+      for (int c = c_first; c < cv; c += c_step)
+      for (int k = k_first; k < K; k += k_step) {
         T x[9], acc[9];
         read_seqs(slots, K, c * NP, n, k, x);
         fwd_block(P, IN, n, K, k, x, acc);
@@ -631,11 +653,9 @@ __global__ __launch_bounds__(kMaxThreads) void line_pass(PassArgs a) {
   }
   __syncthreads();
   {
-    auto value = [&](int c, int q) -> T {
+    // value at position g = q + 1 = n jn + s of line c (s = 0: mesh node)
+    auto value = [&](int c, int jn, int s) -> T {
       const int cnp = c * NP;
-      const int g = q + 1;
-      const int jn = g / n;
-      const int s = g - jn * n;
       if (s == 0) return seq_of(slots, K, cnp, 0, jn);
       const int je = jn + 1;   // element
       const T zl = (je - 1 >= 1) ? seq_of(slots, K, cnp, s, je - 1) : T(0);
@@ -643,22 +663,22 @@ __global__ __launch_bounds__(kMaxThreads) void line_pass(PassArgs a) {
       const T ee = (je & 1) ? e0[c * 8 + s - 1] : -e0[c * 8 + (n - s) - 1];
       return zl + zr + ee;
     };
-    if (cfast) {
-      int q = tid / cv, c = tid - q * cv;
-      const int dq = nthr / cv, dc = nthr - dq * cv;
-      while (q < m) {
-        dst[base[c] + (long long)q * inner] = (TOUT)value(c, q);
-        q += dq;
-        c += dc;
-        if (c >= cv) {
-          c -= cv;
-          ++q;
+    const int q_first = cfast ? (tid >> lcb) : tid;
+    const int q_step = cfast ? (nthr >> lcb) : nthr;
+    const int dj = q_step / n, ds = q_step - dj * n;
+    const int c_first = cfast ? (tid & (cb - 1)) : 0;
+    const int c_step = cfast ? cb : 1;
+    for (int c = c_first; c < cv; c += c_step) {
+      TOUT* d = dst + base[c];
+      int jn = (q_first + 1) / n, sp = (q_first + 1) - jn * n;
+      for (int q = q_first; q < m; q += q_step) {
+        d[(long long)q * inner] = (TOUT)value(c, jn, sp);
+        jn += dj;
+        sp += ds;
+        if (sp >= n) {
+          sp -= n;
+          ++jn;
         }
-      }
-    } else {
-      for (int c = 0; c < cv; ++c) {
-        TOUT* d = dst + base[c];
-        for (int q = tid; q < m; q += nthr) d[q] = (TOUT)value(c, q);
       }
     }
   }
@@ -683,6 +703,7 @@ Shape shape_for(int n, int K, size_t cplx_bytes, long long nlines) {
   c = std::min<long long>(c, kMaxCB);
   c = std::min<long long>(c, nlines);
   if (c < 1) c = 1;
+  while (c & (c - 1)) c &= c - 1;   // round down to a power of two
   Shape s;
   s.cb = (int)c;
   const int waves = (int)((c * NP + TPW - 1) / TPW);

@@ -150,6 +150,156 @@ __global__ __launch_bounds__(256) void op_kernel(OpArgs a, long long total) {
   else static_cast<double*>(a.out)[idx] = res;
 }
 
+// ---------------------------------------------------------------------------
+// 2D operator by element tiles.  A workgroup owns the points of TE0 x TE1
+// elements (positions n(E-1)+1 .. n(E-1+TE) per axis); the element after the
+// tile along each axis also touches owned points (its first node line), so
+// the workgroup stages u for (TE0+1) x (TE1+1) elements in LDS.
+//   Phase 1, per element e and local index i:
+//     D0_e[i][r1] = sum_{r0 != i} A0[i][r0] (u[r0][r1] - u[i][r1])   (stiffness along 0)
+//     D1_e[r0][i] = sum_{r1 != i} A1[i][r1] (u[r0][r1] - u[r0][i])   (stiffness along 1)
+//     M1_e[r0][i] = sum_{r1} C1[i][r1] u[r0][r1]                     (mass along 1)
+//   Phase 2, per owned point, summed over the 1, 2 or 4 elements holding it
+//   (local indices a0, a1):
+//     s0 sum_{r1} C1[a1][r1] D0_e[a0][r1] + sum_{r0} C0[a0][r0] (s1 D1_e[r0][a1] + alpha M1_e[r0][a1])
+// which is the element row of s0 A0 (x) C1 + s1 C0 (x) A1 + alpha C0 (x) C1 with
+// every stiffness factor applied to u first.
+// ---------------------------------------------------------------------------
+
+struct Tile2 {
+  int TE0, TE1, nt0, nt1;
+};
+
+__global__ __launch_bounds__(256) void op2_tiled_kernel(OpArgs a, Tile2 tl) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int n0 = a.n[0], n1 = a.n[1], b0 = n0 + 1, b1 = n1 + 1;
+  const int K0 = a.K[0], K1 = a.K[1], m0 = a.m[0], m1 = a.m[1];
+  const int t0 = blockIdx.x / tl.nt1, t1 = blockIdx.x - t0 * tl.nt1;
+  const long long roff = (long long)blockIdx.y * m0 * m1;
+  const int E0 = t0 * tl.TE0 + 1, E1 = t1 * tl.TE1 + 1;        // first element (1-based)
+  const int ne0 = min(tl.TE0 + 1, K0 - E0 + 1), ne1 = min(tl.TE1 + 1, K1 - E1 + 1);
+  const int P0 = n0 * ne0 + 1, P1 = n1 * ne1 + 1;              // staged points per axis
+  const int g00 = n0 * (E0 - 1), g10 = n1 * (E1 - 1);          // position of local point 0
+  const int eb = b0 * b1;                                       // values per element block
+
+  double* A0 = reinterpret_cast<double*>(smem);
+  double* C0 = A0 + 100;
+  double* A1 = C0 + 100;
+  double* C1 = A1 + 100;
+  double* U = C1 + 100;                                         // [P0][P1]
+  double* I = U + ((P0 * P1 + 1) & ~1);                          // [elements][3][b0 b1]
+  const int tid = threadIdx.x, nthr = blockDim.x;
+
+  for (int i = tid; i < b0 * b0; i += nthr) {
+    A0[i] = a.A[0][i];
+    C0[i] = a.C[0][i];
+  }
+  for (int i = tid; i < b1 * b1; i += nthr) {
+    A1[i] = a.A[1][i];
+    C1[i] = a.C[1][i];
+  }
+  const double* __restrict__ u = a.u + roff;
+  for (int i = tid; i < P0 * P1; i += nthr) {
+    const int i0 = i / P1, i1 = i - i0 * P1;
+    const int g0 = g00 + i0, g1 = g10 + i1;
+    double v = 0.0;
+    if (g0 >= 1 && g0 <= m0 && g1 >= 1 && g1 <= m1) v = u[(long long)(g0 - 1) * m1 + (g1 - 1)];
+    U[i] = v;
+  }
+  __syncthreads();
+
+  // phase 1
+  const int bmax = b0 > b1 ? b0 : b1;
+  const int tasks = ne0 * ne1 * bmax;
+  for (int task = tid; task < tasks; task += nthr) {
+    const int el = task / bmax, i = task - el * bmax;
+    const int l0 = el / ne1, l1 = el - l0 * ne1;
+    const double* Ue = U + (l0 * n0) * P1 + l1 * n1;             // element origin
+    double* D0 = I + (size_t)el * 3 * eb;
+    double* D1 = D0 + eb;
+    double* M1 = D1 + eb;
+    if (i < b0) {
+      const double* Ai = A0 + i * b0;
+      for (int r1 = 0; r1 < b1; ++r1) {
+        const double ui = Ue[i * P1 + r1];
+        double t = 0.0;
+        for (int r0 = 0; r0 < b0; ++r0)
+          if (r0 != i) t += Ai[r0] * (Ue[r0 * P1 + r1] - ui);
+        D0[i * b1 + r1] = t;
+      }
+    }
+    if (i < b1) {
+      const double* Ai = A1 + i * b1;
+      const double* Ci = C1 + i * b1;
+      for (int r0 = 0; r0 < b0; ++r0) {
+        const double* row = Ue + r0 * P1;
+        const double ui = row[i];
+        double t = 0.0, mm = 0.0;
+        for (int r1 = 0; r1 < b1; ++r1) {
+          const double v = row[r1];
+          if (r1 != i) t += Ai[r1] * (v - ui);
+          mm += Ci[r1] * v;
+        }
+        D1[r0 * b1 + i] = t;
+        M1[r0 * b1 + i] = mm;
+      }
+    }
+  }
+  __syncthreads();
+
+  // phase 2: owned points p = 1 .. n TE per axis (local), inside the domain
+  const double s0 = a.scale[0], s1 = a.scale[1], al = a.alpha;
+  const int own0 = n0 * tl.TE0, own1 = n1 * tl.TE1;
+  const int cnt = own0 * own1;
+  const double* __restrict__ f = a.f ? a.f + roff : nullptr;
+  for (int i = tid; i < cnt; i += nthr) {
+    const int p0 = i / own1 + 1, p1 = i - (p0 - 1) * own1 + 1;
+    const int g0 = g00 + p0, g1 = g10 + p1;
+    if (g0 > m0 || g1 > m1) continue;
+    int el0[2], a0s[2], n0e = 1, el1[2], a1s[2], n1e = 1;
+    if (p0 % n0 == 0) {
+      el0[0] = p0 / n0 - 1; a0s[0] = n0;
+      el0[1] = p0 / n0;     a0s[1] = 0;
+      n0e = (el0[1] < ne0) ? 2 : 1;
+    } else {
+      el0[0] = p0 / n0; a0s[0] = p0 % n0;
+    }
+    if (p1 % n1 == 0) {
+      el1[0] = p1 / n1 - 1; a1s[0] = n1;
+      el1[1] = p1 / n1;     a1s[1] = 0;
+      n1e = (el1[1] < ne1) ? 2 : 1;
+    } else {
+      el1[0] = p1 / n1; a1s[0] = p1 % n1;
+    }
+    double acc = 0.0;
+    for (int c0 = 0; c0 < n0e; ++c0)
+      for (int c1 = 0; c1 < n1e; ++c1) {
+        const int el = el0[c0] * ne1 + el1[c1];
+        const int a0 = a0s[c0], a1 = a1s[c1];
+        const double* D0 = I + (size_t)el * 3 * eb;
+        const double* D1 = D0 + eb;
+        const double* M1 = D1 + eb;
+        double t = 0.0;
+        for (int r1 = 0; r1 < b1; ++r1) t += C1[a1 * b1 + r1] * D0[a0 * b1 + r1];
+        double w = 0.0;
+        for (int r0 = 0; r0 < b0; ++r0)
+          w += C0[a0 * b0 + r0] * (s1 * D1[r0 * b1 + a1] + al * M1[r0 * b1 + a1]);
+        acc += s0 * t + w;
+      }
+    const long long idx = (long long)(g0 - 1) * m1 + (g1 - 1);
+    const double res = f ? f[idx] - acc : acc;
+    if (a.out_f32) static_cast<float*>(a.out)[roff + idx] = (float)res;
+    else static_cast<double*>(a.out)[roff + idx] = res;
+  }
+}
+
+// LDS bytes of a 2D tile of TE0 x TE1 owned elements.
+size_t tile2_lds(int n0, int n1, int TE0, int TE1) {
+  const size_t P0 = (size_t)n0 * (TE0 + 1) + 1, P1 = (size_t)n1 * (TE1 + 1) + 1;
+  const size_t els = (size_t)(TE0 + 1) * (TE1 + 1);
+  return (400 + ((P0 * P1 + 1) & ~size_t(1)) + els * 3 * (n0 + 1) * (n1 + 1)) * sizeof(double);
+}
+
 // u += delta and per-workgroup partial sums of delta^2 and u^2 (u after the update).
 __global__ __launch_bounds__(256) void axpy_norms_kernel(const float* delta, double* u,
                                                          long long count, double* partial) {
@@ -217,7 +367,29 @@ hipError_t launch_operator(const OpArgs& a, hipStream_t s) {
   const unsigned blocks = (unsigned)((total + 255) / 256);
   switch (a.N) {
     case 1: hipLaunchKernelGGL(op_kernel<1>, dim3(blocks), dim3(256), 0, s, a, total); break;
-    case 2: hipLaunchKernelGGL(op_kernel<2>, dim3(blocks), dim3(256), 0, s, a, total); break;
+    case 2: {
+      // largest square-ish tile that keeps LDS within 64 KB (at least 1 x 1)
+      Tile2 tl{1, 1, 0, 0};
+      for (int te = 16; te >= 1; --te) {
+        if (tile2_lds(a.n[0], a.n[1], te, te) <= 64 * 1024) {
+          tl.TE0 = tl.TE1 = te;
+          break;
+        }
+      }
+      tl.nt0 = (a.K[0] + tl.TE0 - 1) / tl.TE0;
+      tl.nt1 = (a.K[1] + tl.TE1 - 1) / tl.TE1;
+      const size_t lds = tile2_lds(a.n[0], a.n[1], tl.TE0, tl.TE1);
+      static bool raised = false;
+      if (!raised) {
+        hipError_t e = hipFuncSetAttribute((const void*)op2_tiled_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        raised = true;
+      }
+      hipLaunchKernelGGL(op2_tiled_kernel, dim3((unsigned)(tl.nt0 * tl.nt1), (unsigned)a.nrhs),
+                         dim3(256), lds, s, a, tl);
+      break;
+    }
     case 3: hipLaunchKernelGGL(op_kernel<3>, dim3(blocks), dim3(256), 0, s, a, total); break;
     default: return hipErrorInvalidValue;
   }
