@@ -64,7 +64,9 @@ enum hofem_status {
 enum hofem_mode {
   HOFEM_MODE_FP64 = 0,     /* FP64 transforms; f, u are double */
   HOFEM_MODE_FP32 = 1,     /* FP32 transforms with FP32 accumulation; f, u are float */
-  HOFEM_MODE_FP32_IR = 2   /* FP32 transforms + FP64 iterative refinement; f, u are double */
+  HOFEM_MODE_FP32_IR = 2,  /* FP32 transforms + FP64 iterative refinement; f, u are double */
+  HOFEM_MODE_FP32_PCG = 3  /* CG on the FP64 operator preconditioned by the FP32 solve;
+                              f, u are double */
 };
 
 typedef struct hofem_plan1d_s* hofem_plan1d;
@@ -72,9 +74,24 @@ typedef struct hofem_solver_s* hofem_solver;
 
 /* Statistics of the last solve (filled when `info` is non-NULL). */
 typedef struct {
-  int iterations;          /* refinement steps taken (0 for direct modes) */
+  int iterations;          /* refinement / CG steps taken (0 for direct modes) */
   double rel_update;       /* ||last correction||_2 / ||u||_2 */
+  double rel_residual;     /* ||f - L u||_2 / ||f||_2 (CG modes), else 0 */
 } hofem_info;
+
+/* Coefficient a(x) of -div(a grad u) + alpha u for hofem_pcg. */
+typedef struct {
+  int kind;                /* 0: a = 1 (the solver's own operator)
+                              1: a(x) = c0 + c1 prod_i t_i(x_i), t_i tabulated
+                              2: a tabulated at every Gauss point */
+  double c0, c1;           /* kind 1 */
+  const double* t_dev[3];  /* kind 1: t_i at the (n_i+1)-point Gauss nodes of every element
+                              of axis i, index e_i (n_i+1) + q (K_i (n_i+1) values); the
+                              nodes of an element in increasing order, i.e. the physical
+                              points (e_i + (1 + xi_q) / 2) h_i with xi_q = table gx */
+  const double* a_dev;     /* kind 2: index E (n+1)^N + Q with E the C-order index of the
+                              element (e_0..e_{N-1}) and Q that of the Gauss point */
+} hofem_coef;
 
 /* ---- 1D eigen data (host) -------------------------------------------- */
 
@@ -99,6 +116,10 @@ int hofem_plan1d_dim(hofem_plan1d plan, int* m);
  *   3  e^(l) as columns: index i (n-1) + l-1              ((n-1)^2 values)
  *   4  local stiffness A on [-1, 1], row major           ((n+1)^2 values)
  *   5  local mass C on [-1, 1], row major                ((n+1)^2 values)
+ *   6  nodes x_q of the (n+1)-point Gauss-Legendre rule, increasing (n+1 values)
+ *   7  its weights w_q                                    (n+1 values)
+ *   8  basis values e_r(x_q) at index q (n+1) + r         ((n+1)^2 values)
+ *   9  basis derivatives e_r'(x_q) at index q (n+1) + r   ((n+1)^2 values)
  * The coefficient index of a line is q = l-1 for k = 0 (l = 1..n-1) and
  * q = n k - 1 + l-1 for k = 1..K-1 (l = 1..n).  `len` must equal the count;
  * otherwise HOFEM_EINVAL. */
@@ -159,6 +180,30 @@ int hofem_forward(hofem_solver solver, int mode, const void* in_dev, void* out_d
  * out = sum of coefficient * eigenvector products.  in_dev == out_dev allowed. */
 int hofem_inverse(hofem_solver solver, int mode, const void* in_dev, void* out_dev, int nrhs,
                   void* stream);
+
+/* Preconditioned conjugate gradients for -div(a grad u) + alpha u = f in the
+ * scaled form of eq. (bvp glob 2) (the operator's stiffness part becomes
+ * sum_i 4 h_i^-2 int a d_i u d_i phi on every element, by the (n+1)-point Gauss
+ * rule per axis), preconditioned by the FP32 fast solve of the solver's own
+ * constant-coefficient operator: the paper's use of the fast algorithm as a
+ * preconditioner for general second-order elliptic equations (Section 1).
+ * FP64 vectors, FP64 matrix-free operator (derivative factors in difference
+ * form, applied first), deterministic reductions.  Starts from the FP32 fast
+ * solve of f; stops when ||f - L u||_2 <= rtol ||f||_2 (rtol > 0) or after
+ * max_iter steps; returns HOFEM_ENOCONV when rtol > 0 was not reached (u
+ * holds the last iterate).  Waits for the stream once per step.
+ * coef == NULL means kind 0.  f_dev, u_dev: [nrhs][m_0]..[m_{N-1}] double,
+ * f_dev != u_dev; right-hand sides are solved one after another. */
+int hofem_pcg_workspace_bytes(hofem_solver solver, const hofem_coef* coef, size_t* bytes);
+int hofem_pcg(hofem_solver solver, const hofem_coef* coef, const double* f_dev, double* u_dev,
+              int nrhs, double rtol, int max_iter, void* ws_dev, size_t ws_bytes, void* stream,
+              hofem_info* info);
+
+/* out = L_a u (f NULL) for the variable-coefficient operator of hofem_pcg
+ * (FP64; needs hofem_pcg_workspace_bytes of workspace for kind 1 and 2). */
+int hofem_apply_coef_operator(hofem_solver solver, const hofem_coef* coef, const double* u_dev,
+                              double* out_dev, int nrhs, void* ws_dev, size_t ws_bytes,
+                              void* stream);
 
 /* out = L u with L the operator of eq. (bvp glob 2), FP64, matrix-free,
  * element by element, the stiffness factors in difference form

@@ -24,15 +24,21 @@ HOFEM_ENOCONV = -4
 HOFEM_EHIP = -5
 HOFEM_ENOMEM = -6
 
-MODES = {"fp64": 0, "fp32": 1, "fp32_ir": 2}
-TABLES = {"lam": 0, "p": 1, "inorm": 2, "E": 3, "A": 4, "C": 5}
+MODES = {"fp64": 0, "fp32": 1, "fp32_ir": 2, "fp32_pcg": 3}
+TABLES = {"lam": 0, "p": 1, "inorm": 2, "E": 3, "A": 4, "C": 5, "gx": 6, "gw": 7, "B": 8, "D": 9}
 
 # Names and signatures of every entry point of include/hofem.h.
 _c_int, _c_double, _c_size, _vp = ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p
 
 
 class hofem_info(ctypes.Structure):
-    _fields_ = [("iterations", ctypes.c_int), ("rel_update", ctypes.c_double)]
+    _fields_ = [("iterations", ctypes.c_int), ("rel_update", ctypes.c_double),
+                ("rel_residual", ctypes.c_double)]
+
+
+class hofem_coef(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("c0", ctypes.c_double), ("c1", ctypes.c_double),
+                ("t_dev", ctypes.c_void_p * 3), ("a_dev", ctypes.c_void_p)]
 
 
 class hofem_pass_time(ctypes.Structure):
@@ -58,6 +64,11 @@ SIGNATURES = {
     "hofem_forward": (_c_int, [_vp, _c_int, _vp, _vp, _c_int, _vp]),
     "hofem_inverse": (_c_int, [_vp, _c_int, _vp, _vp, _c_int, _vp]),
     "hofem_apply_operator": (_c_int, [_vp, _vp, _vp, _c_int, _vp]),
+    "hofem_pcg_workspace_bytes": (_c_int, [_vp, ctypes.POINTER(hofem_coef), ctypes.POINTER(_c_size)]),
+    "hofem_pcg": (_c_int, [_vp, ctypes.POINTER(hofem_coef), _vp, _vp, _c_int, _c_double, _c_int,
+                           _vp, _c_size, _vp, ctypes.POINTER(hofem_info)]),
+    "hofem_apply_coef_operator": (_c_int, [_vp, ctypes.POINTER(hofem_coef), _vp, _vp, _c_int, _vp,
+                                           _c_size, _vp]),
     "hofem_solver_set_timing": (_c_int, [_vp, _c_int]),
     "hofem_solver_pass_times": (_c_int, [_vp, ctypes.POINTER(hofem_pass_time), _c_int,
                                          ctypes.POINTER(_c_int)]),
@@ -186,6 +197,46 @@ def hofem_apply_operator(solver, u, out, nrhs=1, stream=None):
            "hofem_apply_operator")
 
 
+def make_coef(kind=0, c0=1.0, c1=0.0, t=(None, None, None), a=None):
+    """hofem_coef from torch device tensors (t: per-axis tables, a: full table)."""
+    c = hofem_coef()
+    c.kind = int(kind)
+    c.c0 = float(c0)
+    c.c1 = float(c1)
+    for i in range(3):
+        ti = t[i] if i < len(t) else None
+        c.t_dev[i] = ti.data_ptr() if ti is not None else None
+    c.a_dev = a.data_ptr() if a is not None else None
+    return c
+
+
+def hofem_pcg_workspace_bytes(solver, coef=None):
+    s = ctypes.c_size_t()
+    _check(_lib.hofem_pcg_workspace_bytes(solver, ctypes.byref(coef) if coef else None,
+                                          ctypes.byref(s)), "hofem_pcg_workspace_bytes")
+    return s.value
+
+
+def hofem_pcg(solver, coef, f, u, nrhs=1, rtol=1e-10, max_iter=100, ws=None, stream=None,
+              raise_noconv=True):
+    info = hofem_info()
+    wsb = 0 if ws is None else ws.numel() * ws.element_size()
+    st = _lib.hofem_pcg(solver, ctypes.byref(coef) if coef else None, _ptr(f), _ptr(u), int(nrhs),
+                        float(rtol), int(max_iter), _ptr(ws), wsb, _stream(stream),
+                        ctypes.byref(info))
+    if st == HOFEM_ENOCONV and not raise_noconv:
+        return info, st
+    _check(st, "hofem_pcg")
+    return info, st
+
+
+def hofem_apply_coef_operator(solver, coef, u, out, nrhs=1, ws=None, stream=None):
+    wsb = 0 if ws is None else ws.numel() * ws.element_size()
+    _check(_lib.hofem_apply_coef_operator(solver, ctypes.byref(coef) if coef else None, _ptr(u),
+                                          _ptr(out), int(nrhs), _ptr(ws), wsb, _stream(stream)),
+           "hofem_apply_coef_operator")
+
+
 def hofem_solver_set_timing(solver, enable):
     _check(_lib.hofem_solver_set_timing(solver, 1 if enable else 0), "hofem_solver_set_timing")
 
@@ -212,7 +263,8 @@ class Plan1D:
     def table(self, which):
         n, K = self.n, self.K
         counts = {"lam": self.m, "p": (K - 1) * n * (n - 1), "inorm": (K - 1) * n,
-                  "E": (n - 1) ** 2, "A": (n + 1) ** 2, "C": (n + 1) ** 2}
+                  "E": (n - 1) ** 2, "A": (n + 1) ** 2, "C": (n + 1) ** 2,
+                  "gx": n + 1, "gw": n + 1, "B": (n + 1) ** 2, "D": (n + 1) ** 2}
         return hofem_plan1d_table(self.handle, which, counts[which])
 
     def close(self):
@@ -242,6 +294,31 @@ class Solver:
             p.close()
         self.size = hofem_solver_size(self.handle)
 
+    def pcg_workspace(self, coef=None, device="cuda"):
+        import torch
+        b = hofem_pcg_workspace_bytes(self.handle, coef)
+        return torch.empty(b, dtype=torch.uint8, device=device)
+
+    def pcg(self, f, u=None, coef=None, nrhs=1, rtol=1e-10, max_iter=100, ws=None, stream=None,
+            raise_noconv=True):
+        """CG on -div(a grad u) + alpha u = f preconditioned by the FP32 fast solve."""
+        import torch
+        self._check_grid(f, torch.float64, nrhs, "f")
+        u = torch.empty_like(f) if u is None else u
+        if ws is None:
+            ws = self.pcg_workspace(coef, f.device)
+        info, st = hofem_pcg(self.handle, coef, f, u, nrhs, rtol, max_iter, ws, stream,
+                             raise_noconv)
+        return u, info, st
+
+    def apply_coef_operator(self, u, coef, out=None, nrhs=1, ws=None, stream=None):
+        import torch
+        out = torch.empty_like(u) if out is None else out
+        if ws is None:
+            ws = self.pcg_workspace(coef, u.device)
+        hofem_apply_coef_operator(self.handle, coef, u, out, nrhs, ws, stream)
+        return out
+
     def workspace(self, mode, nrhs=1, device="cuda"):
         import torch
         b = hofem_solver_workspace_bytes(self.handle, mode, nrhs)
@@ -267,7 +344,7 @@ class Solver:
         if u is None:
             u = torch.empty_like(f)
         self._check_grid(u, dt, nrhs, "u")
-        if mode == "fp32_ir" and ws is None:
+        if mode in ("fp32_ir", "fp32_pcg") and ws is None:
             ws = self.workspace(mode, nrhs, f.device)
         info, st = hofem_solve(self.handle, mode, f, u, nrhs, ws, max_iter, tol, stream, want_info,
                                raise_noconv)

@@ -35,7 +35,7 @@ def build(verbose=True):
     o = os.path.join(OUT_DIR, "plan1d.o")
     _run(["g++"] + CXX_FLAGS + ["-c", os.path.join(CSRC, "plan1d.cpp"), "-o", o])
     objs.append(o)
-    for src in ("kernels.hip", "operator.hip", "capi.hip"):
+    for src in ("kernels.hip", "operator.hip", "pcg.hip", "capi.hip"):
         o = os.path.join(OUT_DIR, src.replace(".hip", ".o"))
         _run([HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", o])
         objs.append(o)

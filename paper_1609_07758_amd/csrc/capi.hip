@@ -47,6 +47,9 @@ struct DevAxis {
   AxisTab t64{}, t32{};
   const double* A = nullptr;
   const double* C = nullptr;
+  const double* B = nullptr;    // basis values at the Gauss nodes
+  const double* D = nullptr;    // basis derivatives at the Gauss nodes
+  const double* gw = nullptr;   // Gauss weights
 };
 
 // Packs host arrays into one byte buffer with 256-byte aligned offsets.
@@ -216,6 +219,156 @@ OpArgs make_op(const hofem_solver_s* S, const double* u, const double* f, void* 
   return o;
 }
 
+VarOpArgs make_varop(const hofem_solver_s* S, const hofem_coef* c, const double* u,
+                     const double* f, double* out, int nrhs) {
+  VarOpArgs v{};
+  v.u = u;
+  v.f = f;
+  v.out = out;
+  v.N = S->N;
+  long long per = 1;
+  for (int i = S->N - 1; i >= 0; --i) {
+    v.stride[i] = per;
+    per *= S->ax[i].m;
+  }
+  v.per_rhs = per;
+  v.nrhs = nrhs;
+  for (int i = 0; i < S->N; ++i) {
+    v.n[i] = S->ax[i].n;
+    v.K[i] = S->ax[i].K;
+    v.scale[i] = S->ax[i].scale;
+    v.B[i] = S->ax[i].B;
+    v.D[i] = S->ax[i].D;
+    v.w[i] = S->ax[i].gw;
+    v.t[i] = c ? c->t_dev[i] : nullptr;
+  }
+  v.alpha = S->alpha;
+  v.kind = c ? c->kind : 0;
+  v.c0 = c ? c->c0 : 1.0;
+  v.c1 = c ? c->c1 : 0.0;
+  v.afull = c ? c->a_dev : nullptr;
+  return v;
+}
+
+constexpr int kPcgParts = 1024;
+
+struct PcgWs {
+  double *r, *z, *p, *q, *elem, *partial, *scal;
+  float* w32;
+};
+
+size_t pcg_bytes(const hofem_solver_s* S, const hofem_coef* c) {
+  const size_t n = S->per_rhs;
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  size_t b = 4 * al(n * sizeof(double)) + al(n * sizeof(float));
+  if (c && c->kind != 0) b += al(varop_elem_bytes(make_varop(S, c, nullptr, nullptr, nullptr, 1)));
+  b += al(2 * kPcgParts * sizeof(double)) + al(16 * sizeof(double));
+  return b;
+}
+
+PcgWs pcg_carve(const hofem_solver_s* S, const hofem_coef* c, void* ws) {
+  const size_t n = S->per_rhs;
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  unsigned char* p = static_cast<unsigned char*>(ws);
+  PcgWs w{};
+  w.r = reinterpret_cast<double*>(p); p += al(n * sizeof(double));
+  w.z = reinterpret_cast<double*>(p); p += al(n * sizeof(double));
+  w.p = reinterpret_cast<double*>(p); p += al(n * sizeof(double));
+  w.q = reinterpret_cast<double*>(p); p += al(n * sizeof(double));
+  w.w32 = reinterpret_cast<float*>(p); p += al(n * sizeof(float));
+  if (c && c->kind != 0) {
+    w.elem = reinterpret_cast<double*>(p);
+    p += al(varop_elem_bytes(make_varop(S, c, nullptr, nullptr, nullptr, 1)));
+  }
+  w.partial = reinterpret_cast<double*>(p); p += al(2 * kPcgParts * sizeof(double));
+  w.scal = reinterpret_cast<double*>(p);
+  return w;
+}
+
+// out = f - A u (f != NULL) or A u, for one right-hand side
+int pcg_apply(hofem_solver_s* S, const hofem_coef* c, const PcgWs& w, const double* u,
+              const double* f, double* out, hipStream_t st) {
+  const long long count = (long long)S->per_rhs;
+  if (!c || c->kind == 0) {
+    OpArgs o = make_op(S, u, f, out, 0, 1);
+    LaunchTimer tm(S, st, HOFEM_PASS_OPERATOR, -1, 1, (double)count * (f ? 24 : 16));
+    HIPCHK(launch_operator(o, st));
+    tm.done();
+  } else {
+    VarOpArgs v = make_varop(S, c, u, f, out, 1);
+    LaunchTimer tm(S, st, HOFEM_PASS_OPERATOR, -1, 1, (double)count * (f ? 24 : 16));
+    HIPCHK(launch_varop(v, w.elem, st));
+    tm.done();
+  }
+  return HOFEM_OK;
+}
+
+// CG on one right-hand side; stops on the relative residual (rtol > 0) or
+// the relative update (utol > 0).
+int pcg_run(hofem_solver_s* S, const hofem_coef* c, const PcgWs& w, const double* f, double* x,
+            double rtol, double utol, int max_iter, hipStream_t st, int* iters, double* rel_res,
+            double* rel_upd, bool* converged) {
+  const long long n = (long long)S->per_rhs;
+  const std::vector<PassSpec> list = solve_list(S->N);
+  const int np = (int)std::max<long long>(1, std::min<long long>(kPcgParts, (n + 255) / 256));
+  double* sc = w.scal;
+  auto precond = [&](const double* in, double* out) {
+    return run_list(S, list, false, in, w.w32, out, 2, 1, 3, 5, 1, st);
+  };
+  int rc = precond(f, x);                                   // x0 = S32 f
+  if (rc != HOFEM_OK) return rc;
+  if ((rc = pcg_apply(S, c, w, x, f, w.r, st)) != HOFEM_OK) return rc;   // r = f - A x
+  if ((rc = precond(w.r, w.z)) != HOFEM_OK) return rc;      // z = S32 r
+  HIPCHK(hipMemcpyAsync(w.p, w.z, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHK(launch_dot2(w.r, w.z, w.r, n, w.partial, np, sc + 2, st));   // rz, (rr -> sc[3])
+  HIPCHK(launch_dot2(f, f, nullptr, n, w.partial, np, sc + 9, st));    // ff
+  double h[16];
+  HIPCHK(hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const double ff = h[9] > 0 ? h[9] : 1.0;
+  *rel_res = std::sqrt(h[3] / ff);
+  *rel_upd = 0.0;
+  *iters = 0;
+  *converged = (rtol > 0 && *rel_res <= rtol);
+  for (int it = 1; it <= max_iter && !*converged; ++it) {
+    if ((rc = pcg_apply(S, c, w, w.p, nullptr, w.q, st)) != HOFEM_OK) return rc;   // q = A p
+    HIPCHK(launch_dot2(w.p, w.q, w.p, n, w.partial, np, sc + 3, st));              // pq, pp
+    HIPCHK(launch_scalar_op(sc, 0, st));                                           // alpha
+    {
+      LaunchTimer tm(S, st, HOFEM_PASS_UPDATE, -1, 1, (double)n * 48);
+      HIPCHK(launch_cg_update(x, w.r, w.p, w.q, n, sc, w.partial, np, sc + 7, st));  // rr, xx
+      tm.done();
+    }
+    HIPCHK(hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    *iters = it;
+    *rel_res = std::sqrt(h[7] / ff);
+    *rel_upd = h[8] > 0 ? std::fabs(h[0]) * std::sqrt(h[4] / h[8]) : 0.0;
+    if ((rtol > 0 && *rel_res <= rtol) || (utol > 0 && *rel_upd <= utol)) {
+      *converged = true;
+      break;
+    }
+    if (it == max_iter) break;
+    HIPCHK(launch_dot2(w.r, w.z, nullptr, n, w.partial, np, sc + 10, st));         // r z_old
+    if ((rc = precond(w.r, w.z)) != HOFEM_OK) return rc;                           // z = S32 r
+    HIPCHK(launch_dot2(w.r, w.z, nullptr, n, w.partial, np, sc + 5, st));          // rz_new
+    HIPCHK(launch_scalar_op(sc, 1, st));                                           // beta
+    HIPCHK(launch_cg_dir(w.p, w.z, n, sc, st));                                    // p = z + beta p
+  }
+  if (rtol <= 0 && utol <= 0) *converged = true;
+  return HOFEM_OK;
+}
+
+bool coef_ok(const hofem_solver_s* S, const hofem_coef* c) {
+  if (!c || c->kind == 0) return true;
+  if (c->kind == 1) {
+    for (int i = 0; i < S->N; ++i)
+      if (!c->t_dev[i]) return false;
+    return std::isfinite(c->c0) && std::isfinite(c->c1);
+  }
+  return c->kind == 2 && c->a_dev != nullptr;
+}
+
 }  // namespace
 
 extern "C" {
@@ -269,6 +422,10 @@ int hofem_plan1d_table(hofem_plan1d plan, int which, double* out_host, size_t le
     case 3: v = &d.E; count = (size_t)(n - 1) * (n - 1); break;
     case 4: v = &d.A; count = (size_t)(n + 1) * (n + 1); break;
     case 5: v = &d.C; count = (size_t)(n + 1) * (n + 1); break;
+    case 6: v = &d.gx; count = (size_t)(n + 1); break;
+    case 7: v = &d.gw; count = (size_t)(n + 1); break;
+    case 8: v = &d.B; count = (size_t)(n + 1) * (n + 1); break;
+    case 9: v = &d.D; count = (size_t)(n + 1) * (n + 1); break;
     default: return HOFEM_EINVAL;
   }
   if (len != count) return HOFEM_EINVAL;
@@ -307,7 +464,7 @@ int hofem_solver_create(int N, const hofem_plan1d* plans, const double* X, doubl
   }
   Packer pk;
   struct Off {
-    size_t lam, lamk, p64, in64, E64, tw64, sn64, p32, in32, E32, tw32, sn32, A, C;
+    size_t lam, lamk, p64, in64, E64, tw64, sn64, p32, in32, E32, tw32, sn32, A, C, B, D, gw;
   } off[3];
   for (int i = 0; i < N; ++i) {
     const Plan1DData& d = plans[i]->d;
@@ -345,6 +502,9 @@ int hofem_solver_create(int N, const hofem_plan1d* plans, const double* X, doubl
     off[i].sn32 = pk.add_f32(d.sn);
     off[i].A = pk.add_f64(d.A);
     off[i].C = pk.add_f64(d.C);
+    off[i].B = pk.add_f64(d.B);
+    off[i].D = pk.add_f64(d.D);
+    off[i].gw = pk.add_f64(d.gw);
   }
   void* mem = nullptr;
   e = hipMalloc(&mem, pk.bytes.size());
@@ -370,6 +530,9 @@ int hofem_solver_create(int N, const hofem_plan1d* plans, const double* X, doubl
                      b + off[i].sn32, lam, lamk, ax.n, ax.K, ax.m};
     ax.A = reinterpret_cast<const double*>(b + off[i].A);
     ax.C = reinterpret_cast<const double*>(b + off[i].C);
+    ax.B = reinterpret_cast<const double*>(b + off[i].B);
+    ax.D = reinterpret_cast<const double*>(b + off[i].D);
+    ax.gw = reinterpret_cast<const double*>(b + off[i].gw);
   }
   *out = S;
   return HOFEM_OK;
@@ -425,6 +588,7 @@ int hofem_solver_workspace_bytes(hofem_solver solver, int mode, int nrhs, size_t
     case HOFEM_MODE_FP64:
     case HOFEM_MODE_FP32: *bytes = 0; return HOFEM_OK;
     case HOFEM_MODE_FP32_IR: *bytes = ir_workspace(solver, nrhs); return HOFEM_OK;
+    case HOFEM_MODE_FP32_PCG: *bytes = pcg_bytes(solver, nullptr); return HOFEM_OK;
     default: return HOFEM_EINVAL;
   }
 }
@@ -442,8 +606,31 @@ int hofem_solve(hofem_solver S, int mode, const void* f_dev, void* u_dev, int nr
     if (info) {
       info->iterations = 0;
       info->rel_update = 0.0;
+      info->rel_residual = 0.0;
     }
     return HOFEM_OK;
+  }
+  if (mode == HOFEM_MODE_FP32_PCG) {
+    if (max_iter < 0 || !std::isfinite(tol) || f_dev == u_dev) return HOFEM_EINVAL;
+    if (!ws_dev || ws_bytes < pcg_bytes(S, nullptr)) return HOFEM_EINVAL;
+    const PcgWs w = pcg_carve(S, nullptr, ws_dev);
+    int its = 0;
+    double rr = 0, ru = 0;
+    bool conv = true;
+    for (int r = 0; r < nrhs; ++r) {
+      bool c1 = false;
+      const int rc = pcg_run(S, nullptr, w, static_cast<const double*>(f_dev) + r * S->per_rhs,
+                             static_cast<double*>(u_dev) + r * S->per_rhs, 0.0, tol, max_iter, st,
+                             &its, &rr, &ru, &c1);
+      if (rc != HOFEM_OK) return rc;
+      conv = conv && c1;
+    }
+    if (info) {
+      info->iterations = its;
+      info->rel_update = ru;
+      info->rel_residual = rr;
+    }
+    return conv ? HOFEM_OK : HOFEM_ENOCONV;
   }
   if (mode != HOFEM_MODE_FP32_IR) return HOFEM_EINVAL;
   if (max_iter < 0 || !std::isfinite(tol)) return HOFEM_EINVAL;
@@ -494,6 +681,7 @@ int hofem_solve(hofem_solver S, int mode, const void* f_dev, void* u_dev, int nr
   if (info) {
     info->iterations = it;
     info->rel_update = 0.0;
+    info->rel_residual = 0.0;
     if (it > 0) {
       if (!have) {
         HIPCHK(hipMemcpyAsync(host, sums, sizeof(host), hipMemcpyDeviceToHost, st));
@@ -527,6 +715,59 @@ int hofem_inverse(hofem_solver S, int mode, const void* in_dev, void* out_dev, i
   for (int a = 0; a < S->N; ++a) l.push_back({a, PASS_INV});
   return run_list(S, l, f64, in_dev, out_dev, out_dev, dt, dt, dt, dt, nrhs,
                   static_cast<hipStream_t>(stream));
+}
+
+int hofem_pcg_workspace_bytes(hofem_solver S, const hofem_coef* coef, size_t* bytes) {
+  if (!S || !bytes || !coef_ok(S, coef)) return HOFEM_EINVAL;
+  *bytes = pcg_bytes(S, coef);
+  return HOFEM_OK;
+}
+
+int hofem_pcg(hofem_solver S, const hofem_coef* coef, const double* f_dev, double* u_dev, int nrhs,
+              double rtol, int max_iter, void* ws_dev, size_t ws_bytes, void* stream,
+              hofem_info* info) {
+  if (!S || !f_dev || !u_dev || nrhs < 1 || f_dev == u_dev || max_iter < 0 ||
+      !std::isfinite(rtol) || !coef_ok(S, coef))
+    return HOFEM_EINVAL;
+  if (!ws_dev || ws_bytes < pcg_bytes(S, coef)) return HOFEM_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const PcgWs w = pcg_carve(S, coef, ws_dev);
+  int its = 0;
+  double rr = 0, ru = 0;
+  bool conv = true;
+  for (int r = 0; r < nrhs; ++r) {
+    bool c1 = false;
+    const int rc = pcg_run(S, coef, w, f_dev + r * S->per_rhs, u_dev + r * S->per_rhs, rtol, 0.0,
+                           max_iter, st, &its, &rr, &ru, &c1);
+    if (rc != HOFEM_OK) return rc;
+    conv = conv && c1;
+  }
+  if (info) {
+    info->iterations = its;
+    info->rel_update = ru;
+    info->rel_residual = rr;
+  }
+  return conv ? HOFEM_OK : HOFEM_ENOCONV;
+}
+
+int hofem_apply_coef_operator(hofem_solver S, const hofem_coef* coef, const double* u_dev,
+                              double* out_dev, int nrhs, void* ws_dev, size_t ws_bytes,
+                              void* stream) {
+  if (!S || !u_dev || !out_dev || nrhs < 1 || u_dev == out_dev || !coef_ok(S, coef))
+    return HOFEM_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (!coef || coef->kind == 0) {
+    OpArgs o = make_op(S, u_dev, nullptr, out_dev, 0, nrhs);
+    HIPCHK(launch_operator(o, st));
+    return HOFEM_OK;
+  }
+  if (!ws_dev || ws_bytes < pcg_bytes(S, coef)) return HOFEM_EINVAL;
+  const PcgWs w = pcg_carve(S, coef, ws_dev);
+  for (int r = 0; r < nrhs; ++r) {
+    VarOpArgs v = make_varop(S, coef, u_dev + r * S->per_rhs, nullptr, out_dev + r * S->per_rhs, 1);
+    HIPCHK(launch_varop(v, w.elem, st));
+  }
+  return HOFEM_OK;
 }
 
 int hofem_apply_operator(hofem_solver S, const double* u_dev, double* out_dev, int nrhs,

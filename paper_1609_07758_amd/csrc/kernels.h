@@ -77,4 +77,39 @@ hipError_t launch_norms(const float* delta, double* u, long long count, double* 
 // u += (double) delta, elementwise.
 hipError_t launch_axpy(const float* delta, double* u, long long count, hipStream_t s);
 
+// FP64 variable-coefficient operator out = f - L_a u (or L_a u when f is NULL).
+struct VarOpArgs {
+  const double* u;
+  const double* f;
+  double* out;
+  int N;
+  int n[3], K[3];
+  long long stride[3];   // grid strides of a right-hand side
+  long long per_rhs;
+  int nrhs;
+  double scale[3];       // 4 h_i^-2
+  double alpha;
+  const double* B[3];    // e_r(x_q), (n+1)^2
+  const double* D[3];    // e_r'(x_q), (n+1)^2
+  const double* w[3];    // Gauss weights, n+1
+  int kind;              // 0: a = 1, 1: a = c0 + c1 prod_i t_i, 2: a at every Gauss point
+  double c0, c1;
+  const double* t[3];    // kind 1: t_i at [element][q], K_i (n_i+1) values
+  const double* afull;   // kind 2: [element][q_0..q_{N-1}]
+};
+size_t varop_elem_bytes(const VarOpArgs& a);
+hipError_t launch_varop(const VarOpArgs& a, double* elem_buf, hipStream_t s);
+
+// PCG vector kernels (np partial sums, reduced in a fixed order).
+hipError_t launch_dot2(const double* x, const double* y, const double* z, long long n,
+                       double* partial, int np, double* out2, hipStream_t s);
+hipError_t launch_cg_update(double* x, double* r, const double* p, const double* q, long long n,
+                            const double* scal, double* partial, int np, double* out2,
+                            hipStream_t s);
+hipError_t launch_cg_dir(double* p, const double* z, long long n, const double* scal,
+                         hipStream_t s);
+// scal[0] = scal[2] / scal[3] (op 0: alpha = rz / pq);
+// scal[1] = scal[5] / scal[2], scal[2] = scal[5] (op 1: beta, rz <- rz_new)
+hipError_t launch_scalar_op(double* scal, int op, hipStream_t s);
+
 }  // namespace hofem

@@ -1,0 +1,392 @@
+// Preconditioned conjugate gradients (FP64 vectors) and the FP64
+// variable-coefficient operator -div(a grad u) + alpha u in the scaled form
+// of eq. (bvp glob 2): sum_i 4 h_i^-2 int_sigma a d_i u d_i phi + alpha int u phi,
+// integrated with the (n+1)-point Gauss rule per axis and element.
+//
+// The paper names the fast solver's use as a preconditioner for general
+// second-order elliptic equations (Section 1); the preconditioner here is the
+// FP32 fast solve of the constant-coefficient operator.
+
+#include <algorithm>
+
+#include "kernels.h"
+
+namespace hofem {
+namespace {
+
+// ---- deterministic reductions ----------------------------------------------
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Workgroup sum of v (256 threads); result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum_d(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) s = sh[0] + sh[1] + sh[2] + sh[3];
+  __syncthreads();
+  return s;
+}
+
+// partial[2b] = sum x * y, partial[2b+1] = sum x * z (0 when z is null)
+__global__ __launch_bounds__(256) void dot2_kernel(const double* __restrict__ x,
+                                                   const double* __restrict__ y,
+                                                   const double* __restrict__ z, long long n,
+                                                   double* partial) {
+  __shared__ double sh[4];
+  double a0 = 0.0, a1 = 0.0;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (long long)gridDim.x * 256) {
+    a0 += x[i] * y[i];
+    if (z) a1 += x[i] * z[i];
+  }
+  a0 = block_sum(a0, sh);
+  a1 = block_sum(a1, sh);
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = a0;
+    partial[2 * blockIdx.x + 1] = a1;
+  }
+}
+
+// x += alpha p, r -= alpha q; partial sums of r^2 and x^2 (alpha from device)
+__global__ __launch_bounds__(256) void cg_update_kernel(double* __restrict__ x,
+                                                        double* __restrict__ r,
+                                                        const double* __restrict__ p,
+                                                        const double* __restrict__ q, long long n,
+                                                        const double* scal, double* partial) {
+  __shared__ double sh[4];
+  const double alpha = scal[0];
+  double a0 = 0.0, a1 = 0.0;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (long long)gridDim.x * 256) {
+    const double xi = x[i] + alpha * p[i];
+    x[i] = xi;
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    a0 += ri * ri;
+    a1 += xi * xi;
+  }
+  a0 = block_sum(a0, sh);
+  a1 = block_sum(a1, sh);
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = a0;
+    partial[2 * blockIdx.x + 1] = a1;
+  }
+}
+
+__global__ void scalar_op_kernel(double* scal, int op) {
+  if (op == 0) {
+    scal[0] = scal[2] / scal[3];
+  } else {
+    // beta = r_new (z_new - z_old) / (r_old z_old): the flexible form, which
+    // tolerates a preconditioner that is symmetric only up to FP32 rounding
+    scal[1] = (scal[5] - scal[10]) / scal[2];
+    scal[2] = scal[5];
+  }
+}
+
+// p = z + beta p (beta read from device)
+__global__ __launch_bounds__(256) void cg_dir_kernel(double* __restrict__ p,
+                                                     const double* __restrict__ z, long long n,
+                                                     const double* scal) {
+  const double beta = scal[1];
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (long long)gridDim.x * 256)
+    p[i] = z[i] + beta * p[i];
+}
+
+// out[0..1] = sums of the interleaved pairs partial[0..2 np) in a fixed order
+__global__ void sum2_kernel(const double* partial, int np, double* out) {
+  __shared__ double s0[256], s1[256];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < np; i += 256) {
+    a += partial[2 * i];
+    b += partial[2 * i + 1];
+  }
+  s0[threadIdx.x] = a;
+  s1[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      s0[threadIdx.x] += s0[threadIdx.x + w];
+      s1[threadIdx.x] += s1[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = s0[0];
+    out[1] = s1[0];
+  }
+}
+
+// ---- variable-coefficient operator ------------------------------------------
+
+// One workgroup per element.  The element's (n+1)^N nodal values and all 1D
+// tables sit in LDS; every 1D factor is applied by one thread per entry.
+template <int N>
+__global__ __launch_bounds__(1024) void varop_element_kernel(VarOpArgs a, double* elem_out) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  int b[3], K[3], st[3];
+  long long el = blockIdx.x;
+  const long long rhs_el = blockIdx.y;
+  int e[3];
+  int npts = 1;
+  for (int i = N - 1; i >= 0; --i) {
+    b[i] = a.n[i] + 1;
+    K[i] = a.K[i];
+    e[i] = (int)(el % K[i]);   // 0-based element index along axis i
+    el /= K[i];
+  }
+  for (int i = N - 1; i >= 0; --i) {
+    st[i] = npts;
+    npts *= b[i];
+  }
+  double* U = reinterpret_cast<double*>(smem);   // [npts]
+  double* T0 = U + npts;
+  double* T1 = T0 + npts;
+  double* OUT = T1 + npts;
+  double* tab = OUT + npts;                        // per axis: B (b^2), D (b^2), w (b)
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  int toff[3];
+  {
+    int off = 0;
+    for (int i = 0; i < N; ++i) {
+      toff[i] = off;
+      off += 2 * b[i] * b[i] + b[i];
+    }
+  }
+  for (int i = 0; i < N; ++i) {
+    const int bb = b[i] * b[i];
+    for (int t = tid; t < bb; t += nthr) {
+      tab[toff[i] + t] = a.B[i][t];
+      tab[toff[i] + bb + t] = a.D[i][t];
+    }
+    for (int t = tid; t < b[i]; t += nthr) tab[toff[i] + 2 * bb + t] = a.w[i][t];
+  }
+  // nodal values (zero on the Dirichlet boundary)
+  const double* __restrict__ u = a.u + rhs_el * a.per_rhs;
+  for (int t = tid; t < npts; t += nthr) {
+    long long idx = 0;
+    bool inside = true;
+    for (int i = 0; i < N; ++i) {
+      const int r = (t / st[i]) % b[i];
+      const int g = a.n[i] * e[i] + r;   // position 0 .. n K
+      if (g <= 0 || g >= a.n[i] * K[i]) inside = false;
+      idx += (long long)(g - 1) * a.stride[i];
+    }
+    U[t] = inside ? u[idx] : 0.0;
+    OUT[t] = 0.0;
+  }
+  __syncthreads();
+
+  // apply along axis i: dst[..q..] = sum_r M[q b + r] src[..r..]; transposed
+  // variant uses M[r b + q]; difference variant subtracts src at r = 0.
+  auto apply = [&](const double* src, double* dst, int i, const double* M, bool transpose,
+                   bool difference) {
+    for (int t = tid; t < npts; t += nthr) {
+      const int q = (t / st[i]) % b[i];
+      const int base = t - q * st[i];
+      const double ref = difference ? src[base] : 0.0;
+      double s = 0.0;
+      for (int r = 0; r < b[i]; ++r) {
+        const double m = transpose ? M[r * b[i] + q] : M[q * b[i] + r];
+        s += m * (src[base + r * st[i]] - ref);
+      }
+      dst[t] = s;
+    }
+    __syncthreads();
+  };
+
+  // quadrature weight times coefficient at every Gauss point of the element
+  auto weight = [&](int t) -> double {
+    double wq = 1.0, prod = 1.0;
+    long long aidx = 0;
+    for (int i = 0; i < N; ++i) {
+      const int q = (t / st[i]) % b[i];
+      wq *= tab[toff[i] + 2 * b[i] * b[i] + q];
+      if (a.kind == 1) prod *= a.t[i][(size_t)e[i] * b[i] + q];
+      aidx = aidx * K[i] + e[i];
+    }
+    double coef = 1.0;
+    if (a.kind == 1) coef = a.c0 + a.c1 * prod;
+    else if (a.kind == 2) coef = a.afull[aidx * npts + t];
+    return wq * coef;
+  };
+
+  for (int term = 0; term < N; ++term) {
+    // stiffness factor first, in difference form, then the basis values along the others
+    const double* src = U;
+    double* bufs[2] = {T0, T1};
+    int cur = 0;
+    apply(src, bufs[cur], term, tab + toff[term] + b[term] * b[term], false, true);
+    for (int i = 0; i < N; ++i) {
+      if (i == term) continue;
+      apply(bufs[cur], bufs[cur ^ 1], i, tab + toff[i], false, false);
+      cur ^= 1;
+    }
+    for (int t = tid; t < npts; t += nthr) bufs[cur][t] *= a.scale[term] * weight(t);
+    __syncthreads();
+    for (int i = N - 1; i >= 0; --i) {
+      if (i == term) continue;
+      apply(bufs[cur], bufs[cur ^ 1], i, tab + toff[i], true, false);
+      cur ^= 1;
+    }
+    apply(bufs[cur], bufs[cur ^ 1], term, tab + toff[term] + b[term] * b[term], true, false);
+    cur ^= 1;
+    for (int t = tid; t < npts; t += nthr) OUT[t] += bufs[cur][t];
+    __syncthreads();
+  }
+  if (a.alpha != 0.0) {
+    double* bufs[2] = {T0, T1};
+    int cur = 0;
+    apply(U, bufs[cur], 0, tab + toff[0], false, false);
+    for (int i = 1; i < N; ++i) {
+      apply(bufs[cur], bufs[cur ^ 1], i, tab + toff[i], false, false);
+      cur ^= 1;
+    }
+    for (int t = tid; t < npts; t += nthr) {
+      double wq = 1.0;
+      for (int i = 0; i < N; ++i) wq *= tab[toff[i] + 2 * b[i] * b[i] + (t / st[i]) % b[i]];
+      bufs[cur][t] *= a.alpha * wq;
+    }
+    __syncthreads();
+    for (int i = N - 1; i >= 0; --i) {
+      apply(bufs[cur], bufs[cur ^ 1], i, tab + toff[i], true, false);
+      cur ^= 1;
+    }
+    for (int t = tid; t < npts; t += nthr) OUT[t] += bufs[cur][t];
+    __syncthreads();
+  }
+  double* dst = elem_out + ((long long)rhs_el * gridDim.x + blockIdx.x) * npts;
+  for (int t = tid; t < npts; t += nthr) dst[t] = OUT[t];
+}
+
+// Per grid point: sum of the element contributions of the 1..2^N elements
+// holding it; out = f - sum (residual) or sum.
+template <int N>
+__global__ __launch_bounds__(256) void varop_gather_kernel(VarOpArgs a, const double* elem_out,
+                                                           long long total) {
+  const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= total) return;
+  const long long rhs = idx / a.per_rhs;
+  long long rem = idx - rhs * a.per_rhs;
+  int ne[3] = {1, 1, 1}, el[3][2], rl[3][2], b[3];
+  long long nel = 1;
+  int npts = 1;
+  for (int i = 0; i < N; ++i) {
+    b[i] = a.n[i] + 1;
+    nel *= a.K[i];
+    npts *= b[i];
+    const int q = (int)(rem / a.stride[i]);
+    rem -= (long long)q * a.stride[i];
+    const int g = q + 1, ni = a.n[i];
+    if (g % ni == 0) {
+      ne[i] = 2;
+      el[i][0] = g / ni - 1; rl[i][0] = ni;
+      el[i][1] = g / ni;     rl[i][1] = 0;
+    } else {
+      el[i][0] = g / ni; rl[i][0] = g % ni;
+    }
+  }
+  double acc = 0.0;
+  for (int c0 = 0; c0 < ne[0]; ++c0)
+    for (int c1 = 0; c1 < (N > 1 ? ne[1] : 1); ++c1)
+      for (int c2 = 0; c2 < (N > 2 ? ne[2] : 1); ++c2) {
+        const int cs[3] = {c0, c1, c2};
+        long long e = 0;
+        int loc = 0;
+        for (int i = 0; i < N; ++i) {
+          e = e * a.K[i] + el[i][cs[i]];
+          loc = loc * b[i] + rl[i][cs[i]];
+        }
+        acc += elem_out[((long long)rhs * nel + e) * npts + loc];
+      }
+  const double res = a.f ? a.f[idx] - acc : acc;
+  a.out[idx] = res;
+}
+
+}  // namespace
+
+size_t varop_elem_bytes(const VarOpArgs& a) {
+  long long nel = 1, npts = 1;
+  for (int i = 0; i < a.N; ++i) {
+    nel *= a.K[i];
+    npts *= a.n[i] + 1;
+  }
+  return (size_t)(nel * npts * a.nrhs) * sizeof(double);
+}
+
+hipError_t launch_varop(const VarOpArgs& a, double* elem_buf, hipStream_t s) {
+  long long nel = 1;
+  int npts = 1, tabs = 0;
+  for (int i = 0; i < a.N; ++i) {
+    nel *= a.K[i];
+    npts *= a.n[i] + 1;
+    tabs += 2 * (a.n[i] + 1) * (a.n[i] + 1) + (a.n[i] + 1);
+  }
+  const int threads = std::min(1024, ((npts + 63) / 64) * 64);
+  const size_t lds = (size_t)(4 * npts + tabs) * sizeof(double);
+  const dim3 grid((unsigned)nel, (unsigned)a.nrhs);
+  long long total = a.per_rhs * a.nrhs;
+  const unsigned gb = (unsigned)((total + 255) / 256);
+  switch (a.N) {
+    case 1:
+      hipLaunchKernelGGL(varop_element_kernel<1>, grid, dim3(threads), lds, s, a, elem_buf);
+      hipLaunchKernelGGL(varop_gather_kernel<1>, dim3(gb), dim3(256), 0, s, a, elem_buf, total);
+      break;
+    case 2:
+      hipLaunchKernelGGL(varop_element_kernel<2>, grid, dim3(threads), lds, s, a, elem_buf);
+      hipLaunchKernelGGL(varop_gather_kernel<2>, dim3(gb), dim3(256), 0, s, a, elem_buf, total);
+      break;
+    case 3: {
+      static bool raised = false;
+      if (!raised) {
+        hipError_t e = hipFuncSetAttribute((const void*)varop_element_kernel<3>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        raised = true;
+      }
+      hipLaunchKernelGGL(varop_element_kernel<3>, grid, dim3(threads), lds, s, a, elem_buf);
+      hipLaunchKernelGGL(varop_gather_kernel<3>, dim3(gb), dim3(256), 0, s, a, elem_buf, total);
+      break;
+    }
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_dot2(const double* x, const double* y, const double* z, long long n,
+                       double* partial, int np, double* out2, hipStream_t s) {
+  hipLaunchKernelGGL(dot2_kernel, dim3(np), dim3(256), 0, s, x, y, z, n, partial);
+  hipLaunchKernelGGL(sum2_kernel, dim3(1), dim3(256), 0, s, partial, np, out2);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_update(double* x, double* r, const double* p, const double* q, long long n,
+                            const double* scal, double* partial, int np, double* out2,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(cg_update_kernel, dim3(np), dim3(256), 0, s, x, r, p, q, n, scal, partial);
+  hipLaunchKernelGGL(sum2_kernel, dim3(1), dim3(256), 0, s, partial, np, out2);
+  return hipGetLastError();
+}
+
+hipError_t launch_scalar_op(double* scal, int op, hipStream_t s) {
+  hipLaunchKernelGGL(scalar_op_kernel, dim3(1), dim3(1), 0, s, scal, op);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_dir(double* p, const double* z, long long n, const double* scal,
+                         hipStream_t s) {
+  long long blocks = std::min<long long>(4096, (n + 255) / 256);
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(cg_dir_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, z, n, scal);
+  return hipGetLastError();
+}
+
+}  // namespace hofem

@@ -60,20 +60,24 @@ void gauss_legendre(int npts, std::vector<q128>& x, std::vector<q128>& w) {
       if (qabs(dz) < 1e-34Q) break;
     }
     legendre(npts, z, p, dp);
-    x[i] = z;
-    w[i] = 2 / ((1 - z * z) * dp * dp);
+    // the initial guesses decrease with i: store in ascending order
+    x[npts - 1 - i] = z;
+    w[npts - 1 - i] = 2 / ((1 - z * z) * dp * dp);
   }
 }
 
-// Local matrices of the order-n Lagrange element on [-1, 1].
-void local_matrices(int n, std::vector<q128>& A, std::vector<q128>& C) {
+// Local matrices of the order-n Lagrange element on [-1, 1]; also returns the
+// Gauss rule and the basis values / derivatives at its nodes.
+void local_matrices(int n, std::vector<q128>& A, std::vector<q128>& C, std::vector<q128>& gx,
+                    std::vector<q128>& gw, std::vector<q128>& Bq, std::vector<q128>& Dq) {
   const int nb = n + 1;
   std::vector<q128> xi(nb);
   for (int k = 0; k <= n; ++k) xi[k] = -1 + (q128)(2 * k) / n;
-  std::vector<q128> gx, gw;
   gauss_legendre(n + 1, gx, gw);
   A.assign(nb * nb, 0);
   C.assign(nb * nb, 0);
+  Bq.assign(nb * nb, 0);
+  Dq.assign(nb * nb, 0);
   std::vector<q128> e(nb), de(nb);
   for (size_t g = 0; g < gx.size(); ++g) {
     const q128 x = gx[g];
@@ -93,11 +97,14 @@ void local_matrices(int n, std::vector<q128>& A, std::vector<q128>& C) {
       }
       de[l] = d;
     }
-    for (int r = 0; r <= n; ++r)
+    for (int r = 0; r <= n; ++r) {
+      Bq[g * nb + r] = e[r];
+      Dq[g * nb + r] = de[r];
       for (int s = 0; s <= n; ++s) {
         A[r * nb + s] += gw[g] * de[r] * de[s];
         C[r * nb + s] += gw[g] * e[r] * e[s];
       }
+    }
   }
   // Symmetrise exactly (the quadrature is symmetric up to rounding).
   for (int r = 0; r <= n; ++r)
@@ -258,8 +265,8 @@ q128 root_in(const Secular& S, q128 th, q128 lo, q128 hi) {
 int plan1d_build(int n, int K, Plan1DData* out) {
   if (n < 1 || n > 9 || K < 2 || (K & (K - 1)) != 0 || K > 65536) return -1;
   const int nb = n + 1, d = n - 1, m = n * K - 1;
-  std::vector<q128> A, C;
-  local_matrices(n, A, C);
+  std::vector<q128> A, C, gx, gw, Bq, Dq;
+  local_matrices(n, A, C, gx, gw, Bq, Dq);
   auto Aat = [&](int r, int s) { return A[r * nb + s]; };
   auto Cat = [&](int r, int s) { return C[r * nb + s]; };
   std::vector<q128> At(d * d), Ct(d * d);
@@ -344,6 +351,18 @@ int plan1d_build(int n, int K, Plan1DData* out) {
       for (int i = 0; i < d; ++i) out->p[base * d + i] = (double)p[i];
       out->lam[n * k - 1 + l] = (double)lam;
     }
+  }
+  out->gx.assign(nb, 0);
+  out->gw.assign(nb, 0);
+  out->B.assign(nb * nb, 0);
+  out->D.assign(nb * nb, 0);
+  for (int i = 0; i < nb; ++i) {
+    out->gx[i] = (double)gx[i];
+    out->gw[i] = (double)gw[i];
+  }
+  for (int i = 0; i < nb * nb; ++i) {
+    out->B[i] = (double)Bq[i];
+    out->D[i] = (double)Dq[i];
   }
   // FFT support: twiddles exp(2 pi i t / K) and sin(pi t / K), t = 0..K-1.
   out->tw.assign(2 * K, 0);

@@ -19,6 +19,9 @@ struct Plan1DData {
   std::vector<double> lam0;      // interior eigenvalues (n-1)
   std::vector<double> tw;        // cos, sin of 2 pi t / K, t = 0..K-1 (interleaved)
   std::vector<double> sn;        // sin(pi t / K), t = 0..K-1
+  // (n+1)-point Gauss-Legendre rule on [-1, 1] and the Lagrange basis there:
+  std::vector<double> gx, gw;    // nodes, weights (n+1)
+  std::vector<double> B, D;      // B[q (n+1) + r] = e_r(x_q), D[q (n+1) + r] = e_r'(x_q)
 };
 
 // Returns 0 on success, -1 for unsupported (n, K).

@@ -87,3 +87,16 @@ def test_local_matrices_match_exact(n):
     Cf = np.array([[float(x) for x in r] for r in C]).ravel()
     assert np.allclose(p.table("A"), Af, rtol=4.5e-16, atol=1e-300)
     assert np.allclose(p.table("C"), Cf, rtol=4.5e-16, atol=1e-300)
+
+
+@pytest.mark.parametrize("n", range(1, 10))
+def test_gauss_tables_match_oracle(n):
+    # nodes increasing, weights, basis values / derivatives at the nodes
+    from oracle import varcoef
+    p = H.Plan1D(n, 4)
+    x, w = varcoef.gauss_rule(n)
+    B, D = varcoef.basis_tables(n)
+    assert np.all(np.diff(p.table("gx")) > 0)
+    # both sides round once from >= 34 digits: equal up to one rounding
+    for name, ref in (("gx", x), ("gw", w), ("B", B.ravel()), ("D", D.ravel())):
+        assert np.allclose(p.table(name), ref, rtol=2.3e-16, atol=1e-30), name

@@ -6,6 +6,9 @@ Configurations (per axis: order n, elements K, box length X):
   small_2d    N=2, n=2, K=16, X=(1,1), alpha=0          (31^2 = 961 unknowns)
   large_2d    N=2, n=9, K=1024, X=(1,1), alpha=0        (9215^2 = 84,916,225 unknowns)
   cube_3d     N=3, n=4, K=128, X=(1,1,1), alpha=0       (511^3 = 133,432,831 unknowns)
+  varcoef_3d  N=3, n=3, K=64, X=(1,1,1), alpha=0        (191^3 = 6,967,871 unknowns) with
+              a(x) = 1 + 0.5 prod_i sin(2 pi k_i x_i), k_i uniform on {1, 2, 3} from the
+              seed (variable-coefficient problem -div(a grad u) = f)
 Right-hand sides of the random kind are i.i.d. uniform[-1, 1) values of f^h
 drawn in C order with numpy's default generator (PCG64) from the seed.
 """
@@ -15,6 +18,7 @@ CONFIGS = {
     "small_2d": dict(orders=(2, 2), Ks=(16, 16), X=(1.0, 1.0), alpha=0.0),
     "large_2d": dict(orders=(9, 9), Ks=(1024, 1024), X=(1.0, 1.0), alpha=0.0),
     "cube_3d": dict(orders=(4, 4, 4), Ks=(128, 128, 128), X=(1.0, 1.0, 1.0), alpha=0.0),
+    "varcoef_3d": dict(orders=(3, 3, 3), Ks=(64, 64, 64), X=(1.0, 1.0, 1.0), alpha=0.0),
 }
 
 
@@ -30,3 +34,14 @@ def uniform_rhs(shp, seed=0, dtype=np.float64):
 def normal_noise(shp, sigma, seed=0):
     """i.i.d. N(0, sigma^2) entries (sigma is the standard deviation)."""
     return np.random.default_rng(seed).normal(0.0, sigma, shp)
+
+
+def wavenumbers(N, seed=0):
+    """k_i uniform on {1, 2, 3} (i = 0..N-1) from the seed."""
+    return tuple(int(k) for k in np.random.default_rng(seed).integers(1, 4, N))
+
+
+def sine_coefficient(ks):
+    """(c0, c1, [t_i]) of a(x) = c0 + c1 prod_i t_i(x_i) with
+    t_i(x) = sin(2 pi k_i x)."""
+    return 1.0, 0.5, [(lambda x, k=k: np.sin(2.0 * np.pi * k * x)) for k in ks]
