@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 
 def kernel_sha():
     h = hashlib.sha256()
-    for name in ("kernels.hip", "capi.hip"):
+    for name in ("linepass.h", "linepass.hip", "linepass_dispatch.hip", "capi.hip"):
         with open(os.path.join(ROOT, "paper_1609_07758_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

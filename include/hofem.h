@@ -121,8 +121,9 @@ int hofem_plan1d_dim(hofem_plan1d plan, int* m);
  *   8  basis values e_r(x_q) at index q (n+1) + r         ((n+1)^2 values)
  *   9  basis derivatives e_r'(x_q) at index q (n+1) + r   ((n+1)^2 values)
  * The coefficient index of a line is q = l-1 for k = 0 (l = 1..n-1) and
- * q = n k - 1 + l-1 for k = 1..K-1 (l = 1..n).  `len` must equal the count;
- * otherwise HOFEM_EINVAL. */
+ * q = (n-1) + (l-1)(K-1) + (k-1) for k = 1..K-1 (l = 1..n): for each l the
+ * wave numbers are consecutive.  `len` must equal the count; otherwise
+ * HOFEM_EINVAL. */
 int hofem_plan1d_table(hofem_plan1d plan, int which, double* out_host, size_t len);
 
 /* ---- N-D solver (device) ---------------------------------------------- */

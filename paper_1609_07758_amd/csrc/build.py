@@ -3,6 +3,7 @@ precompute.  Usage: ``python paper_1609_07758_amd/csrc/build.py`` (or build()).
 
 Every invocation recompiles all sources (a few tens of seconds).
 """
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -29,16 +30,29 @@ def _run(cmd):
     subprocess.run(cmd, check=True)
 
 
-def build(verbose=True):
-    os.makedirs(OUT_DIR, exist_ok=True)
-    objs = []
+def _jobs():
+    """(command, object) for every translation unit; the line passes are
+    compiled once per element order."""
+    jobs = []
     o = os.path.join(OUT_DIR, "plan1d.o")
-    _run(["g++"] + CXX_FLAGS + ["-c", os.path.join(CSRC, "plan1d.cpp"), "-o", o])
-    objs.append(o)
-    for src in ("kernels.hip", "operator.hip", "pcg.hip", "capi.hip"):
+    jobs.append((["g++"] + CXX_FLAGS + ["-c", os.path.join(CSRC, "plan1d.cpp"), "-o", o], o))
+    for n in range(1, 10):
+        o = os.path.join(OUT_DIR, f"linepass_{n}.o")
+        jobs.append(([HIPCC] + HIP_FLAGS + [f"-DHOFEM_ORDER={n}", "-c",
+                                            os.path.join(CSRC, "linepass.hip"), "-o", o], o))
+    for src in ("linepass_dispatch.hip", "operator.hip", "pcg.hip", "capi.hip"):
         o = os.path.join(OUT_DIR, src.replace(".hip", ".o"))
-        _run([HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", o])
-        objs.append(o)
+        jobs.append(([HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", o], o))
+    return jobs
+
+
+def build(verbose=True, jobs=None):
+    os.makedirs(OUT_DIR, exist_ok=True)
+    todo = _jobs()
+    workers = jobs or max(1, min(len(todo), os.cpu_count() or 1))
+    with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as ex:
+        list(ex.map(lambda job: _run(job[0]), todo))
+    objs = [o for _, o in todo]
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs + ["-lquadmath"])
     os.replace(tmp, LIB)

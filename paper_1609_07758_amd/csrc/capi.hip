@@ -464,7 +464,7 @@ int hofem_solver_create(int N, const hofem_plan1d* plans, const double* X, doubl
   }
   Packer pk;
   struct Off {
-    size_t lam, lamk, p64, in64, E64, tw64, sn64, p32, in32, E32, tw32, sn32, A, C, B, D, gw;
+    size_t lam, blk64, E64, tw64, sn64, blk32, E32, tw32, sn32, A, C, B, D, gw;
   } off[3];
   for (int i = 0; i < N; ++i) {
     const Plan1DData& d = plans[i]->d;
@@ -476,27 +476,25 @@ int hofem_solver_create(int N, const hofem_plan1d* plans, const double* X, doubl
     const double h = X[i] / d.K;
     ax.scale = 4.0 / (h * h);
     S->per_rhs *= (size_t)d.m;
-    // k-fastest copies of the per-wave-number tables for the device
+    // per-wave-number tables blocked by 64 wave numbers (layout in kernels.h)
     const int n = d.n, K = d.K;
-    std::vector<double> pT((size_t)(K - 1) * n * std::max(n - 1, 1), 0.0),
-        inT((size_t)(K - 1) * n), lamT((size_t)(K - 1) * n);
-    for (int k = 1; k < K; ++k)
+    const size_t NE = (size_t)n * (n - 1) + n, nblk = ((size_t)K - 1 + 63) / 64;
+    std::vector<double> blk(nblk * NE * 64, 0.0);
+    for (int k = 1; k < K; ++k) {
+      const size_t b = (size_t)(k - 1) / 64, o = (size_t)(k - 1) % 64;
       for (int l = 0; l < n; ++l) {
-        inT[(size_t)l * (K - 1) + k - 1] = d.inorm[(size_t)(k - 1) * n + l];
-        lamT[(size_t)l * (K - 1) + k - 1] = d.lam[(size_t)n * k - 1 + l];
         for (int c = 0; c < n - 1; ++c)
-          pT[((size_t)l * (n - 1) + c) * (K - 1) + k - 1] =
+          blk[(b * NE + (size_t)l * (n - 1) + c) * 64 + o] =
               d.p[((size_t)(k - 1) * n + l) * (n - 1) + c];
+        blk[(b * NE + (size_t)n * (n - 1) + l) * 64 + o] = d.inorm[(size_t)(k - 1) * n + l];
       }
+    }
     off[i].lam = pk.add_f64(d.lam);
-    off[i].lamk = pk.add_f64(lamT);
-    off[i].p64 = pk.add_f64(pT);
-    off[i].in64 = pk.add_f64(inT);
+    off[i].blk64 = pk.add_f64(blk);
     off[i].E64 = pk.add_f64(d.E);
     off[i].tw64 = pk.add_f64(d.tw);
     off[i].sn64 = pk.add_f64(d.sn);
-    off[i].p32 = pk.add_f32(pT);
-    off[i].in32 = pk.add_f32(inT);
+    off[i].blk32 = pk.add_f32(blk);
     off[i].E32 = pk.add_f32(d.E);
     off[i].tw32 = pk.add_f32(d.tw);
     off[i].sn32 = pk.add_f32(d.sn);
@@ -523,11 +521,10 @@ int hofem_solver_create(int N, const hofem_plan1d* plans, const double* X, doubl
   for (int i = 0; i < N; ++i) {
     DevAxis& ax = S->ax[i];
     const double* lam = reinterpret_cast<const double*>(b + off[i].lam);
-    const double* lamk = reinterpret_cast<const double*>(b + off[i].lamk);
-    ax.t64 = AxisTab{b + off[i].p64, b + off[i].in64, b + off[i].E64, b + off[i].tw64,
-                     b + off[i].sn64, lam, lamk, ax.n, ax.K, ax.m};
-    ax.t32 = AxisTab{b + off[i].p32, b + off[i].in32, b + off[i].E32, b + off[i].tw32,
-                     b + off[i].sn32, lam, lamk, ax.n, ax.K, ax.m};
+    ax.t64 = AxisTab{b + off[i].blk64, b + off[i].E64, b + off[i].tw64, b + off[i].sn64, lam,
+                     ax.n, ax.K, ax.m};
+    ax.t32 = AxisTab{b + off[i].blk32, b + off[i].E32, b + off[i].tw32, b + off[i].sn32, lam,
+                     ax.n, ax.K, ax.m};
     ax.A = reinterpret_cast<const double*>(b + off[i].A);
     ax.C = reinterpret_cast<const double*>(b + off[i].C);
     ax.B = reinterpret_cast<const double*>(b + off[i].B);

@@ -6,17 +6,23 @@
 
 namespace hofem {
 
-// Device tables of one axis in one precision (T = float or double).  The
-// per-wave-number tables are stored with k fastest so that lanes handling
-// consecutive k read consecutive addresses.
+// Device tables of one axis in one precision (T = float or double).
+//
+// Coefficient order of a line (m = nK - 1 entries): q = l-1 for the k = 0
+// modes (l = 1..n-1), q = (n-1) + (l-1)(K-1) + (k-1) for k = 1..K-1 and
+// l = 1..n, i.e. for each l the wave numbers k are consecutive.
+//
+// The per-wave-number tables are blocked by 64 wave numbers (one wavefront):
+// entry e of wave number k sits at ((k-1)/64 * NE + e) * 64 + (k-1) % 64 with
+// NE = n(n-1) + n, e = (l-1)(n-1) + (i-1) for component i of p_k^(l) and
+// e = n(n-1) + l-1 for 1 / ||s_k^(l)||^2, so that a wavefront handling 64
+// consecutive k reads 64 consecutive values per entry.
 struct AxisTab {
-  const void* p;       // component i of p_k^(l) at ((l-1) (n-1) + i) (K-1) + k-1
-  const void* inorm;   // 1 / ||s_k^(l)||^2 at (l-1) (K-1) + k-1
+  const void* blk;     // blocked p and 1/||s||^2 (T)
   const void* E;       // e^(l) columns, i (n-1) + l-1
   const void* tw;      // cos, sin (2 pi t / K) interleaved, t < K
   const void* sn;      // sin(pi t / K), t < K
   const double* lam;   // scaled eigenvalues in coefficient order (FP64)
-  const double* lamk;  // lambda_k^(l) at (l-1) (K-1) + k-1 (FP64)
   int n, K, m;
 };
 
@@ -40,6 +46,19 @@ struct PassArgs {
   long long odiv[2];
   long long omod[2];
 };
+
+// Per-order launchers, each defined in its own translation unit.
+template <int N>
+hipError_t launch_pass_order(int kind, int dt, const PassArgs& a, hipStream_t s);
+template <> hipError_t launch_pass_order<1>(int, int, const PassArgs&, hipStream_t);
+template <> hipError_t launch_pass_order<2>(int, int, const PassArgs&, hipStream_t);
+template <> hipError_t launch_pass_order<3>(int, int, const PassArgs&, hipStream_t);
+template <> hipError_t launch_pass_order<4>(int, int, const PassArgs&, hipStream_t);
+template <> hipError_t launch_pass_order<5>(int, int, const PassArgs&, hipStream_t);
+template <> hipError_t launch_pass_order<6>(int, int, const PassArgs&, hipStream_t);
+template <> hipError_t launch_pass_order<7>(int, int, const PassArgs&, hipStream_t);
+template <> hipError_t launch_pass_order<8>(int, int, const PassArgs&, hipStream_t);
+template <> hipError_t launch_pass_order<9>(int, int, const PassArgs&, hipStream_t);
 
 // Launch one pass.  dt: 0 = FP64 compute (double in/out),
 // 1 = FP32 compute with float in/out, 2 = FP32 compute, double in, float out,

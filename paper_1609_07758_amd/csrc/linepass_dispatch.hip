@@ -1,0 +1,30 @@
+// Dispatch of the line passes to the per-order kernels, and their launch
+// shape (lines per workgroup, LDS bytes).
+#include "linepass.h"
+
+namespace hofem {
+
+hipError_t launch_pass(int kind, int dt, const PassArgs& a, hipStream_t s) {
+  switch (a.tab.n) {
+    case 1: return launch_pass_order<1>(kind, dt, a, s);
+    case 2: return launch_pass_order<2>(kind, dt, a, s);
+    case 3: return launch_pass_order<3>(kind, dt, a, s);
+    case 4: return launch_pass_order<4>(kind, dt, a, s);
+    case 5: return launch_pass_order<5>(kind, dt, a, s);
+    case 6: return launch_pass_order<6>(kind, dt, a, s);
+    case 7: return launch_pass_order<7>(kind, dt, a, s);
+    case 8: return launch_pass_order<8>(kind, dt, a, s);
+    case 9: return launch_pass_order<9>(kind, dt, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+void pass_shape(int n, int K, int is_f64, long long nlines, long long inner, int* cb,
+                size_t* lds_bytes) {
+  (void)inner;
+  const lp::Shape s = lp::shape_for(n, K, is_f64 ? 16 : 8, nlines);
+  *cb = s.cb;
+  *lds_bytes = s.lds;
+}
+
+}  // namespace hofem

@@ -349,7 +349,7 @@ int plan1d_build(int n, int K, Plan1DData* out) {
       size_t base = ((size_t)(k - 1) * n + l);
       out->inorm[base] = (double)(1 / norm2);
       for (int i = 0; i < d; ++i) out->p[base * d + i] = (double)p[i];
-      out->lam[n * k - 1 + l] = (double)lam;
+      out->lam[(size_t)(n - 1) + (size_t)l * (K - 1) + (k - 1)] = (double)lam;
     }
   }
   out->gx.assign(nb, 0);

@@ -8,7 +8,7 @@ namespace hofem {
 // FP64 tables of the 1D eigen data for one (n, K), each value rounded once
 // from binary128.  Coefficient index q of a line (length m = nK - 1):
 //   k = 0, l = 1..n-1      ->  q = l - 1
-//   k = 1..K-1, l = 1..n   ->  q = n k - 1 + (l - 1)
+//   k = 1..K-1, l = 1..n   ->  q = (n - 1) + (l - 1)(K - 1) + (k - 1)
 struct Plan1DData {
   int n = 0, K = 0, m = 0;
   std::vector<double> A, C;      // local stiffness / mass on [-1,1], (n+1)^2 row major

@@ -66,7 +66,8 @@ def test_null_and_size_errors():
 def test_plan_tables_match_oracle(n, K):
     p = H.Plan1D(n, K)
     o = spectral.eigen_structured(n, K)
-    lam = np.concatenate([o["lam0"], o["lam"].ravel()])
+    # coefficient order: the k = 0 modes, then for each l the wave numbers k = 1..K-1
+    lam = np.concatenate([o["lam0"], o["lam"].T.ravel()])
     # both sides round high-precision values once: equal up to one rounding
     assert np.allclose(p.table("lam"), lam, rtol=2.3e-16, atol=0)
     if n > 1:

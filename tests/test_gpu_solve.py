@@ -131,6 +131,12 @@ def test_forward_coefficients_match_oracle_1d():
     _, Cs = assembly.assemble_1d_sparse(n, K)
     norms2 = np.einsum("ij,ij->j", Sv, Cs @ Sv)
     want = (Sv.T @ y) / norms2
+    # the oracle's columns run k-major (s_k^(1..n) for each k); the library's
+    # coefficient order runs l-major: q = n-1 + (l-1)(K-1) + (k-1) for k >= 1
+    order = np.arange(m)
+    kk, ll = np.meshgrid(np.arange(1, K), np.arange(n), indexing="ij")
+    order[(n - 1) + ll * (K - 1) + (kk - 1)] = (n - 1) + n * (kk - 1) + ll
+    want = want[order]
     assert np.max(np.abs(got - want)) < 1e-13 * np.abs(want).max()
 
 
