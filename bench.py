@@ -1,21 +1,31 @@
 #!/usr/bin/env python3
 """Throughput of the fast direct high-order FEM solve on one MI355X.
 
-Workload large_2d: -Lap u = f on [0,1]^2 with Dirichlet data, Lagrange order
-n = 9, K = 1024 elements per axis, (9*1024-1)^2 = 84,916,225 unknowns, f^h
-i.i.d. uniform[-1,1) (seed 0), resident in HBM before timing starts.
+Headline workload large_2d: -Lap u = f on [0,1]^2 with Dirichlet data,
+Lagrange order n = 9, K = 1024 elements per axis, (9*1024-1)^2 = 84,916,225
+unknowns, f^h i.i.d. uniform[-1,1) (seed 0), resident in HBM before timing
+starts.  A step is one whole solve (every pass of algorithm (a)).  `value`
+is the FP64 solve's unknowns/s.
 
-A step is one whole solve (every pass of algorithm (a)).  `value` is the
-FP64 solve's unknowns/s; the FP32-transform solve with FP64 iterative
-refinement (3 steps by default) and the unrefined FP32 solve are timed the
-same way and reported beside it, with their relative l2 distance to the FP64
-solution.  Per-pass durations come from HIP events the library records
-around each kernel on the stream it runs on; `roofline` reports the pass
-that takes most time.  `cpu_baseline` times the CPU oracle (dense
-eigenvector products along both axes) on the host and, since it produces the
-exact solution, also yields the FP64 parity figure of the run.
+Beside it, on the same input: the FP32-transform solve with FP64
+refinement (fixed step count, no host synchronisation), the FP32-
+preconditioned conjugate-gradient form (FP64 residuals, stops on a relative
+update of 1e-13), the unrefined FP32 solve, and their relative l2 distances
+to the FP64 solution.  Per-pass durations come from HIP events the library
+records around each kernel on the stream it runs on; `roofline` reports the
+pass that takes most time.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Further workloads (one entry each under other_workloads):
+  batch_2d    256 independent 2D problems (K in {32..256}, n in {2..6}, 4 RHS
+              each), one batched call replayed from a HIP graph;
+  cube_3d     3D n = 4, K = 128 (511^3 unknowns), manufactured f plus noise;
+  varcoef_3d  -div(a grad u) = f, 3D n = 3, K = 64, PCG to 1e-10.
+
+`cpu_baseline` times the CPU oracle (dense eigenvector products along both
+axes) on the host for the whole large_2d right-hand side; since it is exact
+it also yields the FP64 parity figure of the run.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--only NAMES]
 """
 import argparse
 import hashlib
@@ -29,11 +39,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+KERNEL_SOURCES = ("linepass.h", "linepass.hip", "linepass_dispatch.hip", "capi.hip")
 
 
 def kernel_sha():
     h = hashlib.sha256()
-    for name in ("linepass.h", "linepass.hip", "linepass_dispatch.hip", "capi.hip"):
+    for name in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_1609_07758_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -54,21 +65,26 @@ def measured_traffic(workload, kind):
     return None if entry is None else entry.get("hbm_bytes_per_launch")
 
 
-def time_solves(torch, solve, steps, warmup):
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_calls(torch, fn, steps, warmup, stream=None):
+    """Mean milliseconds per call of fn, HIP events on the current stream."""
     for _ in range(warmup):
-        solve()
+        fn()
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
-    start.record()
+    start.record(stream)
     for _ in range(steps):
-        solve()
-    stop.record()
+        fn()
+    stop.record(stream)
     torch.cuda.synchronize()
     return start.elapsed_time(stop) / steps
 
 
-def cpu_baseline(cfg, f_host, u_gpu64, u_ir):
+def cpu_baseline(cfg, f_host, u_gpu64, others):
     """Time the oracle's dense solve on the host; return the record and the
     parity of the GPU solutions against it."""
     import numpy as np
@@ -89,13 +105,215 @@ def cpu_baseline(cfg, f_host, u_gpu64, u_ir):
     except Exception:
         threads = cores
     nref = np.linalg.norm(ref)
-    par64 = float(np.linalg.norm(u_gpu64 - ref) / nref)
-    parir = float(np.linalg.norm(u_ir - ref) / nref)
+    parity = {"fp64_rel_l2": float(np.linalg.norm(u_gpu64 - ref) / nref)}
+    for name, u in others.items():
+        parity[name + "_rel_l2"] = float(np.linalg.norm(u - ref) / nref)
     rec = {"value": M / t_apply, "unit": "unknowns/s", "cores": int(threads), "kind": "oracle",
-           "sample": f"whole {cfg['name']} right-hand side through the oracle's dense "
-                     f"eigenvector products (FP64, {t_apply:.1f} s); eigen data and dense V "
+           "sample": f"whole {cfg['name']} right-hand side ({M} unknowns) through the oracle's "
+                     f"dense eigenvector products (FP64, {t_apply:.1f} s); eigen data and dense V "
                      f"construction timed apart: {t_setup:.1f} s"}
-    return rec, par64, parir
+    return rec, parity
+
+
+def bench_headline(args, torch, H, np, workloads, dev):
+    cfg = dict(workloads.CONFIGS["large_2d"])
+    cfg["name"] = "large_2d"
+    shp = workloads.shape(cfg["orders"], cfg["Ks"])
+    M = int(np.prod(shp))
+    f_host = workloads.uniform_rhs(shp, seed=0)
+    f64 = torch.from_numpy(f_host).to(dev)
+    f32 = f64.float()
+    S = H.Solver(cfg["orders"], cfg["Ks"], cfg["X"], cfg["alpha"])
+    u64 = torch.empty_like(f64)
+    uir = torch.empty_like(f64)
+    upcg = torch.empty_like(f64)
+    u32 = torch.empty_like(f32)
+    ws_ir = S.workspace("fp32_ir")
+    ws_pcg = S.workspace("fp32_pcg")
+    torch.cuda.synchronize()
+    log("large_2d: FP64")
+
+    # FP64 solve (the headline figure), with per-pass event timing.
+    S.set_timing(True)
+    for _ in range(args.warmup):
+        S.solve(f64, u64, mode="fp64")
+    S.pass_times()
+    ms64 = time_calls(torch, lambda: S.solve(f64, u64, mode="fp64"), args.steps, 0)
+    passes64 = S.pass_times()
+    S.set_timing(False)
+
+    log("large_2d: FP32 + refinement")
+    S.set_timing(True)
+    ms_ir = time_calls(torch, lambda: S.solve(f64, uir, mode="fp32_ir", ws=ws_ir,
+                                              max_iter=args.ir_iters, tol=0.0),
+                       args.steps, args.warmup)
+    passes_ir = S.pass_times()
+    S.set_timing(False)
+    ms32 = time_calls(torch, lambda: S.solve(f32, u32, mode="fp32"), args.steps, args.warmup)
+
+    log("large_2d: FP32-preconditioned CG")
+    pcg_info = {}
+
+    def pcg():
+        _, info, _ = S.solve(f64, upcg, mode="fp32_pcg", ws=ws_pcg, max_iter=30, tol=1e-13,
+                             want_info=True, raise_noconv=False)
+        pcg_info["it"] = info.iterations
+        pcg_info["upd"] = info.rel_update
+        pcg_info["res"] = info.rel_residual
+    ms_pcg = time_calls(torch, pcg, max(1, args.steps // 4), 1)
+
+    nrm = torch.linalg.vector_norm(u64)
+    dist = lambda u: float(torch.linalg.vector_norm(u.double() - u64) / nrm)
+    hist = []
+    tmp = torch.empty_like(f64)
+    for it in range(0, 6):
+        S.solve(f64, tmp, mode="fp32_ir", ws=ws_ir, max_iter=it, tol=0.0)
+        hist.append(dist(tmp))
+    torch.cuda.synchronize()
+
+    dom = max(passes64, key=lambda p: p["ms"])
+    avg_ms = dom["ms"] / dom["launches"]
+    achieved = dom["bytes"] / (avg_ms * 1e-3) / 1e9
+    kind = f"{dom['kind']}_axis{dom['axis']}_fp64"
+    traffic = measured_traffic("large_2d", kind)
+    rec = {
+        "value": M / (ms64 * 1e-3),
+        "ms_per_step": ms64,
+        "config": {"workload": "large_2d", "N": 2, "order_n": cfg["orders"][0],
+                   "K_per_axis": cfg["Ks"][0], "unknowns": M, "rhs": "uniform[-1,1) seed 0",
+                   "alpha": cfg["alpha"]},
+        "fp32_refined": {"unknowns_per_s": M / (ms_ir * 1e-3), "ms_per_step": ms_ir,
+                         "refinement_steps": args.ir_iters, "speedup_vs_fp64": ms64 / ms_ir,
+                         "rel_l2_vs_fp64_gpu": dist(uir),
+                         "rel_l2_vs_fp64_gpu_by_steps": hist},
+        "fp32_pcg": {"unknowns_per_s": M / (ms_pcg * 1e-3), "ms_per_solve": ms_pcg,
+                     "iterations": pcg_info.get("it"), "rel_update": pcg_info.get("upd"),
+                     "rel_residual": pcg_info.get("res"), "speedup_vs_fp64": ms64 / ms_pcg,
+                     "rel_l2_vs_fp64_gpu": dist(upcg)},
+        "fp32_unrefined": {"unknowns_per_s": M / (ms32 * 1e-3), "ms_per_step": ms32,
+                           "rel_l2_vs_fp64_gpu": dist(u32)},
+        "passes_fp64": [dict(p, avg_ms=p["ms"] / p["launches"],
+                             gbs=p["bytes"] / (p["ms"] / p["launches"] * 1e-3) / 1e9)
+                        for p in passes64],
+        "passes_fp32_refined": [dict(p, avg_ms=p["ms"] / p["launches"]) for p in passes_ir],
+        "roofline": {"bound": "hbm", "kernel": kind, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": dom["bytes"], "avg_launch_ms": avg_ms},
+    }
+    if not args.no_cpu_baseline:
+        log("large_2d: CPU oracle")
+        base, parity = cpu_baseline(cfg, f_host, u64.cpu().numpy(),
+                                    {"fp32_refined": uir.cpu().numpy(),
+                                     "fp32_pcg": upcg.cpu().numpy()})
+        rec["cpu_baseline"] = base
+        rec["parity_vs_oracle"] = parity
+    else:
+        rec["cpu_baseline"] = None
+    S.close()
+    return rec
+
+
+def bench_batch(args, torch, H, np, workloads, dev):
+    cfg = workloads.BATCH
+    pairs = workloads.batch_problems(cfg["count"], seed=0)
+    solvers = {}
+    probs = []
+    for n, K in pairs:
+        if (n, K) not in solvers:
+            solvers[(n, K)] = H.Solver((n, n), (K, K), cfg["X"], cfg["alpha"])
+        probs.append((solvers[(n, K)], cfg["nrhs"]))
+    B = H.Batch(probs)
+    f = torch.empty(B.total, dtype=torch.float64, device=dev)
+    for p, arr in enumerate(workloads.batch_rhs(pairs, cfg["nrhs"], seed=0)):
+        B.view(f, p).copy_(torch.from_numpy(arr))
+    u = torch.empty_like(f)
+    uir = torch.empty_like(f)
+    ws = B.workspace("fp32_ir")
+    s = torch.cuda.Stream()
+    steps = max(2, args.steps // 4)
+    log(f"batch_2d: {len(pairs)} problems, {B.groups} groups, {B.total} unknowns")
+    with torch.cuda.stream(s):
+        ms64 = time_calls(torch, lambda: B.solve(f, u, mode="fp64", use_graph=True,
+                                                 stream=s.cuda_stream), steps, 2, s)
+        ms64_eager = time_calls(torch, lambda: B.solve(f, u, mode="fp64", use_graph=False,
+                                                       stream=s.cuda_stream), steps, 1, s)
+        ms_ir = time_calls(torch, lambda: B.solve(f, uir, mode="fp32_ir", ws=ws,
+                                                  max_iter=args.ir_iters, use_graph=True,
+                                                  stream=s.cuda_stream), steps, 2, s)
+    torch.cuda.synchronize()
+    err = float(torch.linalg.vector_norm(uir - u) / torch.linalg.vector_norm(u))
+    rec = {"workload": "batch_2d", "problems": len(pairs), "groups": B.groups,
+           "rhs_per_problem": cfg["nrhs"], "unknowns": B.total,
+           "fp64": {"unknowns_per_s": B.total / (ms64 * 1e-3), "ms_per_batch": ms64,
+                    "ms_per_batch_without_graph": ms64_eager},
+           "fp32_refined": {"unknowns_per_s": B.total / (ms_ir * 1e-3), "ms_per_batch": ms_ir,
+                            "refinement_steps": args.ir_iters, "rel_l2_vs_fp64_gpu": err}}
+    B.close()
+    for S in solvers.values():
+        S.close()
+    return rec
+
+
+def bench_cube(args, torch, H, np, workloads, dev):
+    cfg = workloads.CONFIGS["cube_3d"]
+    shp = workloads.shape(cfg["orders"], cfg["Ks"])
+    M = int(np.prod(shp))
+    f64 = torch.from_numpy(workloads.manufactured_3d(cfg, seed=0)).to(dev)
+    S = H.Solver(cfg["orders"], cfg["Ks"], cfg["X"], cfg["alpha"])
+    u64 = torch.empty_like(f64)
+    uir = torch.empty_like(f64)
+    ws = S.workspace("fp32_ir")
+    steps = max(2, args.steps // 2)
+    log(f"cube_3d: {M} unknowns")
+    S.set_timing(True)
+    ms64 = time_calls(torch, lambda: S.solve(f64, u64, mode="fp64"), steps, 1)
+    passes64 = S.pass_times()
+    S.set_timing(False)
+    ms_ir = time_calls(torch, lambda: S.solve(f64, uir, mode="fp32_ir", ws=ws,
+                                              max_iter=args.ir_iters, tol=0.0), steps, 1)
+    err = float(torch.linalg.vector_norm(uir - u64) / torch.linalg.vector_norm(u64))
+    rec = {"workload": "cube_3d", "unknowns": M,
+           "fp64": {"unknowns_per_s": M / (ms64 * 1e-3), "ms_per_step": ms64,
+                    "passes": [dict(p, avg_ms=p["ms"] / p["launches"],
+                                    gbs=p["bytes"] / (p["ms"] / p["launches"] * 1e-3) / 1e9)
+                               for p in passes64]},
+           "fp32_refined": {"unknowns_per_s": M / (ms_ir * 1e-3), "ms_per_step": ms_ir,
+                            "refinement_steps": args.ir_iters, "rel_l2_vs_fp64_gpu": err}}
+    S.close()
+    return rec
+
+
+def bench_varcoef(args, torch, H, np, workloads, dev):
+    cfg = workloads.CONFIGS["varcoef_3d"]
+    shp = workloads.shape(cfg["orders"], cfg["Ks"])
+    M = int(np.prod(shp))
+    S = H.Solver(cfg["orders"], cfg["Ks"], cfg["X"], cfg["alpha"])
+    c0, c1, ts = workloads.sine_coefficient(workloads.wavenumbers(3, seed=0))
+    tabs = []
+    for i, (n, K, X) in enumerate(zip(cfg["orders"], cfg["Ks"], cfg["X"])):
+        gx = H.Plan1D(n, K).table("gx")      # Gauss nodes of the library's rule
+        pts = (np.arange(K)[:, None] + (gx[None, :] + 1.0) / 2.0) * (X / K)
+        tabs.append(torch.from_numpy(ts[i](pts)).to(dev))
+    coef = H.make_coef(1, c0, c1, t=tuple(tabs))
+    f = torch.from_numpy(workloads.uniform_rhs(shp, seed=0)).to(dev)
+    u = torch.empty_like(f)
+    ws = S.pcg_workspace(coef)
+    log(f"varcoef_3d: {M} unknowns")
+    info = {}
+
+    def run():
+        _, inf, _ = S.pcg(f, u, coef=coef, rtol=1e-10, max_iter=300, ws=ws)
+        info["it"] = inf.iterations
+        info["res"] = inf.rel_residual
+    ms = time_calls(torch, run, 2, 1)
+    out = torch.empty_like(f)
+    ms_op = time_calls(torch, lambda: S.apply_coef_operator(u, coef, out=out, ws=ws), 5, 1)
+    rec = {"workload": "varcoef_3d", "unknowns": M, "rtol": 1e-10,
+           "iterations": info["it"], "rel_residual": info["res"], "ms_per_solve": ms,
+           "unknowns_per_s": M / (ms * 1e-3),
+           "operator": {"ms_per_apply": ms_op, "unknowns_per_s": M / (ms_op * 1e-3)}}
+    S.close()
+    return rec
 
 
 def main():
@@ -103,9 +321,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="large_2d")
     ap.add_argument("--ir-iters", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", default="large_2d,batch_2d,cube_3d,varcoef_3d",
+                    help="comma-separated workloads; large_2d is the headline")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -120,13 +339,8 @@ def main():
     import paper_1609_07758_amd as H
     import workloads
 
-    cfg = dict(workloads.CONFIGS[args.workload])
-    cfg["name"] = args.workload
-    shp = workloads.shape(cfg["orders"], cfg["Ks"])
-    M = int(np.prod(shp))
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-
     if args.calibration_copy:
         a = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
         b = torch.empty_like(a)
@@ -134,89 +348,23 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    f_host = workloads.uniform_rhs(shp, seed=0)
-    f64 = torch.from_numpy(f_host).to(dev)
-    f32 = f64.float()
-    S = H.Solver(cfg["orders"], cfg["Ks"], cfg["X"], cfg["alpha"])
-    u64 = torch.empty_like(f64)
-    uir = torch.empty_like(f64)
-    u32 = torch.empty_like(f32)
-    ws = S.workspace("fp32_ir")
-    torch.cuda.synchronize()
 
-    # FP64 solve (the headline figure), with per-pass event timing.
-    S.set_timing(True)
-    for _ in range(args.warmup):
-        S.solve(f64, u64, mode="fp64")
-    S.pass_times()
-    ms64 = time_solves(torch, lambda: S.solve(f64, u64, mode="fp64"), args.steps, 0)
-    passes64 = S.pass_times()
-    S.set_timing(False)
-
-    # FP32 transforms + FP64 refinement, fixed number of steps (no host sync).
-    S.set_timing(True)
-    ms_ir = time_solves(torch, lambda: S.solve(f64, uir, mode="fp32_ir", ws=ws,
-                                               max_iter=args.ir_iters, tol=0.0),
-                        args.steps, args.warmup)
-    passes_ir = S.pass_times()
-    S.set_timing(False)
-    ms32 = time_solves(torch, lambda: S.solve(f32, u32, mode="fp32"), args.steps, args.warmup)
-
-    nrm = torch.linalg.vector_norm(u64)
-    ir_vs_64 = float(torch.linalg.vector_norm(uir - u64) / nrm)
-    f32_vs_64 = float(torch.linalg.vector_norm(u32.double() - u64) / nrm)
-    # refinement history: distance to the FP64 solution after 0..4 steps
-    hist = []
-    tmp = torch.empty_like(f64)
-    for it in range(0, 5):
-        S.solve(f64, tmp, mode="fp32_ir", ws=ws, max_iter=it, tol=0.0)
-        hist.append(float(torch.linalg.vector_norm(tmp - u64) / nrm))
-    torch.cuda.synchronize()
-
-    dom = max(passes64, key=lambda p: p["ms"])
-    avg_ms = dom["ms"] / dom["launches"]
-    achieved = dom["bytes"] / (avg_ms * 1e-3) / 1e9
-    kind = f"{dom['kind']}_axis{dom['axis']}_fp64"
-    traffic = measured_traffic(args.workload, kind)
-
-    record = {
-        "metric": "unknowns/s, 2D n=9 K=2^10: FP64 vs FP32+refine @1e-12 rel L2; % HBM peak",
-        "value": M / (ms64 * 1e-3),
-        "unit": "unknowns/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms64,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": args.workload, "N": len(shp), "order_n": cfg["orders"][0],
-                   "K_per_axis": cfg["Ks"][0], "unknowns": M, "rhs": "uniform[-1,1) seed 0",
-                   "alpha": cfg["alpha"]},
-        "fp32_refined": {"unknowns_per_s": M / (ms_ir * 1e-3), "ms_per_step": ms_ir,
-                         "refinement_steps": args.ir_iters,
-                         "speedup_vs_fp64": ms64 / ms_ir,
-                         "rel_l2_vs_fp64_gpu": ir_vs_64,
-                         "rel_l2_vs_fp64_gpu_by_steps": hist},
-        "fp32_unrefined": {"unknowns_per_s": M / (ms32 * 1e-3), "ms_per_step": ms32,
-                           "rel_l2_vs_fp64_gpu": f32_vs_64},
-        "passes_fp64": [dict(p, avg_ms=p["ms"] / p["launches"],
-                             gbs=p["bytes"] / (p["ms"] / p["launches"] * 1e-3) / 1e9)
-                        for p in passes64],
-        "passes_fp32_refined": [dict(p, avg_ms=p["ms"] / p["launches"]) for p in passes_ir],
-        "roofline": {"bound": "hbm", "kernel": kind, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": dom["bytes"], "avg_launch_ms": avg_ms},
-        "kernel_sha": kernel_sha(),
-    }
-    if not args.no_cpu_baseline:
-        rec, par64, parir = cpu_baseline(cfg, f_host, u64.cpu().numpy(), uir.cpu().numpy())
-        record["cpu_baseline"] = rec
-        record["parity_vs_oracle"] = {"fp64_rel_l2": par64, "fp32_refined_rel_l2": parir}
-    else:
-        record["cpu_baseline"] = None
+    only = set(args.only.split(","))
+    record = {"metric": "unknowns/s, 2D n=9 K=2^10: FP64 vs FP32+refine @1e-12 rel L2; % HBM peak",
+              "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+              "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+              "data": "synthetic"}
+    if "large_2d" in only:
+        record.update(bench_headline(args, torch, H, np, workloads, dev))
+    others = {}
+    for name, fn in (("batch_2d", bench_batch), ("cube_3d", bench_cube),
+                     ("varcoef_3d", bench_varcoef)):
+        if name in only:
+            others[name] = fn(args, torch, H, np, workloads, dev)
+            torch.cuda.empty_cache()
+    if others:
+        record["other_workloads"] = others
+    record["kernel_sha"] = kernel_sha()
     print(json.dumps(record), flush=True)
 
 

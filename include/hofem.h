@@ -213,6 +213,53 @@ int hofem_apply_coef_operator(hofem_solver solver, const hofem_coef* coef, const
 int hofem_apply_operator(hofem_solver solver, const double* u_dev, double* out_dev, int nrhs,
                          void* stream);
 
+/* ---- batched form -------------------------------------------------------- */
+
+/* One problem of a batch: the solver of its operator and its number of
+ * right-hand sides.  Problems that share a solver handle and nrhs form a
+ * group that is solved by one batched launch per pass, so a caller with many
+ * problems of few distinct (orders, K, box, alpha) should create one solver
+ * per distinct operator and reuse the handle. */
+typedef struct {
+  hofem_solver solver;
+  int nrhs;
+} hofem_batch_problem;
+
+typedef struct hofem_batch_s* hofem_batch;
+
+/* Groups `count` problems (the batched form of algorithm (a) over many
+ * independent problems) and fixes the packed device layout of their
+ * right-hand sides and solutions: problem p occupies nrhs * prod m_i values
+ * of one packed buffer from offsets[p] on, [nrhs][m_0]..[m_{N-1}] (see
+ * hofem_batch_offsets; problems that share a group are adjacent).  The solvers must outlive
+ * the batch.  Creates kSideStreams = 4 HIP streams (default priority) and
+ * events on the current device; HOFEM_EINVAL for a NULL solver or nrhs < 1. */
+int hofem_batch_create(const hofem_batch_problem* probs, int count, hofem_batch* out);
+void hofem_batch_destroy(hofem_batch batch);
+
+/* out_host[0..count-1] = value offset of each problem in the packed layout,
+ * out_host[count] = total values.  len must equal count + 1. */
+int hofem_batch_offsets(hofem_batch batch, size_t* out_host, size_t len);
+
+/* Number of groups (distinct (solver, nrhs) pairs). */
+int hofem_batch_groups(hofem_batch batch, int* groups);
+
+/* Device workspace for hofem_batch_solve in `mode` (FP64, FP32 or FP32_IR;
+ * 0 for the direct modes). */
+int hofem_batch_workspace_bytes(hofem_batch batch, int mode, size_t* bytes);
+
+/* Solves every problem of the batch: f_dev, u_dev are packed buffers (double
+ * for FP64 and FP32_IR, float for FP32), f_dev != u_dev for FP32_IR, which
+ * runs exactly max_iter refinement steps (no tolerance test, no host
+ * synchronisation).  use_graph != 0: the first call per mode runs eagerly;
+ * later calls capture the whole batch once into a HIP graph (groups on
+ * forked streams, joined back into `stream`) and replay it while mode,
+ * buffers and max_iter stay the same (stream NULL, the legacy default
+ * stream, always runs eagerly).  Results do not depend on use_graph.
+ * Calls on one batch must not overlap. */
+int hofem_batch_solve(hofem_batch batch, int mode, const void* f_dev, void* u_dev, void* ws_dev,
+                      size_t ws_bytes, int max_iter, int use_graph, void* stream);
+
 /* ---- per-pass timing (profiling aid) ----------------------------------- */
 
 /* Kinds of device work the solver enqueues. */

@@ -36,6 +36,10 @@ class hofem_info(ctypes.Structure):
                 ("rel_residual", ctypes.c_double)]
 
 
+class hofem_batch_problem(ctypes.Structure):
+    _fields_ = [("solver", ctypes.c_void_p), ("nrhs", ctypes.c_int)]
+
+
 class hofem_coef(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("c0", ctypes.c_double), ("c1", ctypes.c_double),
                 ("t_dev", ctypes.c_void_p * 3), ("a_dev", ctypes.c_void_p)]
@@ -64,6 +68,13 @@ SIGNATURES = {
     "hofem_forward": (_c_int, [_vp, _c_int, _vp, _vp, _c_int, _vp]),
     "hofem_inverse": (_c_int, [_vp, _c_int, _vp, _vp, _c_int, _vp]),
     "hofem_apply_operator": (_c_int, [_vp, _vp, _vp, _c_int, _vp]),
+    "hofem_batch_create": (_c_int, [ctypes.POINTER(hofem_batch_problem), _c_int,
+                                    ctypes.POINTER(_vp)]),
+    "hofem_batch_destroy": (None, [_vp]),
+    "hofem_batch_offsets": (_c_int, [_vp, ctypes.POINTER(_c_size), _c_size]),
+    "hofem_batch_groups": (_c_int, [_vp, ctypes.POINTER(_c_int)]),
+    "hofem_batch_workspace_bytes": (_c_int, [_vp, _c_int, ctypes.POINTER(_c_size)]),
+    "hofem_batch_solve": (_c_int, [_vp, _c_int, _vp, _vp, _vp, _c_size, _c_int, _c_int, _vp]),
     "hofem_pcg_workspace_bytes": (_c_int, [_vp, ctypes.POINTER(hofem_coef), ctypes.POINTER(_c_size)]),
     "hofem_pcg": (_c_int, [_vp, ctypes.POINTER(hofem_coef), _vp, _vp, _c_int, _c_double, _c_int,
                            _vp, _c_size, _vp, ctypes.POINTER(hofem_info)]),
@@ -235,6 +246,94 @@ def hofem_apply_coef_operator(solver, coef, u, out, nrhs=1, ws=None, stream=None
     _check(_lib.hofem_apply_coef_operator(solver, ctypes.byref(coef) if coef else None, _ptr(u),
                                           _ptr(out), int(nrhs), _ptr(ws), wsb, _stream(stream)),
            "hofem_apply_coef_operator")
+
+
+def hofem_batch_create(problems):
+    """problems: sequence of (solver handle, nrhs)."""
+    arr = (hofem_batch_problem * len(problems))()
+    for i, (h, nrhs) in enumerate(problems):
+        arr[i].solver = h
+        arr[i].nrhs = int(nrhs)
+    b = ctypes.c_void_p()
+    _check(_lib.hofem_batch_create(arr, len(problems), ctypes.byref(b)), "hofem_batch_create")
+    return b
+
+
+def hofem_batch_destroy(batch):
+    _lib.hofem_batch_destroy(batch)
+
+
+def hofem_batch_offsets(batch, count):
+    out = (ctypes.c_size_t * (count + 1))()
+    _check(_lib.hofem_batch_offsets(batch, out, count + 1), "hofem_batch_offsets")
+    return [int(x) for x in out]
+
+
+def hofem_batch_groups(batch):
+    g = ctypes.c_int()
+    _check(_lib.hofem_batch_groups(batch, ctypes.byref(g)), "hofem_batch_groups")
+    return g.value
+
+
+def hofem_batch_workspace_bytes(batch, mode):
+    b = ctypes.c_size_t()
+    _check(_lib.hofem_batch_workspace_bytes(batch, MODES[mode] if isinstance(mode, str) else mode,
+                                            ctypes.byref(b)), "hofem_batch_workspace_bytes")
+    return b.value
+
+
+def hofem_batch_solve(batch, mode, f, u, ws=None, max_iter=0, use_graph=True, stream=None):
+    wsb = 0 if ws is None else ws.numel() * ws.element_size()
+    m = MODES[mode] if isinstance(mode, str) else mode
+    _check(_lib.hofem_batch_solve(batch, m, _ptr(f), _ptr(u), _ptr(ws), wsb, int(max_iter),
+                                  1 if use_graph else 0, _stream(stream)), "hofem_batch_solve")
+
+
+class Batch:
+    """Independent problems solved together: problems = [(Solver, nrhs), ...].
+
+    The right-hand sides and solutions live in packed 1D device buffers;
+    problem p occupies nrhs * grid values from offsets[p] on, as [nrhs][grid]
+    (offsets[-1] is the total)."""
+
+    def __init__(self, problems):
+        self.problems = [(s, int(r)) for s, r in problems]
+        self.handle = hofem_batch_create([(s.handle, r) for s, r in self.problems])
+        self.offsets = hofem_batch_offsets(self.handle, len(self.problems))
+        self.groups = hofem_batch_groups(self.handle)
+        self.total = self.offsets[-1]
+
+    def view(self, buf, p):
+        s, r = self.problems[p]
+        o = self.offsets[p]
+        return buf[o:o + r * s.size].view((r,) + s.shape)
+
+    def workspace(self, mode, device="cuda"):
+        import torch
+        return torch.empty(hofem_batch_workspace_bytes(self.handle, mode), dtype=torch.uint8,
+                           device=device)
+
+    def solve(self, f, u, mode="fp64", ws=None, max_iter=0, use_graph=True, stream=None):
+        import torch
+        dt = torch.float32 if mode == "fp32" else torch.float64
+        for name, t in (("f", f), ("u", u)):
+            if not t.is_cuda or not t.is_contiguous() or t.dtype != dt or t.numel() != self.total:
+                raise ValueError(f"{name} must be a contiguous {dt} device tensor of {self.total}")
+        if ws is None and mode == "fp32_ir":
+            ws = self.workspace(mode, f.device)
+        hofem_batch_solve(self.handle, mode, f, u, ws, max_iter, use_graph, stream)
+        return u
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            hofem_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def hofem_solver_set_timing(solver, enable):

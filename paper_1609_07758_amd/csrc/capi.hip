@@ -35,6 +35,12 @@ int hip_fail(hipError_t e) {
   return HOFEM_EHIP;
 }
 
+}  // namespace
+
+int hofem::record_hip_error(hipError_t e) { return hip_fail(e); }
+
+namespace {
+
 #define HIPCHK(x)                               \
   do {                                          \
     hipError_t e_ = (x);                        \

@@ -6,6 +6,10 @@
 
 namespace hofem {
 
+// Records e as the thread's last HIP error (hofem_last_hip_error) and
+// returns HOFEM_EHIP.
+int record_hip_error(hipError_t e);
+
 // Device tables of one axis in one precision (T = float or double).
 //
 // Coefficient order of a line (m = nK - 1 entries): q = l-1 for the k = 0

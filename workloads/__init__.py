@@ -9,6 +9,8 @@ Configurations (per axis: order n, elements K, box length X):
   varcoef_3d  N=3, n=3, K=64, X=(1,1,1), alpha=0        (191^3 = 6,967,871 unknowns) with
               a(x) = 1 + 0.5 prod_i sin(2 pi k_i x_i), k_i uniform on {1, 2, 3} from the
               seed (variable-coefficient problem -div(a grad u) = f)
+  batch_2d    256 independent 2D problems on [0,1]^2, alpha=0, per problem K uniform on
+              {32, 64, 128, 256} then n uniform on {2..6}, 4 right-hand sides each
 Right-hand sides of the random kind are i.i.d. uniform[-1, 1) values of f^h
 drawn in C order with numpy's default generator (PCG64) from the seed.
 """
@@ -45,3 +47,45 @@ def sine_coefficient(ks):
     """(c0, c1, [t_i]) of a(x) = c0 + c1 prod_i t_i(x_i) with
     t_i(x) = sin(2 pi k_i x)."""
     return 1.0, 0.5, [(lambda x, k=k: np.sin(2.0 * np.pi * k * x)) for k in ks]
+
+
+BATCH = dict(count=256, Ks=(32, 64, 128, 256), orders=(2, 3, 4, 5, 6), nrhs=4,
+             X=(1.0, 1.0), alpha=0.0)
+
+
+def batch_problems(count=256, seed=0, Ks=BATCH["Ks"], orders=BATCH["orders"]):
+    """(n, K) per problem: for each problem K, then n, from one generator."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        K = int(rng.choice(Ks))
+        n = int(rng.choice(orders))
+        out.append((n, K))
+    return out
+
+
+def batch_rhs(problems, nrhs=4, seed=0, dtype=np.float64):
+    """Right-hand sides of the batch, one (nrhs, m, m) array per problem in
+    problem order, i.i.d. uniform[-1, 1) from a generator seeded seed + 1."""
+    rng = np.random.default_rng(seed + 1)
+    for n, K in problems:
+        m = n * K - 1
+        yield rng.uniform(-1.0, 1.0, (nrhs, m, m)).astype(dtype)
+
+
+def grid_points(n, K, X):
+    """Coordinates q X / (n K), q = 1..nK-1, of the unknowns along one axis."""
+    return np.arange(1, n * K) * (X / (n * K))
+
+
+def manufactured_3d(cfg, seed=0, sigma=1e-3):
+    """Nodal values of f = 11 pi^2 sin(pi x) sin(pi y) sin(3 pi z) (= -Lap of
+    u = sin(pi x) sin(pi y) sin(3 pi z)) on the grid of a 3D configuration,
+    plus i.i.d. N(0, sigma^2) noise (sigma is the standard deviation)."""
+    (n0, n1, n2), (K0, K1, K2), (X0, X1, X2) = cfg["orders"], cfg["Ks"], cfg["X"]
+    a = np.sin(np.pi * grid_points(n0, K0, X0))
+    b = np.sin(np.pi * grid_points(n1, K1, X1))
+    c = np.sin(3 * np.pi * grid_points(n2, K2, X2))
+    f = (11 * np.pi ** 2) * a[:, None, None] * b[None, :, None] * c[None, None, :]
+    f += np.random.default_rng(seed).normal(0.0, sigma, f.shape)
+    return f
