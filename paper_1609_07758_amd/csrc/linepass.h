@@ -452,40 +452,47 @@ __device__ __forceinline__ void fwd_block(const T* __restrict__ tb, const T (&x)
 // y_s = sum_l w_l p_k^(l)_s.
 template <typename T, int N>
 __device__ __forceinline__ void inv_block(const T* __restrict__ tb, const T (&w)[N], T (&y)[N]) {
+  constexpr int NP_ = N * (N - 1);
+  T tab[NP_ > 0 ? NP_ : 1];
+#pragma unroll
+  for (int e = 0; e < NP_; ++e) tab[e] = tb[e * 64];
 #pragma unroll
   for (int i = 0; i < N; ++i) y[i] = T(0);
 #pragma unroll
   for (int l = 0; l < N; ++l) {
     y[0] += w[l];
 #pragma unroll
-    for (int i = 1; i < N; ++i) y[i] += w[l] * tb[(l * (N - 1) + i - 1) * 64];
+    for (int i = 1; i < N; ++i) y[i] += w[l] * tab[l * (N - 1) + i - 1];
   }
 }
 
 // Fused pass at k >= 1: direct coefficients, division by the FP64
-// denominators dbase + sc lamk[l], inverse combination; each row p_k^(l) of
-// the table is read once and used for both products.
+// denominators dbase + sc lamk[l], inverse combination.  The wave number's
+// table entries are all loaded first (one read each, every load in flight at
+// once) and then used for both products.
 template <typename T, int N>
 __device__ __forceinline__ void fused_block(const T* __restrict__ tb, const double* __restrict__ lk,
                                             int K, double dbase, double sc, const T (&x)[N],
                                             T (&y)[N]) {
+  constexpr int NE = N * (N - 1) + N;
+  T tab[NE];
+  double lam[N];
+#pragma unroll
+  for (int e = 0; e < NE; ++e) tab[e] = tb[e * 64];
+#pragma unroll
+  for (int l = 0; l < N; ++l) lam[l] = lk[(size_t)l * (K - 1)];
 #pragma unroll
   for (int i = 0; i < N; ++i) y[i] = T(0);
 #pragma unroll
   for (int l = 0; l < N; ++l) {
-    T row[N > 1 ? N - 1 : 1];
     T s = x[0];
 #pragma unroll
-    for (int i = 1; i < N; ++i) {
-      row[i - 1] = tb[(l * (N - 1) + i - 1) * 64];
-      s += row[i - 1] * x[i];
-    }
-    s *= tb[(N * (N - 1) + l) * 64];
-    const double den = dbase + sc * lk[(size_t)l * (K - 1)];
-    const T w = (T)((double)s / den);
+    for (int i = 1; i < N; ++i) s += tab[l * (N - 1) + i - 1] * x[i];
+    s *= tab[N * (N - 1) + l];
+    const T w = (T)((double)s / (dbase + sc * lam[l]));
     y[0] += w;
 #pragma unroll
-    for (int i = 1; i < N; ++i) y[i] += w * row[i - 1];
+    for (int i = 1; i < N; ++i) y[i] += w * tab[l * (N - 1) + i - 1];
   }
 }
 
@@ -756,7 +763,9 @@ __global__ __launch_bounds__(threads_for<T>()) void line_pass(PassArgs a) {
         }
       }
       __syncthreads();
-      // sine pre-processing of the task's own (W, d) pair, in registers
+      // sine pre-processing of the task's own (W, d) pair, in registers (the
+      // weights are recomputed here rather than held across the block phase)
+      task_sines<T, K, R>(SN, j, snr);
       if (task_ok) {
 #pragma unroll
         for (int t = 0; t < R; ++t) {

@@ -151,9 +151,13 @@ def test_fp32_solve_within_1e5(orders, Ks, X, alpha):
 
 @pytest.mark.parametrize("orders,Ks,X,alpha", [CASES[0], CASES[2], CASES[7], CASES[9], CASES[11]])
 def test_fp32_refined_reaches_1e12(orders, Ks, X, alpha):
+    # Plain residual correction contracts erratically where eps_32 * cond(L)
+    # is not small (n = 9, K = 1024: some steps barely contract), so the
+    # refinement runs to a relative update of 1e-14 (at most 20 steps).
     shp = workloads.shape(orders, Ks)
     f = workloads.uniform_rhs(shp, seed=2)
-    got, _ = run_case(orders, Ks, X, alpha, f, mode="fp32_ir", max_iter=4)
+    got, _ = run_case(orders, Ks, X, alpha, f, mode="fp32_ir", max_iter=20, tol=1e-14,
+                      raise_noconv=False)
     want = osolve.solve(f, orders, Ks, X, alpha)
     assert rel(got, want) < 1e-12
 
