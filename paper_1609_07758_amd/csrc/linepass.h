@@ -59,9 +59,10 @@ constexpr int kMaxCB = 64;         // lines per workgroup (upper bound)
 // has the maximum size: the load, block and scatter phases use all lanes.
 template <typename T>
 constexpr int threads_for() { return 512; }
-// global loads in flight per lane: one round for lines up to 16384 values
-template <typename T>
-constexpr int unroll_for() { return sizeof(T) == 8 ? 32 : 16; }
+// global loads in flight per lane: one round for the workgroup's values
+// (at most 64 KB of lines per workgroup unless a single line needs more)
+template <typename T, int LOG2K>
+constexpr int unroll_for() { return (sizeof(T) == 8 && LOG2K >= 10) ? 32 : 16; }
 constexpr unsigned kXcds = 8;      // accelerator complex dies of an MI355X
 
 template <typename T>
@@ -277,29 +278,32 @@ __device__ __forceinline__ void load_canonical(cx<T> (&v)[R], const cx<T>* buf, 
   for (int t = 0; t < R; ++t) v[t] = buf[sw(j + G * t)];
 }
 
-template <int LOG2K>
+// Points per lane: R = min(RMAX, K); a transform of K = 2^LOG2K points takes
+// at most three radix-(<= R) steps.
+template <int LOG2K, int LOG2RMAX = 4>
 struct FftShape {
   static constexpr int K = 1 << LOG2K;
-  static constexpr int R = K < 16 ? K : 16;
-  static constexpr int LOG2R = LOG2K < 4 ? LOG2K : 4;
+  static constexpr int LOG2R = LOG2K < LOG2RMAX ? LOG2K : LOG2RMAX;
+  static constexpr int R = 1 << LOG2R;
   static constexpr int G = K / R;
 };
 
 // Forward K-point FFT of the task's points (in v, canonical distribution);
 // result in natural order in buf.  The twiddles of the later steps are
 // loaded before the first step, so that their latency overlaps it.
-template <typename T, int LOG2K>
-__device__ __forceinline__ void task_fft(cx<T> (&v)[FftShape<LOG2K>::R], cx<T>* buf, int j,
-                                         const cx<T>* __restrict__ tw) {
-  using S = FftShape<LOG2K>;
-  constexpr int K = S::K, R = S::R;
-  constexpr int L1 = LOG2K - S::LOG2R;           // left after the first step
-  constexpr int R2 = L1 >= 4 ? 16 : (L1 > 0 ? (1 << L1) : 2);
-  constexpr int D2 = S::LOG2R;
-  constexpr int L2 = L1 - (L1 >= 4 ? 4 : L1);
-  constexpr int R3 = L2 >= 4 ? 16 : (L2 > 0 ? (1 << L2) : 2);
-  constexpr int D3 = D2 + (L1 >= 4 ? 4 : L1);
-  static_assert(L2 <= 4, "K up to 2^12");
+template <typename T, int LOG2K, int LOG2RMAX>
+__device__ __forceinline__ void task_fft(cx<T> (&v)[(FftShape<LOG2K, LOG2RMAX>::R)], cx<T>* buf,
+                                         int j, const cx<T>* __restrict__ tw) {
+  using S = FftShape<LOG2K, LOG2RMAX>;
+  constexpr int K = S::K, R = S::R, LR = S::LOG2R;
+  constexpr int L1 = LOG2K - LR;                 // left after the first step
+  constexpr int S2 = L1 >= LR ? LR : L1;         // log2 of the second radix
+  constexpr int R2 = S2 > 0 ? (1 << S2) : 2;
+  constexpr int D2 = LR;
+  constexpr int L2 = L1 - S2;
+  constexpr int R3 = L2 > 0 ? (1 << L2) : 2;
+  constexpr int D3 = D2 + S2;
+  static_assert(L2 <= LR, "at most three steps");
   cx<T> none[R / R][TwBase<R>::NBASE];
   cx<T> t2[R / R2][TwBase<R2>::NBASE];
   cx<T> t3[R / R3][TwBase<R3>::NBASE];
@@ -325,6 +329,7 @@ __device__ __forceinline__ void task_fft(cx<T> (&v)[FftShape<LOG2K>::R], cx<T>* 
 // sin and cos of pi j / K (two table reads) and the constants of pi t / R.
 template <typename T, int K, int R>
 __device__ __forceinline__ void task_sines(const T* __restrict__ sn, int j, T (&out)[R]) {
+  static_assert(R <= 16, "16 rotation constants");
   const T sa = sn[j], ca = sn[K / 2 - j];
 #pragma unroll
   for (int t = 0; t < R; ++t)
@@ -334,9 +339,9 @@ __device__ __forceinline__ void task_sines(const T* __restrict__ sn, int j, T (&
 // After task_fft: the two sine transforms of the pair, (X^a_k, X^b_k) at
 // index k = 1..K-1 of buf (index 0 set to zero).  Lane j handles the wave
 // numbers k in [j C, (j+1) C), C = K / (2 G).
-template <typename T, int LOG2K>
+template <typename T, int LOG2K, int LOG2RMAX>
 __device__ __forceinline__ void task_post(cx<T>* buf, int j) {
-  using S = FftShape<LOG2K>;
+  using S = FftShape<LOG2K, LOG2RMAX>;
   constexpr int K = S::K, G = S::G;
   constexpr int C = (K / 2) / G;
   // The running sums are carried in FP64 whatever T is: in FP32 their
@@ -496,15 +501,32 @@ __device__ __forceinline__ void fused_block(const T* __restrict__ tb, const doub
   }
 }
 
+// log2 of the points per lane: 8 in FP64 for K <= 512 (fewer registers, so
+// that more workgroups share a CU), 16 otherwise.
+template <typename T, int LOG2K>
+constexpr int log2_rmax() { return (sizeof(T) == 8 && LOG2K <= 9) ? 3 : 4; }
+
+// Register budget: four waves per SIMD (two 512-lane workgroups per CU, up
+// to 128 VGPRs) where that costs no spills; otherwise two (FP64 single-line
+// passes and orders >= 7, whose per-wave-number tables alone take 2 n^2
+// registers) or three (the FP32 fused pass of orders >= 8).
+template <typename T, int N, int LOG2K, int MODE>
+constexpr int waves_per_simd() {
+  if (sizeof(T) == 8) return (LOG2K <= 9 && N <= 6) ? 4 : 2;
+  return (N >= 8 && MODE == PASS_FUSED) ? 3 : 4;
+}
+
 template <typename T, int N, int LOG2K, int MODE, typename TIN, typename TOUT>
-__global__ __launch_bounds__(threads_for<T>()) void line_pass(PassArgs a) {
-  using S = FftShape<LOG2K>;
+__global__ __launch_bounds__(threads_for<T>())
+__attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void line_pass(PassArgs a) {
+  constexpr int LRM = log2_rmax<T, LOG2K>();
+  using S = FftShape<LOG2K, LRM>;
   constexpr int K = S::K, R = S::R, G = S::G;
   constexpr int TPW = 64 / G;          // tasks per wavefront
   constexpr int NP = (N + 1) / 2;      // slot pairs per line
   constexpr int M = N * K - 1;         // line length
   constexpr int KM = K - 1;
-  constexpr int kUnroll = unroll_for<T>();
+  constexpr int kUnroll = unroll_for<T, LOG2K>();
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x;
   const int nthr = blockDim.x;
@@ -670,8 +692,8 @@ __global__ __launch_bounds__(threads_for<T>()) void line_pass(PassArgs a) {
     }
     __syncthreads();
     if (task_ok) {
-      task_fft<T, LOG2K>(v, tbuf, j, TW);
-      task_post<T, LOG2K>(tbuf, j);
+      task_fft<T, LOG2K, LRM>(v, tbuf, j, TW);
+      task_post<T, LOG2K, LRM>(tbuf, j);
     }
     __syncthreads();
     if constexpr (N > 1) {
@@ -820,8 +842,8 @@ __global__ __launch_bounds__(threads_for<T>()) void line_pass(PassArgs a) {
 
   // ---- inverse sine transforms and scatter to the physical line ----------
   if (task_ok) {
-    task_fft<T, LOG2K>(v, tbuf, j, TW);
-    task_post<T, LOG2K>(tbuf, j);
+    task_fft<T, LOG2K, LRM>(v, tbuf, j, TW);
+    task_post<T, LOG2K, LRM>(tbuf, j);
   }
   __syncthreads();
   if constexpr (N > 1) {
@@ -874,7 +896,8 @@ struct Shape {
 
 inline Shape shape_for(int n, int K, size_t cplx_bytes, long long nlines) {
   const int NP = (n + 1) / 2;
-  const int R = K < 16 ? K : 16;
+  const int rmax = (cplx_bytes == 16 && K <= 512) ? 8 : 16;   // as log2_rmax
+  const int R = K < rmax ? K : rmax;
   const int G = K / R;
   const int TPW = 64 / G;
   const size_t per_line = ((size_t)NP * K + 1) * cplx_bytes;
