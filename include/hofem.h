@@ -209,7 +209,10 @@ int hofem_apply_coef_operator(hofem_solver solver, const hofem_coef* coef, const
 /* out = L u with L the operator of eq. (bvp glob 2), FP64, matrix-free,
  * element by element, the stiffness factors in difference form
  * sum_{l != k} A_kl (v_l - v_k) so that constants are exactly in their
- * kernel.  u_dev != out_dev. */
+ * kernel.  u_dev != out_dev.  For N = 3 with equal orders the element
+ * outputs go through a device buffer of prod K_i (n+1)^3 doubles that the
+ * solver allocates on the first operator apply (this call, FP32_IR or
+ * FP32_PCG) and frees in hofem_solver_destroy; HOFEM_ENOMEM if it cannot. */
 int hofem_apply_operator(hofem_solver solver, const double* u_dev, double* out_dev, int nrhs,
                          void* stream);
 

@@ -92,6 +92,8 @@ struct hofem_solver_s {
   DevAxis ax[3];
   void* mem = nullptr;
   size_t per_rhs = 0;
+  // element outputs of the 3D operator (allocated on its first use)
+  double* op_elem = nullptr;
   // per-pass timing
   bool timing = false;
   std::vector<hipEvent_t> event_pool;
@@ -204,8 +206,9 @@ size_t ir_workspace(const hofem_solver_s* S, int nrhs) {
   return b;
 }
 
-OpArgs make_op(const hofem_solver_s* S, const double* u, const double* f, void* out, int out_f32,
-               int nrhs) {
+// Operator arguments; the 3D operator's element buffer is allocated on first use.
+int make_op(hofem_solver_s* S, const double* u, const double* f, void* out, int out_f32, int nrhs,
+            OpArgs* op) {
   OpArgs o{};
   o.u = u;
   o.f = f;
@@ -222,7 +225,16 @@ OpArgs make_op(const hofem_solver_s* S, const double* u, const double* f, void* 
   }
   o.alpha = S->alpha;
   o.nrhs = nrhs;
-  return o;
+  const size_t ne = op3_elem_doubles(o);
+  if (ne && !S->op_elem) {
+    void* m = nullptr;
+    hipError_t e = hipMalloc(&m, ne * sizeof(double));
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? HOFEM_ENOMEM : hip_fail(e);
+    S->op_elem = static_cast<double*>(m);
+  }
+  o.elem = S->op_elem;
+  *op = o;
+  return HOFEM_OK;
 }
 
 VarOpArgs make_varop(const hofem_solver_s* S, const hofem_coef* c, const double* u,
@@ -296,7 +308,9 @@ int pcg_apply(hofem_solver_s* S, const hofem_coef* c, const PcgWs& w, const doub
               const double* f, double* out, hipStream_t st) {
   const long long count = (long long)S->per_rhs;
   if (!c || c->kind == 0) {
-    OpArgs o = make_op(S, u, f, out, 0, 1);
+    OpArgs o;
+    const int rc = make_op(S, u, f, out, 0, 1, &o);
+    if (rc != HOFEM_OK) return rc;
     LaunchTimer tm(S, st, HOFEM_PASS_OPERATOR, -1, 1, (double)count * (f ? 24 : 16));
     HIPCHK(launch_operator(o, st));
     tm.done();
@@ -545,6 +559,7 @@ void hofem_solver_destroy(hofem_solver solver) {
   if (!solver) return;
   for (hipEvent_t e : solver->event_pool) (void)hipEventDestroy(e);
   if (solver->mem) (void)hipFree(solver->mem);
+  if (solver->op_elem) (void)hipFree(solver->op_elem);
   delete solver;
 }
 
@@ -654,8 +669,10 @@ int hofem_solve(hofem_solver S, int mode, const void* f_dev, void* u_dev, int nr
   double host[2] = {0.0, 0.0};
   bool have = false;
   for (; it < max_iter;) {
-    OpArgs o = make_op(S, static_cast<const double*>(u_dev), static_cast<const double*>(f_dev), r32,
-                       1, nrhs);
+    OpArgs o;
+    rc = make_op(S, static_cast<const double*>(u_dev), static_cast<const double*>(f_dev), r32, 1,
+                 nrhs, &o);
+    if (rc != HOFEM_OK) return rc;
     {
       LaunchTimer tm(S, st, HOFEM_PASS_OPERATOR, -1, 1, (double)count * (8 + 8 + 4));
       HIPCHK(launch_operator(o, st));
@@ -760,7 +777,9 @@ int hofem_apply_coef_operator(hofem_solver S, const hofem_coef* coef, const doub
     return HOFEM_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (!coef || coef->kind == 0) {
-    OpArgs o = make_op(S, u_dev, nullptr, out_dev, 0, nrhs);
+    OpArgs o;
+    const int rc = make_op(S, u_dev, nullptr, out_dev, 0, nrhs, &o);
+    if (rc != HOFEM_OK) return rc;
     HIPCHK(launch_operator(o, st));
     return HOFEM_OK;
   }
@@ -776,7 +795,9 @@ int hofem_apply_coef_operator(hofem_solver S, const hofem_coef* coef, const doub
 int hofem_apply_operator(hofem_solver S, const double* u_dev, double* out_dev, int nrhs,
                          void* stream) {
   if (!S || !u_dev || !out_dev || nrhs < 1 || u_dev == out_dev) return HOFEM_EINVAL;
-  OpArgs o = make_op(S, u_dev, nullptr, out_dev, 0, nrhs);
+  OpArgs o;
+  const int rc = make_op(S, u_dev, nullptr, out_dev, 0, nrhs, &o);
+  if (rc != HOFEM_OK) return rc;
   HIPCHK(launch_operator(o, static_cast<hipStream_t>(stream)));
   return HOFEM_OK;
 }

@@ -88,8 +88,13 @@ struct OpArgs {
   const double* A[3];  // local stiffness (n_i+1)^2, device
   const double* C[3];  // local mass (n_i+1)^2, device
   int nrhs;
+  // 3D with equal orders: per-element outputs of one right-hand side,
+  // prod K_i (n+1)^3 doubles (op3_elem_doubles), device
+  double* elem;
 };
 hipError_t launch_operator(const OpArgs& a, hipStream_t s);
+// Element buffer the 3D operator needs (0 when it needs none).
+size_t op3_elem_doubles(const OpArgs& a);
 
 // u += delta over `count` elements with per-workgroup partial sums of
 // delta^2 and u^2 (nparts workgroups), reduced to out[0..1] by a second

@@ -476,6 +476,183 @@ hipError_t launch_op2_order(const OpArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// 3D operator for equal orders NO (compile time): per element, sum-factorised
+// with the stiffness factor applied to u first in difference form,
+//   E = C_2 [ s0 C_1 (A_0 U) + s1 C_0 (A_1 U) ] + C_1 C_0 [ (s2 A_2 + alpha C_2) U ]
+// (X_a: factor X along axis a), EPW elements per workgroup, one line of b
+// outputs per lane and contraction; the elements' outputs go to a buffer and
+// a second kernel sums, for every point, the 1..8 elements holding it in a
+// fixed order (deterministic).
+// ---------------------------------------------------------------------------
+
+template <int NO>
+struct Op3Shape {
+  static constexpr int B = NO + 1, BBB = B * B * B;
+  static constexpr int EPW0 = 40960 / (6 * BBB * 8);
+  static constexpr int EPW = EPW0 < 1 ? 1 : (EPW0 > 32 ? 32 : EPW0);
+  static constexpr int LDS = 6 * BBB * EPW * 8;
+};
+
+// dst[line, q] (+)= sum_r M[q][r] src[line, r] along axis ax of b^3 blocks;
+// mode 0: plain, 1: difference form sum_{r != q} M[q][r] (src_r - src_q),
+// 2: sd * (difference form of M) + sp * (plain with M2).
+template <int B, int MODE, bool ACC>
+__device__ __forceinline__ void op3_contract(const double* src, double* dst, int ax,
+                                             const double* __restrict__ M,
+                                             const double* __restrict__ M2, double sd, double sp,
+                                             int nel, int tid, int nthr) {
+  constexpr int BB = B * B, BBB = B * B * B;
+  for (int task = tid; task < nel * BB; task += nthr) {
+    const int el = task / BB, line = task - el * BB;
+    const int i = line / B, j = line - i * B;
+    // stride of the contracted axis and base of the line inside the block
+    const int st = ax == 0 ? BB : (ax == 1 ? B : 1);
+    const int base = ax == 0 ? (i * B + j) : (ax == 1 ? (i * BB + j) : (i * BB + j * B));
+    const double* s = src + el * BBB + base;
+    double* d = dst + el * BBB + base;
+    double v[B];
+#pragma unroll
+    for (int r = 0; r < B; ++r) v[r] = s[r * st];
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      double t = 0.0;
+      if (MODE == 0) {
+#pragma unroll
+        for (int r = 0; r < B; ++r) t += M[q * B + r] * v[r];
+      } else {
+        double dd = 0.0;
+#pragma unroll
+        for (int r = 0; r < B; ++r)
+          if (r != q) dd += M[q * B + r] * (v[r] - v[q]);
+        if (MODE == 1) {
+          t = dd;
+        } else {
+          double pp = 0.0;
+#pragma unroll
+          for (int r = 0; r < B; ++r) pp += M2[q * B + r] * v[r];
+          t = sd * dd + sp * pp;
+        }
+      }
+      if (ACC) d[q * st] += t; else d[q * st] = t;
+    }
+  }
+}
+
+template <int NO>
+__global__ __launch_bounds__(256) void op3_element_kernel(OpArgs a, const double* u,
+                                                          long long nel) {
+  using SH = Op3Shape<NO>;
+  constexpr int B = SH::B, BBB = SH::BBB, EPW = SH::EPW;
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* U = reinterpret_cast<double*>(smem);
+  double* X = U + EPW * BBB;
+  double* Y = X + EPW * BBB;
+  double* Z = Y + EPW * BBB;
+  double* P = Z + EPW * BBB;
+  double* W = P + EPW * BBB;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const long long e0 = (long long)blockIdx.x * EPW;
+  const int ne = (int)min((long long)EPW, nel - e0);
+  const int K1 = a.K[1], K2 = a.K[2], m1 = a.m[1], m2 = a.m[2];
+  for (int t = tid; t < ne * BBB; t += nthr) {
+    const int el = t / BBB, loc = t - el * BBB;
+    const long long eg = e0 + el;
+    const int k0 = (int)(eg / ((long long)K1 * K2)), rem = (int)(eg - (long long)k0 * K1 * K2);
+    const int k1 = rem / K2, k2 = rem - k1 * K2;
+    const int r0 = loc / (B * B), r1 = (loc / B) % B, r2 = loc % B;
+    const int g0 = NO * k0 + r0, g1 = NO * k1 + r1, g2 = NO * k2 + r2;
+    double v = 0.0;
+    if (g0 >= 1 && g0 <= a.m[0] && g1 >= 1 && g1 <= m1 && g2 >= 1 && g2 <= m2)
+      v = u[((long long)(g0 - 1) * m1 + (g1 - 1)) * m2 + (g2 - 1)];
+    U[t] = v;
+  }
+  __syncthreads();
+  const double s0 = a.scale[0], s1 = a.scale[1], s2 = a.scale[2], al = a.alpha;
+  op3_contract<B, 1, false>(U, X, 0, a.A[0], nullptr, 1.0, 0.0, ne, tid, nthr);
+  op3_contract<B, 1, false>(U, Y, 1, a.A[1], nullptr, 1.0, 0.0, ne, tid, nthr);
+  op3_contract<B, 2, false>(U, Z, 2, a.A[2], a.C[2], s2, al, ne, tid, nthr);
+  __syncthreads();
+  op3_contract<B, 0, false>(X, P, 1, a.C[1], nullptr, 0.0, 0.0, ne, tid, nthr);
+  op3_contract<B, 0, false>(Z, W, 0, a.C[0], nullptr, 0.0, 0.0, ne, tid, nthr);
+  __syncthreads();
+  // P = s0 P + s1 C_0 Y
+  for (int t = tid; t < ne * BBB; t += nthr) P[t] *= s0;
+  __syncthreads();
+  op3_contract<B, 0, false>(Y, X, 0, a.C[0], nullptr, 0.0, 0.0, ne, tid, nthr);
+  __syncthreads();
+  for (int t = tid; t < ne * BBB; t += nthr) P[t] += s1 * X[t];
+  __syncthreads();
+  op3_contract<B, 0, false>(P, U, 2, a.C[2], nullptr, 0.0, 0.0, ne, tid, nthr);
+  __syncthreads();
+  op3_contract<B, 0, true>(W, U, 1, a.C[1], nullptr, 0.0, 0.0, ne, tid, nthr);
+  __syncthreads();
+  double* out = a.elem + e0 * BBB;
+  for (int t = tid; t < ne * BBB; t += nthr) out[t] = U[t];
+}
+
+// Per point: the sum of the element outputs holding it, then f - sum (or sum).
+template <int NO>
+__global__ __launch_bounds__(256) void op3_gather_kernel(OpArgs a, const double* f, void* out,
+                                                         long long total) {
+  constexpr int B = NO + 1, BBB = B * B * B;
+  const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= total) return;
+  const int m1 = a.m[1], m2 = a.m[2], K1 = a.K[1], K2 = a.K[2];
+  const int q0 = (int)(idx / ((long long)m1 * m2)), rem = (int)(idx - (long long)q0 * m1 * m2);
+  const int q1 = rem / m2, q2 = rem - q1 * m2;
+  int ne[3], el[3][2], rl[3][2];
+  const int qs[3] = {q0, q1, q2};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int g = qs[i] + 1;
+    if (g % NO == 0) {
+      ne[i] = 2;
+      el[i][0] = g / NO - 1; rl[i][0] = NO;
+      el[i][1] = g / NO;     rl[i][1] = 0;
+    } else {
+      ne[i] = 1;
+      el[i][0] = g / NO; rl[i][0] = g % NO;
+    }
+  }
+  double acc = 0.0;
+  for (int c0 = 0; c0 < ne[0]; ++c0)
+    for (int c1 = 0; c1 < ne[1]; ++c1)
+      for (int c2 = 0; c2 < ne[2]; ++c2) {
+        const long long e = ((long long)el[0][c0] * K1 + el[1][c1]) * K2 + el[2][c2];
+        const int loc = (rl[0][c0] * B + rl[1][c1]) * B + rl[2][c2];
+        acc += a.elem[e * BBB + loc];
+      }
+  const double res = f ? f[idx] - acc : acc;
+  if (a.out_f32) static_cast<float*>(out)[idx] = (float)res;
+  else static_cast<double*>(out)[idx] = res;
+}
+
+template <int NO>
+hipError_t launch_op3_order(const OpArgs& a, hipStream_t s) {
+  using SH = Op3Shape<NO>;
+  const long long nel = (long long)a.K[0] * a.K[1] * a.K[2];
+  const long long per = (long long)a.m[0] * a.m[1] * a.m[2];
+  const unsigned blocks = (unsigned)((nel + SH::EPW - 1) / SH::EPW);
+  static bool raised = false;
+  if (!raised) {
+    hipError_t e = hipFuncSetAttribute((const void*)op3_element_kernel<NO>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    raised = true;
+  }
+  for (int r = 0; r < a.nrhs; ++r) {
+    const double* u = a.u + r * per;
+    const double* f = a.f ? a.f + r * per : nullptr;
+    void* out = a.out_f32 ? (void*)(static_cast<float*>(a.out) + r * per)
+                          : (void*)(static_cast<double*>(a.out) + r * per);
+    hipLaunchKernelGGL(op3_element_kernel<NO>, dim3(blocks), dim3(256), SH::LDS, s, a, u, nel);
+    hipLaunchKernelGGL(op3_gather_kernel<NO>, dim3((unsigned)((per + 255) / 256)), dim3(256), 0,
+                       s, a, f, out, per);
+  }
+  return hipGetLastError();
+}
+
 // LDS bytes of a 2D tile of TE0 x TE1 owned elements.
 size_t tile2_lds(int n0, int n1, int TE0, int TE1) {
   const size_t P0 = (size_t)n0 * (TE0 + 1) + 1, P1 = (size_t)n1 * (TE1 + 1) + 1;
@@ -587,7 +764,23 @@ hipError_t launch_operator(const OpArgs& a, hipStream_t s) {
                          dim3(256), lds, s, a, tl);
       break;
     }
-    case 3: hipLaunchKernelGGL(op_kernel<3>, dim3(blocks), dim3(256), 0, s, a, total); break;
+    case 3:
+      if (a.elem && a.n[0] == a.n[1] && a.n[1] == a.n[2]) {
+        switch (a.n[0]) {
+          case 1: return launch_op3_order<1>(a, s);
+          case 2: return launch_op3_order<2>(a, s);
+          case 3: return launch_op3_order<3>(a, s);
+          case 4: return launch_op3_order<4>(a, s);
+          case 5: return launch_op3_order<5>(a, s);
+          case 6: return launch_op3_order<6>(a, s);
+          case 7: return launch_op3_order<7>(a, s);
+          case 8: return launch_op3_order<8>(a, s);
+          case 9: return launch_op3_order<9>(a, s);
+          default: break;
+        }
+      }
+      hipLaunchKernelGGL(op_kernel<3>, dim3(blocks), dim3(256), 0, s, a, total);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -606,6 +799,12 @@ hipError_t launch_axpy(const float* delta, double* u, long long count, hipStream
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(axpy_kernel, dim3((unsigned)blocks), dim3(256), 0, s, delta, u, count);
   return hipGetLastError();
+}
+
+size_t op3_elem_doubles(const OpArgs& a) {
+  if (a.N != 3 || a.n[0] != a.n[1] || a.n[1] != a.n[2]) return 0;
+  const size_t b = (size_t)a.n[0] + 1;
+  return (size_t)a.K[0] * a.K[1] * a.K[2] * b * b * b;
 }
 
 }  // namespace hofem
