@@ -507,13 +507,12 @@ template <typename T, int LOG2K>
 constexpr int log2_rmax() { return (sizeof(T) == 8 && LOG2K <= 9) ? 3 : 4; }
 
 // Register budget: four waves per SIMD (two 512-lane workgroups per CU, up
-// to 128 VGPRs) where that costs no spills; otherwise two (FP64 single-line
-// passes and orders >= 7, whose per-wave-number tables alone take 2 n^2
-// registers) or three (the FP32 fused pass of orders >= 8).
+// to 128 VGPRs), except in FP64 for single-line passes and orders >= 7,
+// whose per-wave-number tables alone take 2 n^2 registers (two waves).
 template <typename T, int N, int LOG2K, int MODE>
 constexpr int waves_per_simd() {
   if (sizeof(T) == 8) return (LOG2K <= 9 && N <= 6) ? 4 : 2;
-  return (N >= 8 && MODE == PASS_FUSED) ? 3 : 4;
+  return 4;
 }
 
 template <typename T, int N, int LOG2K, int MODE, typename TIN, typename TOUT>
