@@ -266,6 +266,147 @@ __global__ __launch_bounds__(1024) void varop_element_kernel(VarOpArgs a, double
   for (int t = tid; t < npts; t += nthr) dst[t] = OUT[t];
 }
 
+// 3D, equal orders NO (compile time): EPW elements per workgroup, every 1D
+// factor applied as one line of b values per lane with the tables as uniform
+// operands; per term i the stiffness factor acts first (difference form:
+// the derivative table applied to u - u_0 along the line), then the basis
+// values along the other axes, the Gauss weights times a, and the
+// transposed factors back.  One phase per factor, a barrier between phases.
+template <int NO>
+struct VarShape {
+  static constexpr int B = NO + 1, BBB = B * B * B;
+  static constexpr int EPW0 = 32768 / (4 * BBB * 8);
+  static constexpr int EPW = EPW0 < 1 ? 1 : (EPW0 > 32 ? 32 : EPW0);
+  static constexpr int LDS = 4 * BBB * EPW * 8;
+};
+
+// dst[line, q] (+)= sum_r m(q, r) (src[line, r] - ref) along axis ax of the
+// b^3 blocks; m(q, r) = M[q B + r] (or M[r B + q] transposed); ref = src at
+// r = 0 in difference form, 0 otherwise.
+template <int B, bool TRANS, bool DIFF, bool ACC>
+__device__ __forceinline__ void var_contract(const double* src, double* dst, int ax,
+                                             const double* __restrict__ M, int nel, int tid,
+                                             int nthr) {
+  constexpr int BB = B * B, BBB = B * B * B;
+  for (int task = tid; task < nel * BB; task += nthr) {
+    const int el = task / BB, line = task - el * BB;
+    const int i = line / B, j = line - i * B;
+    const int st = ax == 0 ? BB : (ax == 1 ? B : 1);
+    const int base = ax == 0 ? (i * B + j) : (ax == 1 ? (i * BB + j) : (i * BB + j * B));
+    const double* sp = src + el * BBB + base;
+    double* d = dst + el * BBB + base;
+    double v[B];
+#pragma unroll
+    for (int r = 0; r < B; ++r) v[r] = sp[r * st];
+    if (DIFF) {
+#pragma unroll
+      for (int r = B - 1; r >= 0; --r) v[r] -= v[0];
+    }
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      double t = 0.0;
+#pragma unroll
+      for (int r = 0; r < B; ++r) t += (TRANS ? M[r * B + q] : M[q * B + r]) * v[r];
+      if (ACC) d[q * st] += t; else d[q * st] = t;
+    }
+  }
+}
+
+template <int NO>
+__global__ __launch_bounds__(256) void varop3_order_kernel(VarOpArgs a, double* elem_out) {
+  using SH = VarShape<NO>;
+  constexpr int B = SH::B, BBB = SH::BBB, EPW = SH::EPW;
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* U = reinterpret_cast<double*>(smem);
+  double* X = U + EPW * BBB;
+  double* Y = X + EPW * BBB;
+  double* E = Y + EPW * BBB;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int K0 = a.K[0], K1 = a.K[1], K2 = a.K[2];
+  const long long nel = (long long)K0 * K1 * K2;
+  const long long e0 = (long long)blockIdx.x * EPW;
+  const int ne = (int)min((long long)EPW, nel - e0);
+  const long long rhs = blockIdx.y;
+  const double* __restrict__ u = a.u + rhs * a.per_rhs;
+  const int m0 = NO * K0 - 1, m1 = NO * K1 - 1, m2 = NO * K2 - 1;
+  for (int t = tid; t < ne * BBB; t += nthr) {
+    const int el = t / BBB, loc = t - el * BBB;
+    const long long eg = e0 + el;
+    const int k0 = (int)(eg / ((long long)K1 * K2)), rem = (int)(eg - (long long)k0 * K1 * K2);
+    const int k1 = rem / K2, k2 = rem - k1 * K2;
+    const int g0 = NO * k0 + loc / (B * B), g1 = NO * k1 + (loc / B) % B, g2 = NO * k2 + loc % B;
+    double v = 0.0;
+    if (g0 >= 1 && g0 <= m0 && g1 >= 1 && g1 <= m1 && g2 >= 1 && g2 <= m2)
+      v = u[(g0 - 1) * a.stride[0] + (g1 - 1) * a.stride[1] + (g2 - 1) * a.stride[2]];
+    U[t] = v;
+  }
+  __syncthreads();
+  // quadrature weight times coefficient (times s) at every Gauss point of the batch
+  auto weigh = [&](double* Z, double s) {
+    for (int t = tid; t < ne * BBB; t += nthr) {
+      const int el = t / BBB, Q = t - el * BBB;
+      const int q0 = Q / (B * B), q1 = (Q / B) % B, q2 = Q % B;
+      double wq = a.w[0][q0] * a.w[1][q1] * a.w[2][q2];
+      const long long eg = e0 + el;
+      if (a.kind == 1) {
+        const int k0 = (int)(eg / ((long long)K1 * K2)), rem = (int)(eg - (long long)k0 * K1 * K2);
+        const int k1 = rem / K2, k2 = rem - k1 * K2;
+        wq *= a.c0 + a.c1 * a.t[0][k0 * B + q0] * a.t[1][k1 * B + q1] * a.t[2][k2 * B + q2];
+      } else if (a.kind == 2) {
+        wq *= a.afull[eg * BBB + Q];
+      }
+      Z[t] *= s * wq;
+    }
+  };
+#pragma unroll
+  for (int term = 0; term < 3; ++term) {
+    const int j = term == 0 ? 1 : 0, k = term == 2 ? 1 : 2;   // the other axes, j < k
+    var_contract<B, false, true, false>(U, X, term, a.D[term], ne, tid, nthr);
+    __syncthreads();
+    var_contract<B, false, false, false>(X, Y, j, a.B[j], ne, tid, nthr);
+    __syncthreads();
+    var_contract<B, false, false, false>(Y, X, k, a.B[k], ne, tid, nthr);
+    __syncthreads();
+    weigh(X, a.scale[term]);
+    __syncthreads();
+    var_contract<B, true, false, false>(X, Y, k, a.B[k], ne, tid, nthr);
+    __syncthreads();
+    var_contract<B, true, false, false>(Y, X, j, a.B[j], ne, tid, nthr);
+    __syncthreads();
+    if (term == 0) var_contract<B, true, false, false>(X, E, term, a.D[term], ne, tid, nthr);
+    else var_contract<B, true, false, true>(X, E, term, a.D[term], ne, tid, nthr);
+    __syncthreads();
+  }
+  if (a.alpha != 0.0) {
+    var_contract<B, false, false, false>(U, X, 0, a.B[0], ne, tid, nthr);
+    __syncthreads();
+    var_contract<B, false, false, false>(X, Y, 1, a.B[1], ne, tid, nthr);
+    __syncthreads();
+    var_contract<B, false, false, false>(Y, X, 2, a.B[2], ne, tid, nthr);
+    __syncthreads();
+    weigh(X, a.alpha);
+    __syncthreads();
+    var_contract<B, true, false, false>(X, Y, 2, a.B[2], ne, tid, nthr);
+    __syncthreads();
+    var_contract<B, true, false, false>(Y, X, 1, a.B[1], ne, tid, nthr);
+    __syncthreads();
+    var_contract<B, true, false, true>(X, E, 0, a.B[0], ne, tid, nthr);
+    __syncthreads();
+  }
+  double* out = elem_out + (rhs * nel + e0) * BBB;
+  for (int t = tid; t < ne * BBB; t += nthr) out[t] = E[t];
+}
+
+template <int NO>
+hipError_t launch_varop3(const VarOpArgs& a, double* elem_buf, hipStream_t s) {
+  using SH = VarShape<NO>;
+  const long long nel = (long long)a.K[0] * a.K[1] * a.K[2];
+  const unsigned blocks = (unsigned)((nel + SH::EPW - 1) / SH::EPW);
+  hipLaunchKernelGGL(varop3_order_kernel<NO>, dim3(blocks, (unsigned)a.nrhs), dim3(256), SH::LDS,
+                     s, a, elem_buf);
+  return hipGetLastError();
+}
+
 // Per grid point: sum of the element contributions of the 1..2^N elements
 // holding it; out = f - sum (residual) or sum.
 template <int N>
@@ -344,6 +485,24 @@ hipError_t launch_varop(const VarOpArgs& a, double* elem_buf, hipStream_t s) {
       hipLaunchKernelGGL(varop_gather_kernel<2>, dim3(gb), dim3(256), 0, s, a, elem_buf, total);
       break;
     case 3: {
+      if (a.n[0] == a.n[1] && a.n[1] == a.n[2]) {
+        hipError_t e = hipSuccess;
+        switch (a.n[0]) {
+          case 1: e = launch_varop3<1>(a, elem_buf, s); break;
+          case 2: e = launch_varop3<2>(a, elem_buf, s); break;
+          case 3: e = launch_varop3<3>(a, elem_buf, s); break;
+          case 4: e = launch_varop3<4>(a, elem_buf, s); break;
+          case 5: e = launch_varop3<5>(a, elem_buf, s); break;
+          case 6: e = launch_varop3<6>(a, elem_buf, s); break;
+          case 7: e = launch_varop3<7>(a, elem_buf, s); break;
+          case 8: e = launch_varop3<8>(a, elem_buf, s); break;
+          case 9: e = launch_varop3<9>(a, elem_buf, s); break;
+          default: e = hipErrorInvalidValue; break;
+        }
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(varop_gather_kernel<3>, dim3(gb), dim3(256), 0, s, a, elem_buf, total);
+        return hipGetLastError();
+      }
       static bool raised = false;
       if (!raised) {
         hipError_t e = hipFuncSetAttribute((const void*)varop_element_kernel<3>,
