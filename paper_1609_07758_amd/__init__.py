@@ -13,6 +13,13 @@ import os
 
 import numpy as np
 
+# torch goes first: its bundled HIP runtime carries the same soname
+# (libamdhip64.so.7) that libhofem.so needs, so the library binds to the very
+# runtime that owns torch's memory and streams.  Loaded the other way round,
+# the system runtime comes in first and torch then maps a second HIP and HSA
+# runtime of its own, whichever initialises last sees no device.
+import torch  # noqa: F401
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhofem.so")
 

@@ -101,3 +101,14 @@ def test_gauss_tables_match_oracle(n):
     # both sides round once from >= 34 digits: equal up to one rounding
     for name, ref in (("gx", x), ("gw", w), ("B", B.ravel()), ("D", D.ravel())):
         assert np.allclose(p.table(name), ref, rtol=2.3e-16, atol=1e-30), name
+
+
+def test_one_hip_runtime_in_process():
+    """The binding and torch share one HIP runtime (a second copy would own
+    no device once torch's has initialised)."""
+    import torch  # noqa: F401
+    maps = open("/proc/self/maps").read().split("\n")
+    hip = {l.split()[-1] for l in maps if "libamdhip64" in l}
+    hsa = {l.split()[-1] for l in maps if "libhsa-runtime64" in l}
+    assert len(hip) == 1, hip
+    assert len(hsa) <= 1, hsa
