@@ -146,8 +146,6 @@ PassArgs make_args(const hofem_solver_s* S, int axis, int kind, bool f64, const 
   }
   a.inner = inner;
   a.nlines = others * nrhs;
-  size_t lds = 0;
-  pass_shape(X.n, X.K, f64 ? 1 : 0, a.nlines, inner, &a.cb, &lds);
   if (kind == PASS_FUSED) {
     a.alpha = S->alpha;
     a.scale = X.scale;

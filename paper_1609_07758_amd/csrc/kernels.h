@@ -39,7 +39,7 @@ struct PassArgs {
   AxisTab tab;
   long long inner;     // stride of the axis (product of the later extents)
   long long nlines;    // number of lines (total elements / m)
-  int cb;              // lines per workgroup
+  int cb;              // lines per workgroup (set by the launcher)
   // Denominator of the fused pass: alpha + scale * lam[q] + sum over the
   // other axes of oscale[i] * olam[i][(t / odiv[i]) % omod[i]], t = line % inner.
   double alpha;
@@ -70,10 +70,6 @@ template <> hipError_t launch_pass_order<9>(int, int, const PassArgs&, hipStream
 // in, double out accumulated (out += result), 5 = FP32 compute, double in,
 // double out (stored).
 hipError_t launch_pass(int kind, int dt, const PassArgs& a, hipStream_t s);
-
-// Workgroup size / lines per workgroup / LDS bytes chosen for (n, K, dtype).
-void pass_shape(int n, int K, int is_f64, long long nlines, long long inner, int* cb,
-                size_t* lds_bytes);
 
 // FP64 matrix-free operator r = f - L u (f may be NULL: r = L u), N = 1..3.
 struct OpArgs {

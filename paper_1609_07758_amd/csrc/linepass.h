@@ -34,12 +34,12 @@
 // wavefront-level ordering only.  The running sums of the odd outputs are a
 // lane-local scan plus a segmented wave scan.
 //
-// LDS holds, per line, ceil(N/2) complex arrays of length K ("slots") and
-// one pad entry; slot pair p carries sequences 2p (real part) and 2p+1
-// (imaginary part): sequence 0 is the node sequence, sequence s >= 1 the
-// interior component s.  The physical line is loaded into the same memory
-// first; the gather that reads it holds its values in registers across a
-// workgroup barrier.
+// LDS holds, per line, ceil(N/2) complex arrays of length K ("slot pairs"):
+// interior component s and its mirror N - s share a pair, the node sequence
+// takes the last one (layout at struct Seq below).  Each sine-transform task
+// works on its own pair only, so a workgroup may run more tasks than it has
+// wavefronts, in rounds.  The physical line is loaded straight into the
+// entries of its sequences.
 //
 // Coefficients leave and enter a pass in the l-major coefficient order of
 // AxisTab, so that lanes handling consecutive wave numbers touch consecutive
@@ -388,6 +388,20 @@ __device__ __forceinline__ void task_post(cx<T>* buf, int j) {
   wave_sync();
 }
 
+// A value that is the same in every lane, moved to scalar registers (long
+// lived per-line quantities then take no vector registers).
+__device__ __forceinline__ long long uni(long long x) {
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)x);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((unsigned long long)x >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ double uni(double x) {
+  return __builtin_bit_cast(double, uni(__builtin_bit_cast(long long, x)));
+}
+__device__ __forceinline__ float uni(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(unsigned, x)));
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
@@ -395,22 +409,57 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
-// Value x_j of sequence s (0 = nodes, s >= 1 = interior component s) of the
-// forward pre-combine, read from a physical line in LDS; zero outside 1..K-1.
+// ---- line layout in LDS ------------------------------------------------------
+//
+// A line holds N sequences of K entries: sequence 0 the mesh nodes (entry j
+// for node j = 1..K-1), sequence s >= 1 interior point s of the elements
+// (entry e-1 for element e = 1..K).  The same entries hold in turn the
+// physical values, the sine transforms, the coefficients of wave number k
+// (entry k) and the inverse transforms; entry 0 of component s holds its
+// k = 0 quantity (S0_s after the direct transforms, E0_s before the scatter).
+// The sequences are stored as slot pairs of K complex entries: component s
+// and its mirror N - s, which the reversal P couples, share a pair as real
+// and imaginary part; the nodes take the last pair, together with the middle
+// component N/2 when N is even.  The sine-transform task of a pair therefore
+// reads and writes that pair only.
+template <int N>
+struct Seq {
+  static constexpr int NP = (N + 1) / 2;
+  __host__ __device__ static constexpr int pair(int s) {
+    return (s == 0 || 2 * s == N) ? NP - 1 : (2 * s < N ? s - 1 : N - s - 1);
+  }
+  __host__ __device__ static constexpr int part(int s) { return (s == 0 || 2 * s < N) ? 0 : 1; }
+};
+
+// Entry i of sequence s of the line whose slots start at ls.
 template <typename T, int N, int K>
-__device__ __forceinline__ T fwd_seq(const T* ln, int s, int j) {
-  if (j <= 0 || j >= K || s >= N) return T(0);
-  if (s == 0) return ln[N * j - 1];
-  return ln[N * j + s - 1] + ln[N * (j - 1) + (N - s) - 1];
+__device__ __forceinline__ T& at(cx<T>* ls, int s, int i) {
+  cx<T>& e = ls[Seq<N>::pair(s) * K + sw(i)];
+  return Seq<N>::part(s) ? e.y : e.x;
 }
 
-// Value of sequence s at wave number j from a coefficient-ordered line in LDS
-// after the inverse block (W_j at q = N-1 + j-1, d_j component s at
-// q = N-1 + s (K-1) + j-1).
-template <typename T, int N, int K>
-__device__ __forceinline__ T inv_seq(const T* ln, int s, int j) {
-  if (j <= 0 || j >= K || s >= N) return T(0);
-  return ln[(N - 1) + s * (K - 1) + j - 1];
+// Input of the direct sine transforms of a pair at index j = 1..K-1, from
+// its entries e = entry j and f = entry j-1.  Interior pair (s, N-s):
+// z_j = y_{j+1/2} + P y_{j-1/2}, i.e. (y_s[j] + y_{N-s}[j-1], y_{N-s}[j] +
+// y_s[j-1]); node pair: (node j, y_{N/2}[j] + y_{N/2}[j-1]) for even N,
+// (node j, 0) for odd N.
+template <typename T, int N>
+__device__ __forceinline__ cx<T> fwd_in(bool interior, cx<T> e, cx<T> f) {
+  // selects rather than branches: `interior` is uniform per task only
+  const T re = e.x + (interior ? f.y : T(0));
+  T im = e.y + (interior ? f.x : f.y);
+  if constexpr (N % 2 == 1) im = interior ? im : T(0);
+  return {re, im};
+}
+
+// Input of the inverse sine transforms of a pair (the imaginary part of the
+// node pair carries no sequence for odd N).
+template <typename T, int N>
+__device__ __forceinline__ cx<T> inv_in(bool interior, cx<T> e) {
+  if constexpr (N % 2 == 1) {
+    if (!interior) return {e.x, T(0)};
+  }
+  return e;
 }
 
 // Sine-transform pre-processing of one pair at index j.
@@ -421,17 +470,6 @@ __device__ __forceinline__ cx<T> dst_pre(cx<T> xj, cx<T> xkj, T snj, int j) {
           snj * (xj.y + xkj.y) + T(0.5) * (xj.y - xkj.y)};
 }
 
-// The N sine-transform outputs of one line (its slots) at wave number k.
-template <typename T, int N, int K>
-__device__ __forceinline__ void read_seqs(const cx<T>* ls, int k, T (&x)[N]) {
-#pragma unroll
-  for (int p = 0; p < (N + 1) / 2; ++p) {
-    const cx<T> v = ls[p * K + sw(k)];
-    x[2 * p] = v.x;
-    if (2 * p + 1 < N) x[2 * p + 1] = v.y;
-  }
-}
-
 // Entry e of the blocked table at wave number k (see AxisTab).
 template <int N>
 __device__ __forceinline__ size_t blk_base(int k) {
@@ -439,28 +477,18 @@ __device__ __forceinline__ size_t blk_base(int k) {
   return (size_t)((k - 1) >> 6) * (NE * 64) + ((k - 1) & 63);
 }
 
-// Direct-transform coefficients at wave number k >= 1:
-// acc[l] = (x_0 + sum_s p_k^(l)_s x_s) / ||s_k^(l)||^2.
-template <typename T, int N>
-__device__ __forceinline__ void fwd_block(const T* __restrict__ tb, const T (&x)[N],
-                                          T (&acc)[N]) {
+// The first NT entries of wave number k's table (all of them issued at once).
+template <typename T, int NT>
+__device__ __forceinline__ void load_tab(const T* __restrict__ tb, T (&tab)[NT]) {
 #pragma unroll
-  for (int l = 0; l < N; ++l) {
-    T s = x[0];
-#pragma unroll
-    for (int i = 1; i < N; ++i) s += tb[(l * (N - 1) + i - 1) * 64] * x[i];
-    acc[l] = s * tb[(N * (N - 1) + l) * 64];
-  }
+  for (int e = 0; e < NT; ++e) tab[e] = tb[e * 64];
 }
 
 // Inverse-transform combination at k >= 1: y_0 = sum_l w_l,
 // y_s = sum_l w_l p_k^(l)_s.
 template <typename T, int N>
-__device__ __forceinline__ void inv_block(const T* __restrict__ tb, const T (&w)[N], T (&y)[N]) {
-  constexpr int NP_ = N * (N - 1);
-  T tab[NP_ > 0 ? NP_ : 1];
-#pragma unroll
-  for (int e = 0; e < NP_; ++e) tab[e] = tb[e * 64];
+__device__ __forceinline__ void inv_apply(const T (&tab)[N * (N - 1) > 0 ? N * (N - 1) : 1],
+                                          const T (&w)[N], T (&y)[N]) {
 #pragma unroll
   for (int i = 0; i < N; ++i) y[i] = T(0);
 #pragma unroll
@@ -471,33 +499,57 @@ __device__ __forceinline__ void inv_block(const T* __restrict__ tb, const T (&w)
   }
 }
 
-// Fused pass at k >= 1: direct coefficients, division by the FP64
-// denominators dbase + sc lamk[l], inverse combination.  The wave number's
-// table entries are all loaded first (one read each, every load in flight at
-// once) and then used for both products.
-template <typename T, int N>
-__device__ __forceinline__ void fused_block(const T* __restrict__ tb, const double* __restrict__ lk,
-                                            int K, double dbase, double sc, const T (&x)[N],
-                                            T (&y)[N]) {
-  constexpr int NE = N * (N - 1) + N;
-  T tab[NE];
-  double lam[N];
-#pragma unroll
-  for (int e = 0; e < NE; ++e) tab[e] = tb[e * 64];
-#pragma unroll
-  for (int l = 0; l < N; ++l) lam[l] = lk[(size_t)l * (K - 1)];
-#pragma unroll
-  for (int i = 0; i < N; ++i) y[i] = T(0);
+// Direct-transform coefficients at wave number k >= 1 for NL lines,
+// acc[u][l] = (x_0 + sum_s p_k^(l)_s x_s) / ||s_k^(l)||^2, and the fused
+// form: division by the FP64 denominators dbase[u] + sc lam_k^(l), then the
+// inverse combination y_0 = sum_l w_l, y_s = sum_l w_l p_k^(l)_s.  The row of
+// eigenvector l (its N-1 entries, its norm and its eigenvalue) is read once
+// per l and applied to every line.
+template <typename T, int N, int NL>
+__device__ __forceinline__ void fwd_lines(const T* __restrict__ tb, const T (&x)[NL][N],
+                                          T (&acc)[NL][N]) {
 #pragma unroll
   for (int l = 0; l < N; ++l) {
-    T s = x[0];
+    T p[N > 1 ? N - 1 : 1];
 #pragma unroll
-    for (int i = 1; i < N; ++i) s += tab[l * (N - 1) + i - 1] * x[i];
-    s *= tab[N * (N - 1) + l];
-    const T w = (T)((double)s / (dbase + sc * lam[l]));
-    y[0] += w;
+    for (int i = 1; i < N; ++i) p[i - 1] = tb[(l * (N - 1) + i - 1) * 64];
+    const T nrm = tb[(N * (N - 1) + l) * 64];
 #pragma unroll
-    for (int i = 1; i < N; ++i) y[i] += w * tab[l * (N - 1) + i - 1];
+    for (int u = 0; u < NL; ++u) {
+      T s = x[u][0];
+#pragma unroll
+      for (int i = 1; i < N; ++i) s += p[i - 1] * x[u][i];
+      acc[u][l] = s * nrm;
+    }
+  }
+}
+
+template <typename T, int N, int NL>
+__device__ __forceinline__ void fused_lines(const T* __restrict__ tb, const double* __restrict__ lk,
+                                            int lstride, const double (&dbase)[NL], double sc,
+                                            const T (&x)[NL][N], T (&y)[NL][N]) {
+#pragma unroll
+  for (int u = 0; u < NL; ++u)
+#pragma unroll
+    for (int i = 0; i < N; ++i) y[u][i] = T(0);
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    T p[N > 1 ? N - 1 : 1];
+#pragma unroll
+    for (int i = 1; i < N; ++i) p[i - 1] = tb[(l * (N - 1) + i - 1) * 64];
+    const T nrm = tb[(N * (N - 1) + l) * 64];
+    const double lam = lk[(size_t)l * lstride];
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      T s = x[u][0];
+#pragma unroll
+      for (int i = 1; i < N; ++i) s += p[i - 1] * x[u][i];
+      s *= nrm;
+      const T w = (T)((double)s / (dbase[u] + sc * lam));
+      y[u][0] += w;
+#pragma unroll
+      for (int i = 1; i < N; ++i) y[u][i] += w * p[i - 1];
+    }
   }
 }
 
@@ -507,12 +559,22 @@ template <typename T, int LOG2K>
 constexpr int log2_rmax() { return (sizeof(T) == 8 && LOG2K <= 9) ? 3 : 4; }
 
 // Register budget: four waves per SIMD (two 512-lane workgroups per CU, up
-// to 128 VGPRs), except in FP64 for single-line passes and orders >= 7,
-// whose per-wave-number tables alone take 2 n^2 registers (two waves).
+// to 128 VGPRs), except in FP64 for K = 1024 and orders >= 7, whose
+// per-wave-number tables alone take 2 n^2 registers (two waves).
+constexpr int waves_per_simd_of(bool f64, int n, int log2K) {
+  return f64 ? ((log2K <= 9 && n <= 6) ? 4 : 2) : 4;
+}
 template <typename T, int N, int LOG2K, int MODE>
-constexpr int waves_per_simd() {
-  if (sizeof(T) == 8) return (LOG2K <= 9 && N <= 6) ? 4 : 2;
-  return 4;
+constexpr int waves_per_simd() { return waves_per_simd_of(sizeof(T) == 8, N, LOG2K); }
+
+// Lines per workgroup in the "tight" layout (at most).
+constexpr int kTight = 2;
+
+// Layout of a line of order n with K elements: padded when two or more fit
+// in 64 KB (two or more workgroups per CU), tight (no padding, the per-line
+// quantities in registers) otherwise.
+constexpr bool tight_layout(int n, int K, int cplx_bytes) {
+  return (64 * 1024) / (((n + 1) / 2 * K + 1) * cplx_bytes) < 2;
 }
 
 template <typename T, int N, int LOG2K, int MODE, typename TIN, typename TOUT>
@@ -522,7 +584,9 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
   using S = FftShape<LOG2K, LRM>;
   constexpr int K = S::K, R = S::R, G = S::G;
   constexpr int TPW = 64 / G;          // tasks per wavefront
-  constexpr int NP = (N + 1) / 2;      // slot pairs per line
+  constexpr int NP = Seq<N>::NP;       // slot pairs per line
+  constexpr int NE = N * (N - 1) + N;  // table entries per wave number
+  constexpr int NPE = N * (N - 1) > 0 ? N * (N - 1) : 1;
   constexpr int M = N * K - 1;         // line length
   constexpr int KM = K - 1;
   constexpr int kUnroll = unroll_for<T, LOG2K>();
@@ -533,13 +597,12 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
   const long long inner = a.inner;
   const int cb = a.cb;            // a power of two
   const int lcb = __builtin_ctz(cb);
-  // One line per workgroup ("tight"): LDS holds the slots and nothing else,
-  // so that two workgroups with the largest lines share a CU; the line's
-  // address and denominator live in registers and the k = 0 quantities S0
-  // and E0 in the index-0 entries of the slots, which no sine transform
-  // output occupies.  Several lines: one pad entry per line (spreads the
-  // lines over the LDS banks) and small arrays after the slots.
-  const bool tight = cb == 1;
+  // Tight layout (lines too long for several per 64 KB): LDS holds the slots
+  // and nothing else, the lines' addresses and denominators live in
+  // registers.  Otherwise one pad entry per line (spreads the lines over the
+  // LDS banks) and the per-line address and denominator after the slots.
+  constexpr bool tight = tight_layout(N, 1 << LOG2K, (int)sizeof(cx<T>));
+  constexpr int NLB = kTight;   // lines per table read (tight)
   const int lsp = tight ? NP * K : NP * K + 1;   // complex entries per line
   // Workgroups are dealt round-robin to the 8 XCDs (each with its own L2):
   // renumber them so that every XCD walks one contiguous range of lines, and
@@ -552,13 +615,10 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
   const bool cfast = inner != 1;
 
   cx<T>* slots = reinterpret_cast<cx<T>*>(smem);
-  T* lines = reinterpret_cast<T*>(smem);        // line c at lines + c * 2 * lsp
-  T* s0 = reinterpret_cast<T*>(slots + (size_t)cb * lsp);   // [cb][8] (not tight)
-  T* e0 = s0 + cb * 8;                                      // [cb][8] (not tight)
-  long long* base = reinterpret_cast<long long*>(e0 + cb * 8);   // [cb] (not tight)
-  double* denb = reinterpret_cast<double*>(base + cb);           // [cb] (not tight)
-  // index-0 store of sequence-pair entries of line 0 (tight): value s < N-1
-  auto i0 = [&](int s) -> T& { return lines[(size_t)(s >> 1) * 2 * K + (s & 1)]; };
+  long long* base = reinterpret_cast<long long*>(slots + (size_t)cb * lsp);   // [cb] (not tight)
+  double* denb = reinterpret_cast<double*>(base + cb);                        // [cb] (not tight)
+  T* e0a = reinterpret_cast<T*>(denb + cb);                                   // [cb][8] (not tight)
+  auto lslots = [&](int c) -> cx<T>* { return slots + (size_t)c * lsp; };
 
   const T* __restrict__ BLK = static_cast<const T*>(a.tab.blk);
   const T* __restrict__ EV = static_cast<const T*>(a.tab.E);
@@ -567,40 +627,73 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
   const TIN* __restrict__ src = static_cast<const TIN*>(a.in);
   TOUT* __restrict__ dst = static_cast<TOUT*>(a.out);
 
-  // this lane's FFT task: (line tc, slot pair tp), lane j of G
   const int lane = tid & 63;
-  const int task = wave * TPW + lane / G;
-  const int j = lane & (G - 1);
-  const bool task_ok = task < cb * NP;
-  const int tc = task_ok ? task / NP : 0;
-  const int tp = task - tc * NP;
-  cx<T>* tbuf = slots + (size_t)tc * lsp + (size_t)tp * K;
-  T snr[R];   // DST pre-weights sin(pi jj / K) of this lane's task points
-  task_sines<T, K, R>(SN, j, snr);
+  const int j = lane & (G - 1);        // lane within the FFT task
+  const int ntask = cv * NP;           // tasks: (line, slot pair)
+  const int per_round = nwaves * TPW;
 
   auto line_den = [&](long long t) -> double {
     double d = a.alpha;
     for (int i = 0; i < a.nother; ++i) d += a.oscale[i] * a.olam[i][(t / a.odiv[i]) % a.omod[i]];
     return d;
   };
-  long long base1 = 0;
-  double den1 = 0.0;
-  if (tight) {
-    const long long o = L0 / inner, t = L0 - o * inner;
-    base1 = o * (long long)M * inner + t;
-    if (MODE == PASS_FUSED) den1 = line_den(t);
+  // tight: every lane computes the lines' addresses and denominators, held
+  // in scalar registers
+  long long tbase[kTight];
+  double tden[kTight];
+  if constexpr (tight) {
+#pragma unroll
+    for (int u = 0; u < kTight; ++u) {
+      const long long L = L0 + (u < cv ? u : 0);
+      const long long o = L / inner, t = L - o * inner;
+      tbase[u] = uni(o * (long long)M * inner + t);
+      tden[u] = (MODE == PASS_FUSED) ? uni(line_den(t)) : 0.0;
+    }
   } else if (tid < cv) {
     const long long L = L0 + tid;
     const long long o = L / inner, t = L - o * inner;
     base[tid] = o * (long long)M * inner + t;
     if (MODE == PASS_FUSED) denb[tid] = line_den(t);
   }
-  auto lbase = [&](int c) -> long long { return tight ? base1 : base[c]; };
-  auto lden = [&](int c) -> double { return tight ? den1 : denb[c]; };
-  auto s0v = [&](int c, int s) -> T { return tight ? i0(s) : s0[c * 8 + s]; };
-  auto e0v = [&](int c, int s) -> T { return tight ? i0(s) : e0[c * 8 + s]; };
+  auto lbase = [&](int c) -> long long {
+    if (!tight) return base[c];
+    long long b = tbase[0];
+#pragma unroll
+    for (int u = 1; u < kTight; ++u)
+      if (c == u) b = tbase[u];
+    return b;
+  };
+  auto lden = [&](int c) -> double {
+    if (!tight) return denb[c];
+    double d = tden[0];
+#pragma unroll
+    for (int u = 1; u < kTight; ++u)
+      if (c == u) d = tden[u];
+    return d;
+  };
+  // LDS entry of input value q of line c: physical order (node j at
+  // q = N j - 1, interior point s of element e at q = N (e-1) + s - 1) or
+  // coefficient order (inverse pass).
+  auto in_entry = [&](int c, int q) -> T& {
+    int s, i;
+    if (MODE == PASS_INV) {
+      if (q < N - 1) {
+        s = q;
+        i = 0;
+      } else {
+        const int r = q - (N - 1);
+        s = r / KM;
+        i = r - s * KM + 1;
+      }
+    } else {
+      const int g = q + 1;
+      s = g % N;
+      i = g / N;
+    }
+    return at<T, N, K>(lslots(c), s, i);
+  };
 
-  // ---- load the cv lines (physical or coefficient order) ------------------
+  // ---- load the cv lines into their sequences ------------------------------
   // Contiguous axis: the cv lines are one contiguous range, swept by all
   // lanes.  Strided axis: lane (q, c) with c = tid mod cb, so adjacent lanes
   // read adjacent lines (adjacent in memory).  kUnroll loads in flight per
@@ -620,7 +713,7 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
         const int i = i00 + u * nthr;
         if (i < total) {
           const int c = i / M, q = i - c * M;
-          lines[(size_t)c * 2 * lsp + q] = (T)r[u];
+          in_entry(c, q) = (T)r[u];
         }
       }
     }
@@ -631,7 +724,6 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
     const int qs = nthr >> lcb;
     if (c < cv) {
       const TIN* sp = src + lbase(c);
-      T* d = lines + (size_t)c * 2 * lsp;
       for (int q0 = tid >> lcb; q0 < M; q0 += kUnroll * qs) {
         TIN r[kUnroll];
 #pragma unroll
@@ -642,90 +734,187 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           const int q = q0 + u * qs;
-          if (q < M) d[q] = (T)r[u];
+          if (q < M) in_entry(c, q) = (T)r[u];
         }
       }
     }
     __syncthreads();
   }
 
-  cx<T> v[R];
-  T e0r[N > 1 ? N - 1 : 1];   // tight: E0 of the line, in thread 0
-
-  if (MODE == PASS_FWD || MODE == PASS_FUSED) {
-    // ---- forward pre-combine + sine pre-processing, into registers -------
-    if (task_ok) {
-      const T* ln = lines + (size_t)tc * 2 * lsp;
-      const bool live = tc < cv;
+  // E0 of the lines, from the k = 0 quantities at entry 0 of the sequences
+  // (S0 in the fused pass, the coefficients w_{0l} in the inverse pass);
+  // entry 0 is scratch space of the inverse transforms, so E0 waits in
+  // scalar registers (tight) or in e0a (padded layout) until the scatter.
+  T e0s[kTight][N > 1 ? N - 1 : 1];
+  auto line_e0 = [&](int c, T (&e0)[N > 1 ? N - 1 : 1]) {
+    if constexpr (N > 1) {
+      cx<T>* ls = lslots(c);
+      T w0[N - 1];
+      if (MODE == PASS_FUSED) {
+        // w_{0l} = S0 . e^(l) / K divided by its denominator
+        T s0l[N - 1];
 #pragma unroll
-      for (int t = 0; t < R; ++t) {
-        const int jj = j + G * t;
-        cx<T> xj = {fwd_seq<T, N, K>(ln, 2 * tp, jj), fwd_seq<T, N, K>(ln, 2 * tp + 1, jj)};
-        cx<T> xk = {fwd_seq<T, N, K>(ln, 2 * tp, K - jj),
-                    fwd_seq<T, N, K>(ln, 2 * tp + 1, K - jj)};
-        v[t] = live ? dst_pre(xj, xk, snr[t], jj) : cx<T>{T(0), T(0)};
+        for (int s = 0; s < N - 1; ++s) s0l[s] = at<T, N, K>(ls, s + 1, 0);
+#pragma unroll
+        for (int l = 0; l < N - 1; ++l) {
+          T acc = T(0);
+#pragma unroll
+          for (int s = 0; s < N - 1; ++s) acc += EV[s * (N - 1) + l] * s0l[s];
+          acc /= (T)K;
+          const double den = lden(c) + a.scale * a.tab.lam[l];
+          w0[l] = (T)((double)acc / den);
+        }
+      } else {
+#pragma unroll
+        for (int l = 0; l < N - 1; ++l) w0[l] = at<T, N, K>(ls, l, 0);
+      }
+#pragma unroll
+      for (int s = 0; s < N - 1; ++s) {
+        T acc = T(0);
+#pragma unroll
+        for (int l = 0; l < N - 1; ++l) acc += EV[s * (N - 1) + l] * w0[l];
+        e0[s] = acc;
       }
     }
-    // S0_s = sum_{j=1..K} ((-P)^{j-1} y_{j-1/2})_s, one wave per (line, s);
-    // tight: a wave keeps its (at most two) sums in registers until the
-    // slots' index-0 entries are free.
+  };
+  auto keep_e0 = [&]() {
+    if constexpr (N > 1) {
+      if constexpr (tight) {
+#pragma unroll
+        for (int u = 0; u < kTight; ++u) {
+          T e[N - 1];
+          line_e0(u < cv ? u : 0, e);
+#pragma unroll
+          for (int s = 0; s < N - 1; ++s) e0s[u][s] = uni(e[s]);
+        }
+      } else if (tid < cv) {
+        T e[N - 1];
+        line_e0(tid, e);
+#pragma unroll
+        for (int s = 0; s < N - 1; ++s) e0a[tid * 8 + s] = e[s];
+      }
+    }
+  };
+
+  if (MODE == PASS_FWD || MODE == PASS_FUSED) {
+    // ---- S0_s = sum_{e=1..K} ((-P)^(e-1) y_{e-1/2})_s ----------------------
+    // = sum_e (-1)^(e-1) y_{e-1/2, s (e odd) or N-s (e even)}: one wave per
+    // (line, component); the sum waits in scalar registers (tight: at most
+    // two per wave) or in s0a until the transforms have freed entry 0.
     T s0r[2] = {T(0), T(0)};
     if constexpr (N > 1) {
       int r = 0;
-      for (int task0 = wave; task0 < cv * (N - 1); task0 += nwaves, ++r) {
-        const int c = task0 / (N - 1), s = task0 - c * (N - 1) + 1;
-        const T* ln = lines + (size_t)c * 2 * lsp;
+      for (int w0 = wave; w0 < cv * (N - 1); w0 += nwaves, ++r) {
+        const int c = w0 / (N - 1), s = w0 - c * (N - 1) + 1;
+        cx<T>* ls = lslots(c);
         T acc = T(0);
-        for (int jj = 1 + lane; jj <= K; jj += 64) {
-          const bool odd = jj & 1;
-          const T val = ln[N * (jj - 1) + (odd ? s : N - s) - 1];
-          acc += odd ? val : -val;
+        for (int e = 1 + lane; e <= K; e += 64) {
+          const T val = (e & 1) ? at<T, N, K>(ls, s, e - 1) : -at<T, N, K>(ls, N - s, e - 1);
+          acc += val;
         }
-        acc = wave_sum(acc);
-        if (tight) {
+        acc = uni(wave_sum(acc));
+        if constexpr (tight) {
           if (r == 0) s0r[0] = acc; else s0r[1] = acc;
         } else if (lane == 0) {
-          s0[c * 8 + s - 1] = acc;
+          e0a[c * 8 + s - 1] = acc;
         }
+      }
+      __syncthreads();   // the sums read entries that the transforms overwrite
+    }
+    // ---- direct sine transforms, one task per (line, pair) ---------------
+    // A task reads its pair into registers (forward pre-combine and sine
+    // pre-processing) and transforms it in place.
+    for (int t0 = 0; t0 < ntask; t0 += per_round) {
+      const int task = t0 + wave * TPW + lane / G;
+      if (task < ntask) {
+        const int tc = task / NP, tp = task - tc * NP;
+        const bool interior = tp < NP - 1;
+        cx<T>* tb = lslots(tc) + (size_t)tp * K;
+        int j = lane & (G - 1);
+        asm volatile("" : "+v"(j));   // keeps the lane's address arithmetic inside the loop
+        T snr[R];   // DST pre-weights sin(pi jj / K) of this lane's task points
+        task_sines<T, K, R>(SN, j, snr);
+        cx<T> v[R];
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+          const int jj = j + G * t;
+          const cx<T> e0 = tb[sw(jj)], e1 = tb[sw((jj - 1) & (K - 1))];
+          const cx<T> m0 = tb[sw((K - jj) & (K - 1))], m1 = tb[sw((K - jj - 1) & (K - 1))];
+          v[t] = dst_pre(fwd_in<T, N>(interior, e0, e1), fwd_in<T, N>(interior, m0, m1), snr[t], jj);
+        }
+        wave_sync();
+        task_fft<T, LOG2K, LRM>(v, tb, j, TW);
+        task_post<T, LOG2K, LRM>(tb, j);
       }
     }
     __syncthreads();
-    if (task_ok) {
-      task_fft<T, LOG2K, LRM>(v, tbuf, j, TW);
-      task_post<T, LOG2K, LRM>(tbuf, j);
-    }
-    __syncthreads();
+    // S0 into entry 0 of its component
     if constexpr (N > 1) {
-      if (tight) {
+      if constexpr (tight) {
         if (lane == 0) {
-          if (wave < N - 1) i0(wave) = s0r[0];
-          if (wave + nwaves < N - 1) i0(wave + nwaves) = s0r[1];
+          int r = 0;
+          for (int w0 = wave; w0 < cv * (N - 1); w0 += nwaves, ++r) {
+            const int c = w0 / (N - 1), s = w0 - c * (N - 1) + 1;
+            at<T, N, K>(lslots(c), s, 0) = r == 0 ? s0r[0] : s0r[1];
+          }
         }
-        __syncthreads();
+      } else {
+        for (int i = tid; i < cv * (N - 1); i += nthr) {
+          const int c = i / (N - 1), s = i - c * (N - 1) + 1;
+          at<T, N, K>(lslots(c), s, 0) = e0a[c * 8 + s - 1];
+        }
       }
+      __syncthreads();
     }
 
     if (MODE == PASS_FWD) {
       // ---- forward block, coefficients to global -------------------------
-      // contiguous axis: k fastest over the lanes (l-major output order);
-      // strided axis: line c fastest (adjacent lines adjacent in memory)
-      const int items = cv * KM;
-      for (int i = tid; i < (cfast ? cb * KM : items); i += nthr) {
-        int c, k;
-        if (cfast) {
-          c = i & (cb - 1);
-          k = (i >> lcb) + 1;
-          if (c >= cv) continue;
-        } else {
-          c = i / KM;
-          k = i - c * KM + 1;
-        }
-        T x[N], acc[N];
-        read_seqs<T, N, K>(slots + (size_t)c * lsp, k, x);
-        fwd_block<T, N>(BLK + blk_base<N>(k), x, acc);
-        const long long ob = lbase(c) + ((long long)(N - 1) + (k - 1)) * inner;
+      if constexpr (tight) {
+        // one wave number per lane; its table entries are read once for
+        // all the lines
+        for (int k = 1 + tid; k < K; k += nthr) {
 #pragma unroll
-        for (int l = 0; l < N; ++l) dst[ob + (long long)l * KM * inner] = (TOUT)acc[l];
+          for (int u0 = 0; u0 < kTight; u0 += NLB) {
+            if (u0 < cv) {
+              T x[NLB][N], acc[NLB][N];
+#pragma unroll
+              for (int u = 0; u < NLB; ++u)
+#pragma unroll
+                for (int s = 0; s < N; ++s) x[u][s] = at<T, N, K>(lslots(u0 + u < cv ? u0 + u : 0), s, k);
+              fwd_lines<T, N, NLB>(BLK + blk_base<N>(k), x, acc);
+#pragma unroll
+              for (int u = 0; u < NLB; ++u) {
+                if (u0 + u < cv) {
+                  const long long ob = tbase[u0 + u] + ((long long)(N - 1) + (k - 1)) * inner;
+#pragma unroll
+                  for (int l = 0; l < N; ++l) dst[ob + (long long)l * KM * inner] = (TOUT)acc[u][l];
+                }
+              }
+            }
+          }
+        }
+      } else {
+        // contiguous axis: k fastest over the lanes (l-major output order);
+        // strided axis: line c fastest (adjacent lines adjacent in memory)
+        const int items = cv * KM;
+        for (int i = tid; i < (cfast ? cb * KM : items); i += nthr) {
+          int c, k;
+          if (cfast) {
+            c = i & (cb - 1);
+            k = (i >> lcb) + 1;
+            if (c >= cv) continue;
+          } else {
+            c = i / KM;
+            k = i - c * KM + 1;
+          }
+          T x[1][N], acc[1][N];
+#pragma unroll
+          for (int s = 0; s < N; ++s) x[0][s] = at<T, N, K>(lslots(c), s, k);
+          fwd_lines<T, N, 1>(BLK + blk_base<N>(k), x, acc);
+          const long long ob = base[c] + ((long long)(N - 1) + (k - 1)) * inner;
+#pragma unroll
+          for (int l = 0; l < N; ++l) dst[ob + (long long)l * KM * inner] = (TOUT)acc[0][l];
+        }
       }
       // k = 0: w_{0l} = S0 . e^(l) / K
       if constexpr (N > 1) {
@@ -734,7 +923,7 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
           const int c = i / (N - 1), l = i - c * (N - 1);
           T acc = T(0);
 #pragma unroll
-          for (int s = 0; s < N - 1; ++s) acc += EV[s * (N - 1) + l] * s0v(c, s);
+          for (int s = 0; s < N - 1; ++s) acc += EV[s * (N - 1) + l] * at<T, N, K>(lslots(c), s + 1, 0);
           dst[lbase(c) + (long long)l * inner] = (TOUT)(acc / (T)K);
         }
       }
@@ -745,129 +934,138 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
     {
       const double sc = a.scale;
       const double* __restrict__ lam = a.tab.lam;
+      if constexpr (tight) {
+        for (int k = 1 + tid; k < K; k += nthr) {
+#pragma unroll
+          for (int u0 = 0; u0 < kTight; u0 += NLB) {
+            if (u0 < cv) {
+              T x[NLB][N], y[NLB][N];
+              double dn[NLB];
+#pragma unroll
+              for (int u = 0; u < NLB; ++u) {
+                dn[u] = tden[u0 + u];
+#pragma unroll
+                for (int s = 0; s < N; ++s) x[u][s] = at<T, N, K>(lslots(u0 + u < cv ? u0 + u : 0), s, k);
+              }
+              fused_lines<T, N, NLB>(BLK + blk_base<N>(k), lam + (N - 1) + (k - 1), KM, dn, sc, x, y);
+#pragma unroll
+              for (int u = 0; u < NLB; ++u) {
+                if (u0 + u < cv) {
+#pragma unroll
+                  for (int s = 0; s < N; ++s) at<T, N, K>(lslots(u0 + u), s, k) = y[u][s];
+                }
+              }
+            }
+          }
+        }
+      } else {
+        const int items = cv * KM;
+        for (int i = tid; i < items; i += nthr) {
+          const int c = i / KM, k = i - c * KM + 1;
+          cx<T>* ls = lslots(c);
+          T x[1][N], y[1][N];
+          const double dn[1] = {denb[c]};
+#pragma unroll
+          for (int s = 0; s < N; ++s) x[0][s] = at<T, N, K>(ls, s, k);
+          fused_lines<T, N, 1>(BLK + blk_base<N>(k), lam + (N - 1) + (k - 1), KM, dn, sc, x, y);
+#pragma unroll
+          for (int s = 0; s < N; ++s) at<T, N, K>(ls, s, k) = y[0][s];
+        }
+      }
+      keep_e0();
+      __syncthreads();
+    }
+  } else {
+    // ---- inverse: block in place on the coefficients ---------------------
+    // (coefficient (l, k) is entry k of sequence l-1; the block at k turns
+    // them into the entries k of the N sequences)
+    if constexpr (tight) {
+      for (int k = 1 + tid; k < K; k += nthr) {
+        T tab[NPE];
+        load_tab<T, NPE>(BLK + blk_base<N>(k), tab);
+#pragma unroll
+        for (int u = 0; u < kTight; ++u) {
+          if (u < cv) {
+            cx<T>* ls = lslots(u);
+            T w[N], y[N];
+#pragma unroll
+            for (int l = 0; l < N; ++l) w[l] = at<T, N, K>(ls, l, k);
+            inv_apply<T, N>(tab, w, y);
+#pragma unroll
+            for (int s = 0; s < N; ++s) at<T, N, K>(ls, s, k) = y[s];
+          }
+        }
+      }
+    } else {
       const int items = cv * KM;
       for (int i = tid; i < items; i += nthr) {
         const int c = i / KM, k = i - c * KM + 1;
-        cx<T>* ls = slots + (size_t)c * lsp;
-        T x[N], y[N];
-        read_seqs<T, N, K>(ls, k, x);
-        fused_block<T, N>(BLK + blk_base<N>(k), lam + (N - 1) + (k - 1), K, lden(c), sc, x, y);
+        cx<T>* ls = lslots(c);
+        T tab[NPE], w[N], y[N];
+        load_tab<T, NPE>(BLK + blk_base<N>(k), tab);
 #pragma unroll
-        for (int s = 0; s < N; ++s) {
-          cx<T>& sl = ls[(s >> 1) * K + sw(k)];
-          if (s & 1) sl.y = y[s]; else sl.x = y[s];
-        }
-        if (N & 1) ls[(NP - 1) * K + sw(k)].y = T(0);
-      }
-      if constexpr (N > 1) {
-        if (tid < cv) {
-          const int c = tid;
-          T s0l[N - 1], w0[N - 1];
+        for (int l = 0; l < N; ++l) w[l] = at<T, N, K>(ls, l, k);
+        inv_apply<T, N>(tab, w, y);
 #pragma unroll
-          for (int s = 0; s < N - 1; ++s) s0l[s] = s0v(c, s);
-#pragma unroll
-          for (int l = 0; l < N - 1; ++l) {
-            T acc = T(0);
-#pragma unroll
-            for (int s = 0; s < N - 1; ++s) acc += EV[s * (N - 1) + l] * s0l[s];
-            acc /= (T)K;
-            const double den = lden(c) + sc * lam[l];
-            w0[l] = (T)((double)acc / den);
-          }
-#pragma unroll
-          for (int s = 0; s < N - 1; ++s) {
-            T acc = T(0);
-#pragma unroll
-            for (int l = 0; l < N - 1; ++l) acc += EV[s * (N - 1) + l] * w0[l];
-            if (tight) e0r[s] = acc; else e0[c * 8 + s] = acc;
-          }
-        }
-      }
-      __syncthreads();
-      // sine pre-processing of the task's own (W, d) pair, in registers (the
-      // weights are recomputed here rather than held across the block phase)
-      task_sines<T, K, R>(SN, j, snr);
-      if (task_ok) {
-#pragma unroll
-        for (int t = 0; t < R; ++t) {
-          const int jj = j + G * t;
-          v[t] = dst_pre(tbuf[sw(jj)], tbuf[sw((K - jj) & (K - 1))], snr[t], jj);
-        }
-        wave_sync();
+        for (int s = 0; s < N; ++s) at<T, N, K>(ls, s, k) = y[s];
       }
     }
-  } else {
-    // ---- inverse: block in place on the coefficient line -----------------
-    // (thread of wave number k reads and writes the entries N-1 + l(K-1) + k-1)
-    const int items = cv * KM;
-    for (int i = tid; i < items; i += nthr) {
-      const int c = i / KM, k = i - c * KM + 1;
-      T* ln = lines + (size_t)c * 2 * lsp + (N - 1) + (k - 1);
-      T w[N], y[N];
-#pragma unroll
-      for (int l = 0; l < N; ++l) w[l] = ln[l * KM];
-      inv_block<T, N>(BLK + blk_base<N>(k), w, y);
-#pragma unroll
-      for (int s = 0; s < N; ++s) ln[s * KM] = y[s];
-    }
-    if constexpr (N > 1) {
-      if (tid < cv) {
-        const int c = tid;
-        const T* ln = lines + (size_t)c * 2 * lsp;
-#pragma unroll
-        for (int s = 0; s < N - 1; ++s) {
-          T acc = T(0);
-#pragma unroll
-          for (int l = 0; l < N - 1; ++l) acc += EV[s * (N - 1) + l] * ln[l];
-          if (tight) e0r[s] = acc; else e0[c * 8 + s] = acc;
-        }
-      }
-    }
-    __syncthreads();
-    if (task_ok) {
-      const T* ln = lines + (size_t)tc * 2 * lsp;
-      const bool live = tc < cv;
-#pragma unroll
-      for (int t = 0; t < R; ++t) {
-        const int jj = j + G * t;
-        cx<T> xj = {inv_seq<T, N, K>(ln, 2 * tp, jj), inv_seq<T, N, K>(ln, 2 * tp + 1, jj)};
-        cx<T> xk = {inv_seq<T, N, K>(ln, 2 * tp, K - jj),
-                    inv_seq<T, N, K>(ln, 2 * tp + 1, K - jj)};
-        v[t] = live ? dst_pre(xj, xk, snr[t], jj) : cx<T>{T(0), T(0)};
-      }
-    }
+    keep_e0();   // coefficient (l, 0) is entry 0 of sequence l-1
     __syncthreads();
   }
 
-  // ---- inverse sine transforms and scatter to the physical line ----------
-  if (task_ok) {
-    task_fft<T, LOG2K, LRM>(v, tbuf, j, TW);
-    task_post<T, LOG2K, LRM>(tbuf, j);
+  // ---- inverse sine transforms, one task per (line, pair) ------------------
+  for (int t0 = 0; t0 < ntask; t0 += per_round) {
+    const int task = t0 + wave * TPW + lane / G;
+    if (task < ntask) {
+      const int tc = task / NP, tp = task - tc * NP;
+      const bool interior = tp < NP - 1;
+      cx<T>* tb = lslots(tc) + (size_t)tp * K;
+      int j = lane & (G - 1);
+      asm volatile("" : "+v"(j));   // keeps the lane's address arithmetic inside the loop
+      T snr[R];
+      task_sines<T, K, R>(SN, j, snr);
+      cx<T> v[R];
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        const int jj = j + G * t;
+        v[t] = dst_pre(inv_in<T, N>(interior, tb[sw(jj)]),
+                       inv_in<T, N>(interior, tb[sw((K - jj) & (K - 1))]), snr[t], jj);
+      }
+      wave_sync();
+      task_fft<T, LOG2K, LRM>(v, tb, j, TW);
+      task_post<T, LOG2K, LRM>(tb, j);
+    }
   }
   __syncthreads();
   if constexpr (N > 1) {
-    if (tight) {
-      if (tid == 0) {
+    if (tid < cv) {
+      cx<T>* ls = lslots(tid);
+      if constexpr (tight) {
 #pragma unroll
-        for (int s = 0; s < N - 1; ++s) i0(s) = e0r[s];
+        for (int u = 0; u < kTight; ++u)
+          if (tid == u) {
+#pragma unroll
+            for (int s = 1; s < N; ++s) at<T, N, K>(ls, s, 0) = e0s[u][s - 1];
+          }
+      } else {
+#pragma unroll
+        for (int s = 1; s < N; ++s) at<T, N, K>(ls, s, 0) = e0a[tid * 8 + s - 1];
       }
-      __syncthreads();
     }
+    __syncthreads();
   }
   {
-    // value at position g = q + 1 = N jn + s of line c (s = 0: mesh node)
+    // value at position g = q + 1 = N jn + s of line c (s = 0: mesh node):
+    // node jn, or Z_s[e-1] + Z_{N-s}[e] + (-P)^(e-1) E0 for element e = jn + 1
     auto value = [&](int c, int q) -> T {
+      cx<T>* ls = lslots(c);
       const int g = q + 1, jn = g / N, s = g - jn * N;
-      const cx<T>* ls = slots + (size_t)c * lsp;
-      auto seq = [&](int sq, int k) -> T {
-        const cx<T> w = ls[(sq >> 1) * K + sw(k)];
-        return (sq & 1) ? w.y : w.x;
-      };
-      if (s == 0) return seq(0, jn);
-      const int je = jn + 1;   // element
-      const T zl = (je - 1 >= 1) ? seq(s, je - 1) : T(0);
-      const T zr = (je <= K - 1) ? seq(N - s, je) : T(0);
-      const T ee = (je & 1) ? e0v(c, s - 1) : -e0v(c, (N - s) - 1);
+      if (s == 0) return at<T, N, K>(ls, 0, jn);
+      const int je = jn + 1;
+      const T zl = (je - 1 >= 1) ? at<T, N, K>(ls, s, je - 1) : T(0);
+      const T zr = (je <= K - 1) ? at<T, N, K>(ls, N - s, je) : T(0);
+      const T ee = (je & 1) ? at<T, N, K>(ls, s, 0) : -at<T, N, K>(ls, N - s, 0);
       return zl + zr + ee;
     };
     if (!cfast) {
@@ -889,41 +1087,58 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
 }
 
 struct Shape {
-  int cb, threads;
+  int cb, threads, tight;
   size_t lds;
 };
 
+// Lines per workgroup and LDS bytes.  Lines that fit two or more to 64 KB
+// (two or more workgroups per CU) use the padded layout; longer lines use the
+// tight one with as many lines (at most kTight) as the CU's LDS share of one
+// workgroup holds: 160 KB divided by the workgroups per CU that the register
+// budget allows.
 inline Shape shape_for(int n, int K, size_t cplx_bytes, long long nlines) {
   const int NP = (n + 1) / 2;
-  const int rmax = (cplx_bytes == 16 && K <= 512) ? 8 : 16;   // as log2_rmax
+  const bool f64 = cplx_bytes == 16;
+  const int rmax = (f64 && K <= 512) ? 8 : 16;   // as log2_rmax
   const int R = K < rmax ? K : rmax;
   const int G = K / R;
   const int TPW = 64 / G;
+  const int threads = f64 ? threads_for<double>() : threads_for<float>();
   const size_t per_line = ((size_t)NP * K + 1) * cplx_bytes;
-  // LDS: about 64 KB per workgroup (two or more workgroups per CU); a line
-  // that needs more gets a workgroup of its own.
-  long long c = (long long)((64 * 1024) / per_line);
-  const int threads = cplx_bytes == 16 ? threads_for<double>() : threads_for<float>();
-  // every FFT task of the workgroup runs at once
-  c = std::min<long long>(c, (long long)(threads / 64) * TPW / NP);
-  c = std::min<long long>(c, kMaxCB);
-  c = std::min<long long>(c, nlines);
-  if (c < 1) c = 1;
-  while (c & (c - 1)) c &= c - 1;   // round down to a power of two
   Shape s;
-  s.cb = (int)c;
   s.threads = threads;
-  if (c == 1)   // slots only (see line_pass)
-    s.lds = (size_t)NP * K * cplx_bytes;
-  else
-    s.lds = (size_t)c * per_line + (size_t)c * 16 * (cplx_bytes / 2) + (size_t)c * 16;
+  long long c = (long long)((64 * 1024) / per_line);
+  if (!tight_layout(n, K, (int)cplx_bytes)) {
+    // every FFT task of the workgroup in one round
+    c = std::min<long long>(c, (long long)(threads / 64) * TPW / NP);
+    c = std::min<long long>(c, kMaxCB);
+    c = std::min<long long>(c, nlines);
+    if (c < 1) c = 1;
+    while (c & (c - 1)) c &= c - 1;   // round down to a power of two
+    s.cb = (int)c;
+    s.tight = 0;
+    s.lds = (size_t)c * per_line + (size_t)c * 16 + (size_t)c * 8 * (cplx_bytes / 2);
+    return s;
+  }
+  int log2K = 0;
+  while ((1 << log2K) < K) ++log2K;
+  const int wgs = std::max(1, waves_per_simd_of(f64, n, log2K) * 4 / (threads / 64));
+  const size_t budget = (size_t)(160 * 1024) / wgs;
+  const size_t tl = (size_t)NP * K * cplx_bytes;
+  c = 1;
+  while (c * 2 <= kTight && (size_t)(c * 2) * tl <= budget && c * 2 <= nlines) c *= 2;
+  s.cb = (int)c;
+  s.tight = 1;
+  s.lds = (size_t)c * tl;
   return s;
 }
 
 template <typename T, int N, int LOG2K, int MODE, typename TIN, typename TOUT>
-hipError_t launch_k(const PassArgs& a, hipStream_t s) {
-  const Shape sh = shape_for(N, 1 << LOG2K, sizeof(cx<T>), a.nlines);
-  if (sh.cb != a.cb || a.tab.n != N || a.tab.K != (1 << LOG2K)) return hipErrorInvalidValue;
+hipError_t launch_k(const PassArgs& a0, hipStream_t s) {
+  const Shape sh = shape_for(N, 1 << LOG2K, sizeof(cx<T>), a0.nlines);
+  if (a0.tab.n != N || a0.tab.K != (1 << LOG2K)) return hipErrorInvalidValue;
+  PassArgs a = a0;
+  a.cb = sh.cb;
   auto fn = line_pass<T, N, LOG2K, MODE, TIN, TOUT>;
   static bool lds_raised = false;   // benign race: every caller sets the same value
   if (!lds_raised) {

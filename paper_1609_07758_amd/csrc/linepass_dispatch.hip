@@ -1,5 +1,4 @@
-// Dispatch of the line passes to the per-order kernels, and their launch
-// shape (lines per workgroup, LDS bytes).
+// Dispatch of the line passes to the per-order kernels.
 #include "linepass.h"
 
 namespace hofem {
@@ -17,14 +16,6 @@ hipError_t launch_pass(int kind, int dt, const PassArgs& a, hipStream_t s) {
     case 9: return launch_pass_order<9>(kind, dt, a, s);
     default: return hipErrorInvalidValue;
   }
-}
-
-void pass_shape(int n, int K, int is_f64, long long nlines, long long inner, int* cb,
-                size_t* lds_bytes) {
-  (void)inner;
-  const lp::Shape s = lp::shape_for(n, K, is_f64 ? 16 : 8, nlines);
-  *cb = s.cb;
-  *lds_bytes = s.lds;
 }
 
 }  // namespace hofem
