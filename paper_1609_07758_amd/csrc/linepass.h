@@ -60,9 +60,12 @@ constexpr int kMaxCB = 64;         // lines per workgroup (upper bound)
 template <typename T>
 constexpr int threads_for() { return 512; }
 // global loads in flight per lane: one round for the workgroup's values
-// (at most 64 KB of lines per workgroup unless a single line needs more)
-template <typename T, int LOG2K>
-constexpr int unroll_for() { return (sizeof(T) == 8 && LOG2K >= 10) ? 32 : 16; }
+// (at most 64 KB of lines per workgroup in the padded layout; the tight
+// layout's two lines take ceil(2 (nK - 1) / 512) per lane)
+template <typename T, int N, int LOG2K, bool TIGHT>
+constexpr int unroll_for() {
+  return TIGHT ? (2 * (N * (1 << LOG2K) - 1) + 511) / 512 : (sizeof(T) == 8 && LOG2K >= 10) ? 32 : 16;
+}
 constexpr unsigned kXcds = 8;      // accelerator complex dies of an MI355X
 
 template <typename T>
@@ -589,7 +592,8 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
   constexpr int NPE = N * (N - 1) > 0 ? N * (N - 1) : 1;
   constexpr int M = N * K - 1;         // line length
   constexpr int KM = K - 1;
-  constexpr int kUnroll = unroll_for<T, LOG2K>();
+  constexpr bool tight = tight_layout(N, 1 << LOG2K, (int)sizeof(cx<T>));
+  constexpr int kUnroll = unroll_for<T, N, LOG2K, tight>();
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x;
   const int nthr = blockDim.x;
@@ -601,7 +605,6 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
   // and nothing else, the lines' addresses and denominators live in
   // registers.  Otherwise one pad entry per line (spreads the lines over the
   // LDS banks) and the per-line address and denominator after the slots.
-  constexpr bool tight = tight_layout(N, 1 << LOG2K, (int)sizeof(cx<T>));
   constexpr int NLB = kTight;   // lines per table read (tight)
   const int lsp = tight ? NP * K : NP * K + 1;   // complex entries per line
   // Workgroups are dealt round-robin to the 8 XCDs (each with its own L2):
@@ -808,6 +811,7 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
         const int c = w0 / (N - 1), s = w0 - c * (N - 1) + 1;
         cx<T>* ls = lslots(c);
         T acc = T(0);
+#pragma unroll
         for (int e = 1 + lane; e <= K; e += 64) {
           const T val = (e & 1) ? at<T, N, K>(ls, s, e - 1) : -at<T, N, K>(ls, N - s, e - 1);
           acc += val;
@@ -1058,29 +1062,54 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
   {
     // value at position g = q + 1 = N jn + s of line c (s = 0: mesh node):
     // node jn, or Z_s[e-1] + Z_{N-s}[e] + (-P)^(e-1) E0 for element e = jn + 1
+    // (branch free: every read is in range and the unused terms are masked)
     auto value = [&](int c, int q) -> T {
       cx<T>* ls = lslots(c);
       const int g = q + 1, jn = g / N, s = g - jn * N;
-      if (s == 0) return at<T, N, K>(ls, 0, jn);
+      const bool inter = s != 0;
       const int je = jn + 1;
-      const T zl = (je - 1 >= 1) ? at<T, N, K>(ls, s, je - 1) : T(0);
-      const T zr = (je <= K - 1) ? at<T, N, K>(ls, N - s, je) : T(0);
-      const T ee = (je & 1) ? at<T, N, K>(ls, s, 0) : -at<T, N, K>(ls, N - s, 0);
-      return zl + zr + ee;
+      const int s2 = inter ? N - s : 0;
+      const T z1 = at<T, N, K>(ls, s, jn);                      // node jn, or Z_s[e-1]
+      const T z2 = at<T, N, K>(ls, s2, je < K ? je : K - 1);    // Z_{N-s}[e]
+      const T ee = at<T, N, K>(ls, (je & 1) ? s : s2, 0);        // E0_s or E0_{N-s}
+      T v = jn >= 1 ? z1 : T(0);
+      v += (inter && je <= K - 1) ? z2 : T(0);
+      v += inter ? ((je & 1) ? ee : -ee) : T(0);
+      return v;
     };
+    constexpr int SU = 8;   // values gathered before their stores are issued
     if (!cfast) {
       TOUT* d = dst + L0 * M;
       const int total = cv * M;
-      for (int i = tid; i < total; i += nthr) {
-        const int c = i / M, q = i - c * M;
-        d[i] = (TOUT)value(c, q);
+      for (int i0 = tid; i0 < total; i0 += SU * nthr) {
+        T val[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+          const int i = min(i0 + u * nthr, total - 1);
+          const int c = i / M, q = i - c * M;
+          val[u] = value(c, q);
+        }
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+          const int i = i0 + u * nthr;
+          if (i < total) d[i] = (TOUT)val[u];
+        }
       }
     } else {
       const int c = tid & (cb - 1);
       const int qs = nthr >> lcb;
       if (c < cv) {
         TOUT* d = dst + lbase(c);
-        for (int q = tid >> lcb; q < M; q += qs) d[(long long)q * inner] = (TOUT)value(c, q);
+        for (int q0 = tid >> lcb; q0 < M; q0 += SU * qs) {
+          T val[SU];
+#pragma unroll
+          for (int u = 0; u < SU; ++u) val[u] = value(c, min(q0 + u * qs, M - 1));
+#pragma unroll
+          for (int u = 0; u < SU; ++u) {
+            const int q = q0 + u * qs;
+            if (q < M) d[(long long)q * inner] = (TOUT)val[u];
+          }
+        }
       }
     }
   }
