@@ -802,51 +802,75 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
   if (MODE == PASS_FWD || MODE == PASS_FUSED) {
     // ---- S0_s = sum_{e=1..K} ((-P)^(e-1) y_{e-1/2})_s ----------------------
     // = sum_e (-1)^(e-1) y_{e-1/2, s (e odd) or N-s (e even)}: one wave per
-    // (line, component); the sum waits in scalar registers (tight: at most
-    // two per wave) or in s0a until the transforms have freed entry 0.
+    // (line, component), read from the loaded entries before the transforms
+    // overwrite them.  The sums wait in scalar registers (tight layout, at
+    // most two per wave) or in e0a until the transforms have freed entry 0.
     T s0r[2] = {T(0), T(0)};
-    if constexpr (N > 1) {
-      int r = 0;
-      for (int w0 = wave; w0 < cv * (N - 1); w0 += nwaves, ++r) {
-        const int c = w0 / (N - 1), s = w0 - c * (N - 1) + 1;
-        cx<T>* ls = lslots(c);
-        T acc = T(0);
+    auto s0_sums = [&]() {
+      if constexpr (N > 1) {
+        int r = 0;
+        for (int w0 = wave; w0 < cv * (N - 1); w0 += nwaves, ++r) {
+          const int c = w0 / (N - 1), s = w0 - c * (N - 1) + 1;
+          cx<T>* ls = lslots(c);
+          T acc = T(0);
 #pragma unroll
-        for (int e = 1 + lane; e <= K; e += 64) {
-          const T val = (e & 1) ? at<T, N, K>(ls, s, e - 1) : -at<T, N, K>(ls, N - s, e - 1);
-          acc += val;
-        }
-        acc = uni(wave_sum(acc));
-        if constexpr (tight) {
-          if (r == 0) s0r[0] = acc; else s0r[1] = acc;
-        } else if (lane == 0) {
-          e0a[c * 8 + s - 1] = acc;
+          for (int e = 1 + lane; e <= K; e += 64) {
+            const T val = at<T, N, K>(ls, (e & 1) ? s : N - s, e - 1);
+            acc += (e & 1) ? val : -val;
+          }
+          acc = uni(wave_sum(acc));
+          if constexpr (tight) {
+            if (r == 0) s0r[0] = acc; else s0r[1] = acc;
+          } else if (lane == 0) {
+            e0a[c * 8 + s - 1] = acc;
+          }
         }
       }
-      __syncthreads();   // the sums read entries that the transforms overwrite
-    }
-    // ---- direct sine transforms, one task per (line, pair) ---------------
-    // A task reads its pair into registers (forward pre-combine and sine
-    // pre-processing) and transforms it in place.
-    for (int t0 = 0; t0 < ntask; t0 += per_round) {
-      const int task = t0 + wave * TPW + lane / G;
-      if (task < ntask) {
-        const int tc = task / NP, tp = task - tc * NP;
-        const bool interior = tp < NP - 1;
-        cx<T>* tb = lslots(tc) + (size_t)tp * K;
-        int j = lane & (G - 1);
-        asm volatile("" : "+v"(j));   // keeps the lane's address arithmetic inside the loop
-        T snr[R];   // DST pre-weights sin(pi jj / K) of this lane's task points
-        task_sines<T, K, R>(SN, j, snr);
-        cx<T> v[R];
+    };
+    // Direct sine transforms, one task per (line, pair): a task reads its
+    // pair into registers (forward pre-combine and sine pre-processing) and
+    // transforms it in place.
+    auto fwd_read = [&](cx<T>* tb, bool interior, int j, cx<T> (&v)[R]) {
+      T snr[R];   // DST pre-weights sin(pi jj / K) of this lane's task points
+      task_sines<T, K, R>(SN, j, snr);
 #pragma unroll
-        for (int t = 0; t < R; ++t) {
-          const int jj = j + G * t;
-          const cx<T> e0 = tb[sw(jj)], e1 = tb[sw((jj - 1) & (K - 1))];
-          const cx<T> m0 = tb[sw((K - jj) & (K - 1))], m1 = tb[sw((K - jj - 1) & (K - 1))];
-          v[t] = dst_pre(fwd_in<T, N>(interior, e0, e1), fwd_in<T, N>(interior, m0, m1), snr[t], jj);
+      for (int t = 0; t < R; ++t) {
+        const int jj = j + G * t;
+        const cx<T> e0 = tb[sw(jj)], e1 = tb[sw((jj - 1) & (K - 1))];
+        const cx<T> m0 = tb[sw((K - jj) & (K - 1))], m1 = tb[sw((K - jj - 1) & (K - 1))];
+        v[t] = dst_pre(fwd_in<T, N>(interior, e0, e1), fwd_in<T, N>(interior, m0, m1), snr[t], jj);
+      }
+    };
+    if constexpr (tight) {
+      // tasks in rounds: the sums first
+      s0_sums();
+      if constexpr (N > 1) __syncthreads();
+      for (int t0 = 0; t0 < ntask; t0 += per_round) {
+        const int task = t0 + wave * TPW + lane / G;
+        if (task < ntask) {
+          const int tc = task / NP, tp = task - tc * NP;
+          cx<T>* tb = lslots(tc) + (size_t)tp * K;
+          int j = lane & (G - 1);
+          asm volatile("" : "+v"(j));   // keeps the lane's address arithmetic inside the loop
+          cx<T> v[R];
+          fwd_read(tb, tp < NP - 1, j, v);
+          wave_sync();
+          task_fft<T, LOG2K, LRM>(v, tb, j, TW);
+          task_post<T, LOG2K, LRM>(tb, j);
         }
-        wave_sync();
+      }
+    } else {
+      // one round (the launch shape guarantees it): every task reads its
+      // pair, the sums overlap those reads, then the transforms
+      const int task = wave * TPW + lane / G;
+      const int tc = task / NP, tp = task - tc * NP;
+      cx<T>* tb = lslots(task < ntask ? tc : 0) + (size_t)tp * K;
+      const int j = lane & (G - 1);
+      cx<T> v[R];
+      if (task < ntask) fwd_read(tb, tp < NP - 1, j, v);
+      s0_sums();
+      __syncthreads();
+      if (task < ntask) {
         task_fft<T, LOG2K, LRM>(v, tb, j, TW);
         task_post<T, LOG2K, LRM>(tb, j);
       }
@@ -1019,27 +1043,35 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
   }
 
   // ---- inverse sine transforms, one task per (line, pair) ------------------
-  for (int t0 = 0; t0 < ntask; t0 += per_round) {
-    const int task = t0 + wave * TPW + lane / G;
-    if (task < ntask) {
-      const int tc = task / NP, tp = task - tc * NP;
-      const bool interior = tp < NP - 1;
-      cx<T>* tb = lslots(tc) + (size_t)tp * K;
-      int j = lane & (G - 1);
-      asm volatile("" : "+v"(j));   // keeps the lane's address arithmetic inside the loop
-      T snr[R];
-      task_sines<T, K, R>(SN, j, snr);
-      cx<T> v[R];
+  auto inv_task = [&](int task, int j) {
+    const int tc = task / NP, tp = task - tc * NP;
+    const bool interior = tp < NP - 1;
+    cx<T>* tb = lslots(tc) + (size_t)tp * K;
+    T snr[R];
+    task_sines<T, K, R>(SN, j, snr);
+    cx<T> v[R];
 #pragma unroll
-      for (int t = 0; t < R; ++t) {
-        const int jj = j + G * t;
-        v[t] = dst_pre(inv_in<T, N>(interior, tb[sw(jj)]),
-                       inv_in<T, N>(interior, tb[sw((K - jj) & (K - 1))]), snr[t], jj);
-      }
-      wave_sync();
-      task_fft<T, LOG2K, LRM>(v, tb, j, TW);
-      task_post<T, LOG2K, LRM>(tb, j);
+    for (int t = 0; t < R; ++t) {
+      const int jj = j + G * t;
+      v[t] = dst_pre(inv_in<T, N>(interior, tb[sw(jj)]),
+                     inv_in<T, N>(interior, tb[sw((K - jj) & (K - 1))]), snr[t], jj);
     }
+    wave_sync();
+    task_fft<T, LOG2K, LRM>(v, tb, j, TW);
+    task_post<T, LOG2K, LRM>(tb, j);
+  };
+  if constexpr (tight) {
+    for (int t0 = 0; t0 < ntask; t0 += per_round) {
+      const int task = t0 + wave * TPW + lane / G;
+      if (task < ntask) {
+        int j = lane & (G - 1);
+        asm volatile("" : "+v"(j));   // keeps the lane's address arithmetic inside the loop
+        inv_task(task, j);
+      }
+    }
+  } else {
+    const int task = wave * TPW + lane / G;   // one round (launch shape)
+    if (task < ntask) inv_task(task, lane & (G - 1));
   }
   __syncthreads();
   if constexpr (N > 1) {
