@@ -53,6 +53,7 @@ struct DevAxis {
   AxisTab t64{}, t32{};
   const double* A = nullptr;
   const double* C = nullptr;
+  std::vector<double> hA, hC;   // host copies of A and C (kernel arguments)
   const double* B = nullptr;    // basis values at the Gauss nodes
   const double* D = nullptr;    // basis derivatives at the Gauss nodes
   const double* gw = nullptr;   // Gauss weights
@@ -220,6 +221,8 @@ int make_op(hofem_solver_s* S, const double* u, const double* f, void* out, int 
     o.scale[i] = S->ax[i].scale;
     o.A[i] = S->ax[i].A;
     o.C[i] = S->ax[i].C;
+    o.hA[i] = S->ax[i].hA.data();
+    o.hC[i] = S->ax[i].hC.data();
   }
   o.alpha = S->alpha;
   o.nrhs = nrhs;
@@ -494,6 +497,8 @@ int hofem_solver_create(int N, const hofem_plan1d* plans, const double* X, doubl
     const double h = X[i] / d.K;
     ax.scale = 4.0 / (h * h);
     S->per_rhs *= (size_t)d.m;
+    ax.hA = d.A;
+    ax.hC = d.C;
     // per-wave-number tables blocked by 64 wave numbers (layout in kernels.h)
     const int n = d.n, K = d.K;
     const size_t NE = (size_t)n * (n - 1) + n, nblk = ((size_t)K - 1 + 63) / 64;

@@ -83,6 +83,8 @@ struct OpArgs {
   double alpha;
   const double* A[3];  // local stiffness (n_i+1)^2, device
   const double* C[3];  // local mass (n_i+1)^2, device
+  const double* hA[3]; // the same, host copies (passed by value to kernels)
+  const double* hC[3];
   int nrhs;
   // 3D with equal orders: per-element outputs of one right-hand side,
   // prod K_i (n+1)^3 doubles (op3_elem_doubles), device
