@@ -294,189 +294,6 @@ __global__ __launch_bounds__(256) void op2_tiled_kernel(OpArgs a, Tile2 tl) {
 }
 
 // ---------------------------------------------------------------------------
-// 2D operator for equal orders n0 = n1 = NO (compile time), by element tiles
-// of TE x TE owned elements (plus the next element along each axis, whose
-// first node line holds owned points), every contraction one row or column
-// per lane with the 1D matrices as uniform (scalar) operands:
-//   1. per staged element, D0[i][r1] = sum_{r0 != i} A0[i][r0] (u[r0][r1] - u[i][r1])
-//      (one column r1 per lane) and
-//      D1[r0][i] = s1 sum_{r1 != i} A1[i][r1] (u[r0][r1] - u[r0][i]) + alpha sum_{r1} C1[i][r1] u[r0][r1]
-//      (one row r0 per lane);
-//   2. E[a0][a1] = s0 sum_{r1} C1[a1][r1] D0[a0][r1]   (one row a0 per lane, in place of D0),
-//      then E[a0][a1] += sum_{r0} C0[a0][r0] D1[r0][a1]  (one column a1 per lane);
-//   3. per owned point, the sum of E over the 1, 2 or 4 elements holding it.
-// E is the element row of s0 A0 (x) C1 + C0 (x) (s1 A1 + alpha C1) with every
-// stiffness factor applied to u first; the sum over elements has a fixed
-// order (deterministic).
-// ---------------------------------------------------------------------------
-
-constexpr int kOp2Threads = 512;
-
-template <int NO>
-struct Op2Shape {
-  static constexpr int B = NO + 1;
-  // owned elements per tile side: LDS = staged points + two b x b blocks per
-  // staged element, within 64 KB
-  static constexpr int lds_doubles(int te) {
-    return (NO * (te + 1) + 1) * (NO * (te + 1) + 1) + 2 * (te + 1) * (te + 1) * B * B;
-  }
-  static constexpr int TE = lds_doubles(8) * 8 <= 65536   ? 8
-                            : lds_doubles(6) * 8 <= 65536 ? 6
-                            : lds_doubles(4) * 8 <= 65536 ? 4
-                            : lds_doubles(3) * 8 <= 65536 ? 3
-                            : lds_doubles(2) * 8 <= 65536 ? 2
-                                                          : 1;
-  static constexpr int LDS = lds_doubles(TE) * 8;
-};
-
-template <int NO>
-__global__ __launch_bounds__(kOp2Threads) void op2_order_kernel(OpArgs a, int nt1) {
-  using SH = Op2Shape<NO>;
-  constexpr int B = SH::B, TE = SH::TE, BB = B * B;
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int K0 = a.K[0], K1 = a.K[1], m0 = a.m[0], m1 = a.m[1];
-  const int t0 = blockIdx.x / nt1, t1 = blockIdx.x - t0 * nt1;
-  const long long roff = (long long)blockIdx.y * m0 * m1;
-  const int E0 = t0 * TE, E1 = t1 * TE;                         // first element (0-based)
-  const int ne0 = min(TE + 1, K0 - E0), ne1 = min(TE + 1, K1 - E1);
-  constexpr int PS = NO * (TE + 1) + 1;                         // staged points per side
-  const int g00 = NO * E0, g10 = NO * E1;                       // position of local point 0
-  double* U = reinterpret_cast<double*>(smem);                  // [PS][PS]
-  double* D0 = U + PS * PS;                                     // [ne][B][B], then E
-  double* D1 = D0 + (TE + 1) * (TE + 1) * BB;                   // [ne][B][B]
-  const int tid = threadIdx.x;
-  const double* __restrict__ A0 = a.A[0];
-  const double* __restrict__ C0 = a.C[0];
-  const double* __restrict__ A1 = a.A[1];
-  const double* __restrict__ C1 = a.C[1];
-  const double s0 = a.scale[0], s1 = a.scale[1], al = a.alpha;
-
-  const double* __restrict__ u = a.u + roff;
-  for (int i = tid; i < PS * PS; i += kOp2Threads) {
-    const int i0 = i / PS, i1 = i - i0 * PS;
-    const int g0 = g00 + i0, g1 = g10 + i1;
-    double v = 0.0;
-    if (g0 >= 1 && g0 <= m0 && g1 >= 1 && g1 <= m1) v = u[(long long)(g0 - 1) * m1 + (g1 - 1)];
-    U[i] = v;
-  }
-  __syncthreads();
-
-  const int ne = ne0 * ne1;
-  // 1. stiffness-first contractions of u
-  for (int task = tid; task < 2 * ne * B; task += kOp2Threads) {
-    const int kind = task / (ne * B), rest = task - kind * ne * B;
-    const int el = rest / B, line = rest - el * B;
-    const int l0 = el / ne1, l1 = el - l0 * ne1;
-    const double* Ue = U + (l0 * NO) * PS + l1 * NO;
-    double v[B];
-    if (kind == 0) {            // column line = r1: D0[i][r1]
-#pragma unroll
-      for (int r = 0; r < B; ++r) v[r] = Ue[r * PS + line];
-      double* out = D0 + el * BB + line;
-#pragma unroll
-      for (int i = 0; i < B; ++i) {
-        double t = 0.0;
-#pragma unroll
-        for (int r = 0; r < B; ++r)
-          if (r != i) t += A0[i * B + r] * (v[r] - v[i]);
-        out[i * B] = t;
-      }
-    } else {                    // row line = r0: D1[r0][i]
-#pragma unroll
-      for (int r = 0; r < B; ++r) v[r] = Ue[line * PS + r];
-      double* out = D1 + el * BB + line * B;
-#pragma unroll
-      for (int i = 0; i < B; ++i) {
-        double t = 0.0, mm = 0.0;
-#pragma unroll
-        for (int r = 0; r < B; ++r) {
-          if (r != i) t += A1[i * B + r] * (v[r] - v[i]);
-          mm += C1[i * B + r] * v[r];
-        }
-        out[i] = s1 * t + al * mm;
-      }
-    }
-  }
-  __syncthreads();
-  // 2a. E[a0][:] = s0 D0[a0][:] C1^T (row per lane, in place)
-  for (int task = tid; task < ne * B; task += kOp2Threads) {
-    const int el = task / B, a0 = task - el * B;
-    double* row = D0 + el * BB + a0 * B;
-    double v[B];
-#pragma unroll
-    for (int r = 0; r < B; ++r) v[r] = row[r];
-#pragma unroll
-    for (int a1 = 0; a1 < B; ++a1) {
-      double t = 0.0;
-#pragma unroll
-      for (int r = 0; r < B; ++r) t += C1[a1 * B + r] * v[r];
-      row[a1] = s0 * t;
-    }
-  }
-  __syncthreads();
-  // 2b. E[:][a1] += C0 D1[:][a1] (column per lane)
-  for (int task = tid; task < ne * B; task += kOp2Threads) {
-    const int el = task / B, a1 = task - el * B;
-    const double* col = D1 + el * BB + a1;
-    double* ecol = D0 + el * BB + a1;
-    double v[B];
-#pragma unroll
-    for (int r = 0; r < B; ++r) v[r] = col[r * B];
-#pragma unroll
-    for (int a0 = 0; a0 < B; ++a0) {
-      double t = 0.0;
-#pragma unroll
-      for (int r = 0; r < B; ++r) t += C0[a0 * B + r] * v[r];
-      ecol[a0 * B] += t;
-    }
-  }
-  __syncthreads();
-  // 3. owned points: local positions p = 1 .. NO TE per axis
-  constexpr int OWN = NO * TE;
-  const double* __restrict__ f = a.f ? a.f + roff : nullptr;
-  for (int i = tid; i < OWN * OWN; i += kOp2Threads) {
-    const int p0 = i / OWN + 1, p1 = i - (p0 - 1) * OWN + 1;
-    const int g0 = g00 + p0, g1 = g10 + p1;
-    if (g0 > m0 || g1 > m1) continue;
-    const int q0 = p0 / NO, r0 = p0 - q0 * NO;     // element q0, local r0 (r0 = 0: node)
-    const int q1 = p1 / NO, r1 = p1 - q1 * NO;
-    double acc;
-    auto Ev = [&](int e0, int e1, int a0, int a1) {
-      return D0[(e0 * ne1 + e1) * BB + a0 * B + a1];
-    };
-    if (r0 != 0 && r1 != 0) {
-      acc = Ev(q0, q1, r0, r1);
-    } else if (r0 == 0 && r1 != 0) {
-      acc = Ev(q0 - 1, q1, NO, r1);
-      if (q0 < ne0) acc += Ev(q0, q1, 0, r1);
-    } else if (r0 != 0 && r1 == 0) {
-      acc = Ev(q0, q1 - 1, r0, NO);
-      if (q1 < ne1) acc += Ev(q0, q1, r0, 0);
-    } else {
-      acc = Ev(q0 - 1, q1 - 1, NO, NO);
-      if (q1 < ne1) acc += Ev(q0 - 1, q1, NO, 0);
-      if (q0 < ne0) {
-        acc += Ev(q0, q1 - 1, 0, NO);
-        if (q1 < ne1) acc += Ev(q0, q1, 0, 0);
-      }
-    }
-    const long long idx = (long long)(g0 - 1) * m1 + (g1 - 1);
-    const double res = f ? f[idx] - acc : acc;
-    if (a.out_f32) static_cast<float*>(a.out)[roff + idx] = (float)res;
-    else static_cast<double*>(a.out)[roff + idx] = res;
-  }
-}
-
-template <int NO>
-hipError_t launch_op2_order(const OpArgs& a, hipStream_t s) {
-  using SH = Op2Shape<NO>;
-  const int nt0 = (a.K[0] + SH::TE - 1) / SH::TE, nt1 = (a.K[1] + SH::TE - 1) / SH::TE;
-  hipLaunchKernelGGL(op2_order_kernel<NO>, dim3((unsigned)(nt0 * nt1), (unsigned)a.nrhs),
-                     dim3(kOp2Threads), SH::LDS, s, a, nt1);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
 // 2D operator for equal orders NO, sum-factorised along the two axes with the
 // assembled 1D matrices (A_g = sum_e A_e, C_g = sum_e C_e):
 //   L u = s0 (A0_g (x) C1_g) u + (C0_g (x) (s1 A1_g + alpha C1_g)) u
