@@ -499,17 +499,20 @@ int hofem_solver_create(int N, const hofem_plan1d* plans, const double* X, doubl
     S->per_rhs *= (size_t)d.m;
     ax.hA = d.A;
     ax.hC = d.C;
-    // per-wave-number tables blocked by 64 wave numbers (layout in kernels.h)
+    // per-wave-number tables blocked by 64 wave numbers, entries in pairs
+    // (layout in kernels.h)
     const int n = d.n, K = d.K;
-    const size_t NE = (size_t)n * (n - 1) + n, nblk = ((size_t)K - 1 + 63) / 64;
-    std::vector<double> blk(nblk * NE * 64, 0.0);
-    for (int k = 1; k < K; ++k) {
+    const size_t NE = (size_t)n * (n - 1) + n, NEP = (NE + 1) / 2, nblk = ((size_t)K - 1 + 63) / 64;
+    std::vector<double> blk(nblk * NEP * 64 * 2, 0.0);
+    auto put = [&](int k, size_t e, double v) {
       const size_t b = (size_t)(k - 1) / 64, o = (size_t)(k - 1) % 64;
+      blk[((b * NEP + e / 2) * 64 + o) * 2 + (e & 1)] = v;
+    };
+    for (int k = 1; k < K; ++k) {
       for (int l = 0; l < n; ++l) {
         for (int c = 0; c < n - 1; ++c)
-          blk[(b * NE + (size_t)l * (n - 1) + c) * 64 + o] =
-              d.p[((size_t)(k - 1) * n + l) * (n - 1) + c];
-        blk[(b * NE + (size_t)n * (n - 1) + l) * 64 + o] = d.inorm[(size_t)(k - 1) * n + l];
+          put(k, (size_t)l * (n - 1) + c, d.p[((size_t)(k - 1) * n + l) * (n - 1) + c]);
+        put(k, (size_t)n * (n - 1) + l, d.inorm[(size_t)(k - 1) * n + l]);
       }
     }
     off[i].lam = pk.add_f64(d.lam);

@@ -16,11 +16,13 @@ int record_hip_error(hipError_t e);
 // modes (l = 1..n-1), q = (n-1) + (l-1)(K-1) + (k-1) for k = 1..K-1 and
 // l = 1..n, i.e. for each l the wave numbers k are consecutive.
 //
-// The per-wave-number tables are blocked by 64 wave numbers (one wavefront):
-// entry e of wave number k sits at ((k-1)/64 * NE + e) * 64 + (k-1) % 64 with
-// NE = n(n-1) + n, e = (l-1)(n-1) + (i-1) for component i of p_k^(l) and
+// The per-wave-number tables are blocked by 64 wave numbers (one wavefront)
+// and hold their entries in pairs: entry e of wave number k sits at
+// (((k-1)/64 * NEP + e/2) * 64 + (k-1) % 64) * 2 + e % 2 with NE = n(n-1) + n,
+// NEP = ceil(NE / 2), e = (l-1)(n-1) + (i-1) for component i of p_k^(l) and
 // e = n(n-1) + l-1 for 1 / ||s_k^(l)||^2, so that a wavefront handling 64
-// consecutive k reads 64 consecutive values per entry.
+// consecutive k reads two entries per lane with one load, 64 consecutive
+// pairs.
 struct AxisTab {
   const void* blk;     // blocked p and 1/||s||^2 (T)
   const void* E;       // e^(l) columns, i (n-1) + l-1

@@ -473,18 +473,31 @@ __device__ __forceinline__ cx<T> dst_pre(cx<T> xj, cx<T> xkj, T snj, int j) {
           snj * (xj.y + xkj.y) + T(0.5) * (xj.y - xkj.y)};
 }
 
-// Entry e of the blocked table at wave number k (see AxisTab).
-template <int N>
-__device__ __forceinline__ size_t blk_base(int k) {
-  constexpr int NE = N * (N - 1) + N;
-  return (size_t)((k - 1) >> 6) * (NE * 64) + ((k - 1) & 63);
+// The per-wave-number tables hold entries in pairs (see AxisTab): one
+// 16-byte (FP64) or 8-byte (FP32) load brings two entries.
+template <typename T>
+struct alignas(2 * sizeof(T)) tpair {
+  T x, y;
+};
+
+// Pair 0 of wave number k's table; entry e is in pair e / 2.
+template <int N, typename T>
+__device__ __forceinline__ const tpair<T>* blk_at(const tpair<T>* blk, int k) {
+  constexpr int NEP = (N * (N - 1) + N + 1) / 2;
+  return blk + (size_t)((k - 1) >> 6) * (NEP * 64) + ((k - 1) & 63);
+}
+
+template <typename T>
+__device__ __forceinline__ T tab_e(const tpair<T>* __restrict__ tb, int e) {
+  const tpair<T> v = tb[(e >> 1) * 64];
+  return (e & 1) ? v.y : v.x;
 }
 
 // The first NT entries of wave number k's table (all of them issued at once).
 template <typename T, int NT>
-__device__ __forceinline__ void load_tab(const T* __restrict__ tb, T (&tab)[NT]) {
+__device__ __forceinline__ void load_tab(const tpair<T>* __restrict__ tb, T (&tab)[NT]) {
 #pragma unroll
-  for (int e = 0; e < NT; ++e) tab[e] = tb[e * 64];
+  for (int e = 0; e < NT; ++e) tab[e] = tab_e(tb, e);
 }
 
 // Inverse-transform combination at k >= 1: y_0 = sum_l w_l,
@@ -509,14 +522,14 @@ __device__ __forceinline__ void inv_apply(const T (&tab)[N * (N - 1) > 0 ? N * (
 // eigenvector l (its N-1 entries, its norm and its eigenvalue) is read once
 // per l and applied to every line.
 template <typename T, int N, int NL>
-__device__ __forceinline__ void fwd_lines(const T* __restrict__ tb, const T (&x)[NL][N],
+__device__ __forceinline__ void fwd_lines(const tpair<T>* __restrict__ tb, const T (&x)[NL][N],
                                           T (&acc)[NL][N]) {
 #pragma unroll
   for (int l = 0; l < N; ++l) {
     T p[N > 1 ? N - 1 : 1];
 #pragma unroll
-    for (int i = 1; i < N; ++i) p[i - 1] = tb[(l * (N - 1) + i - 1) * 64];
-    const T nrm = tb[(N * (N - 1) + l) * 64];
+    for (int i = 1; i < N; ++i) p[i - 1] = tab_e(tb, l * (N - 1) + i - 1);
+    const T nrm = tab_e(tb, N * (N - 1) + l);
 #pragma unroll
     for (int u = 0; u < NL; ++u) {
       T s = x[u][0];
@@ -528,7 +541,7 @@ __device__ __forceinline__ void fwd_lines(const T* __restrict__ tb, const T (&x)
 }
 
 template <typename T, int N, int NL>
-__device__ __forceinline__ void fused_lines(const T* __restrict__ tb, const double* __restrict__ lk,
+__device__ __forceinline__ void fused_lines(const tpair<T>* __restrict__ tb, const double* __restrict__ lk,
                                             int lstride, const double (&dbase)[NL], double sc,
                                             const T (&x)[NL][N], T (&y)[NL][N]) {
 #pragma unroll
@@ -539,8 +552,8 @@ __device__ __forceinline__ void fused_lines(const T* __restrict__ tb, const doub
   for (int l = 0; l < N; ++l) {
     T p[N > 1 ? N - 1 : 1];
 #pragma unroll
-    for (int i = 1; i < N; ++i) p[i - 1] = tb[(l * (N - 1) + i - 1) * 64];
-    const T nrm = tb[(N * (N - 1) + l) * 64];
+    for (int i = 1; i < N; ++i) p[i - 1] = tab_e(tb, l * (N - 1) + i - 1);
+    const T nrm = tab_e(tb, N * (N - 1) + l);
     const double lam = lk[(size_t)l * lstride];
 #pragma unroll
     for (int u = 0; u < NL; ++u) {
@@ -623,7 +636,7 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
   T* e0a = reinterpret_cast<T*>(denb + cb);                                   // [cb][8] (not tight)
   auto lslots = [&](int c) -> cx<T>* { return slots + (size_t)c * lsp; };
 
-  const T* __restrict__ BLK = static_cast<const T*>(a.tab.blk);
+  const tpair<T>* __restrict__ BLK = static_cast<const tpair<T>*>(a.tab.blk);
   const T* __restrict__ EV = static_cast<const T*>(a.tab.E);
   const cx<T>* __restrict__ TW = static_cast<const cx<T>*>(a.tab.tw);
   const T* __restrict__ SN = static_cast<const T*>(a.tab.sn);
@@ -909,7 +922,7 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
               for (int u = 0; u < NLB; ++u)
 #pragma unroll
                 for (int s = 0; s < N; ++s) x[u][s] = at<T, N, K>(lslots(u0 + u < cv ? u0 + u : 0), s, k);
-              fwd_lines<T, N, NLB>(BLK + blk_base<N>(k), x, acc);
+              fwd_lines<T, N, NLB>(blk_at<N>(BLK, k), x, acc);
 #pragma unroll
               for (int u = 0; u < NLB; ++u) {
                 if (u0 + u < cv) {
@@ -938,7 +951,7 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
           T x[1][N], acc[1][N];
 #pragma unroll
           for (int s = 0; s < N; ++s) x[0][s] = at<T, N, K>(lslots(c), s, k);
-          fwd_lines<T, N, 1>(BLK + blk_base<N>(k), x, acc);
+          fwd_lines<T, N, 1>(blk_at<N>(BLK, k), x, acc);
           const long long ob = base[c] + ((long long)(N - 1) + (k - 1)) * inner;
 #pragma unroll
           for (int l = 0; l < N; ++l) dst[ob + (long long)l * KM * inner] = (TOUT)acc[0][l];
@@ -975,7 +988,7 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
 #pragma unroll
                 for (int s = 0; s < N; ++s) x[u][s] = at<T, N, K>(lslots(u0 + u < cv ? u0 + u : 0), s, k);
               }
-              fused_lines<T, N, NLB>(BLK + blk_base<N>(k), lam + (N - 1) + (k - 1), KM, dn, sc, x, y);
+              fused_lines<T, N, NLB>(blk_at<N>(BLK, k), lam + (N - 1) + (k - 1), KM, dn, sc, x, y);
 #pragma unroll
               for (int u = 0; u < NLB; ++u) {
                 if (u0 + u < cv) {
@@ -995,7 +1008,7 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
           const double dn[1] = {denb[c]};
 #pragma unroll
           for (int s = 0; s < N; ++s) x[0][s] = at<T, N, K>(ls, s, k);
-          fused_lines<T, N, 1>(BLK + blk_base<N>(k), lam + (N - 1) + (k - 1), KM, dn, sc, x, y);
+          fused_lines<T, N, 1>(blk_at<N>(BLK, k), lam + (N - 1) + (k - 1), KM, dn, sc, x, y);
 #pragma unroll
           for (int s = 0; s < N; ++s) at<T, N, K>(ls, s, k) = y[0][s];
         }
@@ -1010,7 +1023,7 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
     if constexpr (tight) {
       for (int k = 1 + tid; k < K; k += nthr) {
         T tab[NPE];
-        load_tab<T, NPE>(BLK + blk_base<N>(k), tab);
+        load_tab<T, NPE>(blk_at<N>(BLK, k), tab);
 #pragma unroll
         for (int u = 0; u < kTight; ++u) {
           if (u < cv) {
@@ -1030,7 +1043,7 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
         const int c = i / KM, k = i - c * KM + 1;
         cx<T>* ls = lslots(c);
         T tab[NPE], w[N], y[N];
-        load_tab<T, NPE>(BLK + blk_base<N>(k), tab);
+        load_tab<T, NPE>(blk_at<N>(BLK, k), tab);
 #pragma unroll
         for (int l = 0; l < N; ++l) w[l] = at<T, N, K>(ls, l, k);
         inv_apply<T, N>(tab, w, y);
