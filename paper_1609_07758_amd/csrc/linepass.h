@@ -96,6 +96,18 @@ __device__ __forceinline__ cx<T> cmulk(cx<T> a, T c, T s) {   // a * (c + i s)
 // the pair separation) spread over all LDS banks.
 __device__ __forceinline__ int sw(int i) { return i ^ ((i >> 4) & 15); }
 
+// 16 bytes of consecutive values, for vector loads and stores.
+template <typename T>
+struct alignas(16) vec16 {
+  T v[16 / sizeof(T)];
+};
+
+// Elements of type T before the first 16-byte boundary at or after p.
+template <typename T>
+__device__ __forceinline__ int head16(const T* p) {
+  return (int)(((16 - ((unsigned long long)p & 15)) & 15) / sizeof(T));
+}
+
 // Orders LDS traffic of the lanes of one wavefront (the lanes of a task).
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -715,21 +727,35 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
   // read adjacent lines (adjacent in memory).  kUnroll loads in flight per
   // lane: one round for the longest lines.
   if (!cfast) {
+    // 16-byte loads from the first 16-byte boundary on; the elements before
+    // it and the last few one by one
     const TIN* sp = src + L0 * M;
     const int total = cv * M;
-    for (int i00 = tid; i00 < total; i00 += kUnroll * nthr) {
-      TIN r[kUnroll];
+    constexpr int VL = 16 / sizeof(TIN);
+    constexpr int kUV = (kUnroll + VL - 1) / VL;
+    const int h = min(head16(sp), total);
+    const int nv = (total - h) / VL;
+    const int tail0 = h + nv * VL;
+    auto put = [&](int i, TIN v) {
+      const int c = i / M, q = i - c * M;
+      in_entry(c, q) = (T)v;
+    };
+    if (tid < h) put(tid, sp[tid]);
+    if (tid < total - tail0) put(tail0 + tid, sp[tail0 + tid]);
+    const vec16<TIN>* vp = reinterpret_cast<const vec16<TIN>*>(sp + h);
+    for (int j00 = tid; j00 < nv; j00 += kUV * nthr) {
+      vec16<TIN> r[kUV];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int i = i00 + u * nthr;
-        r[u] = sp[i < total ? i : 0];
+      for (int u = 0; u < kUV; ++u) {
+        const int j = j00 + u * nthr;
+        r[u] = vp[j < nv ? j : 0];
       }
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int i = i00 + u * nthr;
-        if (i < total) {
-          const int c = i / M, q = i - c * M;
-          in_entry(c, q) = (T)r[u];
+      for (int u = 0; u < kUV; ++u) {
+        const int j = j00 + u * nthr;
+        if (j < nv) {
+#pragma unroll
+          for (int e = 0; e < VL; ++e) put(h + VL * j + e, r[u].v[e]);
         }
       }
     }
@@ -1124,20 +1150,33 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
     };
     constexpr int SU = 8;   // values gathered before their stores are issued
     if (!cfast) {
+      // 16-byte stores from the first 16-byte boundary on
       TOUT* d = dst + L0 * M;
       const int total = cv * M;
-      for (int i0 = tid; i0 < total; i0 += SU * nthr) {
-        T val[SU];
+      constexpr int VS = 16 / sizeof(TOUT);
+      constexpr int SUV = SU / VS > 0 ? SU / VS : 1;
+      const int h = min(head16(d), total);
+      const int nv = (total - h) / VS;
+      const int tail0 = h + nv * VS;
+      auto val_at = [&](int i) -> T {
+        const int c = i / M, q = i - c * M;
+        return value(c, q);
+      };
+      if (tid < h) d[tid] = (TOUT)val_at(tid);
+      if (tid < total - tail0) d[tail0 + tid] = (TOUT)val_at(tail0 + tid);
+      vec16<TOUT>* vd = reinterpret_cast<vec16<TOUT>*>(d + h);
+      for (int j0 = tid; j0 < nv; j0 += SUV * nthr) {
+        vec16<TOUT> val[SUV];
 #pragma unroll
-        for (int u = 0; u < SU; ++u) {
-          const int i = min(i0 + u * nthr, total - 1);
-          const int c = i / M, q = i - c * M;
-          val[u] = value(c, q);
+        for (int u = 0; u < SUV; ++u) {
+          const int j = min(j0 + u * nthr, nv - 1);
+#pragma unroll
+          for (int e = 0; e < VS; ++e) val[u].v[e] = (TOUT)val_at(h + VS * j + e);
         }
 #pragma unroll
-        for (int u = 0; u < SU; ++u) {
-          const int i = i0 + u * nthr;
-          if (i < total) d[i] = (TOUT)val[u];
+        for (int u = 0; u < SUV; ++u) {
+          const int j = j0 + u * nthr;
+          if (j < nv) vd[j] = val[u];
         }
       }
     } else {
