@@ -277,7 +277,7 @@ struct VarShape {
   static constexpr int B = NO + 1, BBB = B * B * B;
   static constexpr int EPW0 = 32768 / (4 * BBB * 8);
   static constexpr int EPW = EPW0 < 1 ? 1 : (EPW0 > 32 ? 32 : EPW0);
-  static constexpr int LDS = 4 * BBB * EPW * 8;
+  static constexpr int LDS = 5 * BBB * EPW * 8;
 };
 
 // dst[line, q] (+)= sum_r m(q, r) (src[line, r] - ref) along axis ax of the
@@ -321,6 +321,7 @@ __global__ __launch_bounds__(256) void varop3_order_kernel(VarOpArgs a, double* 
   double* X = U + EPW * BBB;
   double* Y = X + EPW * BBB;
   double* E = Y + EPW * BBB;
+  double* WA = E + EPW * BBB;   // quadrature weight times coefficient per Gauss point
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int K0 = a.K[0], K1 = a.K[1], K2 = a.K[2];
   const long long nel = (long long)K0 * K1 * K2;
@@ -341,22 +342,24 @@ __global__ __launch_bounds__(256) void varop3_order_kernel(VarOpArgs a, double* 
     U[t] = v;
   }
   __syncthreads();
-  // quadrature weight times coefficient (times s) at every Gauss point of the batch
-  auto weigh = [&](double* Z, double s) {
-    for (int t = tid; t < ne * BBB; t += nthr) {
-      const int el = t / BBB, Q = t - el * BBB;
-      const int q0 = Q / (B * B), q1 = (Q / B) % B, q2 = Q % B;
-      double wq = a.w[0][q0] * a.w[1][q1] * a.w[2][q2];
-      const long long eg = e0 + el;
-      if (a.kind == 1) {
-        const int k0 = (int)(eg / ((long long)K1 * K2)), rem = (int)(eg - (long long)k0 * K1 * K2);
-        const int k1 = rem / K2, k2 = rem - k1 * K2;
-        wq *= a.c0 + a.c1 * a.t[0][k0 * B + q0] * a.t[1][k1 * B + q1] * a.t[2][k2 * B + q2];
-      } else if (a.kind == 2) {
-        wq *= a.afull[eg * BBB + Q];
-      }
-      Z[t] *= s * wq;
+  // quadrature weight times coefficient at every Gauss point of the batch,
+  // once; each term then scales its values by it (times s)
+  for (int t = tid; t < ne * BBB; t += nthr) {
+    const int el = t / BBB, Q = t - el * BBB;
+    const int q0 = Q / (B * B), q1 = (Q / B) % B, q2 = Q % B;
+    double wq = a.w[0][q0] * a.w[1][q1] * a.w[2][q2];
+    const long long eg = e0 + el;
+    if (a.kind == 1) {
+      const int k0 = (int)(eg / ((long long)K1 * K2)), rem = (int)(eg - (long long)k0 * K1 * K2);
+      const int k1 = rem / K2, k2 = rem - k1 * K2;
+      wq *= a.c0 + a.c1 * a.t[0][k0 * B + q0] * a.t[1][k1 * B + q1] * a.t[2][k2 * B + q2];
+    } else if (a.kind == 2) {
+      wq *= a.afull[eg * BBB + Q];
     }
+    WA[t] = wq;
+  }
+  auto weigh = [&](double* Z, double s) {
+    for (int t = tid; t < ne * BBB; t += nthr) Z[t] *= s * WA[t];
   };
 #pragma unroll
   for (int term = 0; term < 3; ++term) {
