@@ -56,6 +56,7 @@ struct DevAxis {
   std::vector<double> hA, hC;   // host copies of A and C (kernel arguments)
   const double* B = nullptr;    // basis values at the Gauss nodes
   const double* D = nullptr;    // basis derivatives at the Gauss nodes
+  const double* Dh = nullptr;   // differentiation on the Gauss nodes
   const double* gw = nullptr;   // Gauss weights
 };
 
@@ -258,6 +259,7 @@ VarOpArgs make_varop(const hofem_solver_s* S, const hofem_coef* c, const double*
     v.scale[i] = S->ax[i].scale;
     v.B[i] = S->ax[i].B;
     v.D[i] = S->ax[i].D;
+    v.Dh[i] = S->ax[i].Dh;
     v.w[i] = S->ax[i].gw;
     v.t[i] = c ? c->t_dev[i] : nullptr;
   }
@@ -485,7 +487,7 @@ int hofem_solver_create(int N, const hofem_plan1d* plans, const double* X, doubl
   }
   Packer pk;
   struct Off {
-    size_t lam, blk64, E64, tw64, sn64, blk32, E32, tw32, sn32, A, C, B, D, gw;
+    size_t lam, blk64, E64, tw64, sn64, blk32, E32, tw32, sn32, A, C, B, D, Dh, gw;
   } off[3];
   for (int i = 0; i < N; ++i) {
     const Plan1DData& d = plans[i]->d;
@@ -528,6 +530,7 @@ int hofem_solver_create(int N, const hofem_plan1d* plans, const double* X, doubl
     off[i].C = pk.add_f64(d.C);
     off[i].B = pk.add_f64(d.B);
     off[i].D = pk.add_f64(d.D);
+    off[i].Dh = pk.add_f64(d.Dh);
     off[i].gw = pk.add_f64(d.gw);
   }
   void* mem = nullptr;
@@ -555,6 +558,7 @@ int hofem_solver_create(int N, const hofem_plan1d* plans, const double* X, doubl
     ax.C = reinterpret_cast<const double*>(b + off[i].C);
     ax.B = reinterpret_cast<const double*>(b + off[i].B);
     ax.D = reinterpret_cast<const double*>(b + off[i].D);
+    ax.Dh = reinterpret_cast<const double*>(b + off[i].Dh);
     ax.gw = reinterpret_cast<const double*>(b + off[i].gw);
   }
   *out = S;

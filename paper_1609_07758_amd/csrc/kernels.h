@@ -119,6 +119,7 @@ struct VarOpArgs {
   double alpha;
   const double* B[3];    // e_r(x_q), (n+1)^2
   const double* D[3];    // e_r'(x_q), (n+1)^2
+  const double* Dh[3];   // differentiation on the Gauss nodes, (n+1)^2
   const double* w[3];    // Gauss weights, n+1
   int kind;              // 0: a = 1, 1: a = c0 + c1 prod_i t_i, 2: a at every Gauss point
   double c0, c1;

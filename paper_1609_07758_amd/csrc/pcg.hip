@@ -268,10 +268,11 @@ __global__ __launch_bounds__(1024) void varop_element_kernel(VarOpArgs a, double
 
 // 3D, equal orders NO (compile time): EPW elements per workgroup, every 1D
 // factor applied as one line of b values per lane with the tables as uniform
-// operands; per term i the stiffness factor acts first (difference form:
-// the derivative table applied to u - u_0 along the line), then the basis
-// values along the other axes, the Gauss weights times a, and the
-// transposed factors back.  One phase per factor, a barrier between phases.
+// operands, in collocation form: the nodal values are taken to the Gauss
+// points once, each gradient component is the Gauss-node differentiation
+// matrix along its axis (difference form), weighted by the quadrature weight
+// times a, and the transposed factors bring the sum back to the nodes.  One
+// phase per factor, a barrier between phases.
 template <int NO>
 struct VarShape {
   static constexpr int B = NO + 1, BBB = B * B * B;
@@ -312,6 +313,35 @@ __device__ __forceinline__ void var_contract(const double* src, double* dst, int
   }
 }
 
+// Derivative of the Gauss-point values along axis ax (difference form,
+// rows of Dh sum to zero) times s and the weighted coefficient:
+// dst[line, q] = s WA[line, q] sum_r Dh(q, r) (src[line, r] - src[line, 0]);
+// with einit, also einit[line, q] = alpha WA[line, q] src[line, q].
+template <int B>
+__device__ __forceinline__ void var_deriv(const double* src, double* dst, int ax,
+                                          const double* __restrict__ M, const double* WA, double s,
+                                          double* einit, double alpha, int nel, int tid, int nthr) {
+  constexpr int BB = B * B, BBB = B * B * B;
+  for (int task = tid; task < nel * BB; task += nthr) {
+    const int el = task / BB, line = task - el * BB;
+    const int i = line / B, j = line - i * B;
+    const int st = ax == 0 ? BB : (ax == 1 ? B : 1);
+    const int base = el * BBB + (ax == 0 ? (i * B + j) : (ax == 1 ? (i * BB + j) : (i * BB + j * B)));
+    double v[B];
+#pragma unroll
+    for (int r = 0; r < B; ++r) v[r] = src[base + r * st];
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      double t = 0.0;
+#pragma unroll
+      for (int r = 1; r < B; ++r) t += M[q * B + r] * (v[r] - v[0]);
+      const double wa = WA[base + q * st];
+      dst[base + q * st] = s * wa * t;
+      if (einit) einit[base + q * st] = alpha * wa * v[q];
+    }
+  }
+}
+
 template <int NO>
 __global__ __launch_bounds__(256) void varop3_order_kernel(VarOpArgs a, double* elem_out) {
   using SH = VarShape<NO>;
@@ -342,8 +372,7 @@ __global__ __launch_bounds__(256) void varop3_order_kernel(VarOpArgs a, double* 
     U[t] = v;
   }
   __syncthreads();
-  // quadrature weight times coefficient at every Gauss point of the batch,
-  // once; each term then scales its values by it (times s)
+  // quadrature weight times coefficient at every Gauss point of the batch
   for (int t = tid; t < ne * BBB; t += nthr) {
     const int el = t / BBB, Q = t - el * BBB;
     const int q0 = Q / (B * B), q1 = (Q / B) % B, q2 = Q % B;
@@ -358,44 +387,31 @@ __global__ __launch_bounds__(256) void varop3_order_kernel(VarOpArgs a, double* 
     }
     WA[t] = wq;
   }
-  auto weigh = [&](double* Z, double s) {
-    for (int t = tid; t < ne * BBB; t += nthr) Z[t] *= s * WA[t];
-  };
+
+  // Collocation form: U_q = (B (x) B (x) B) u at the Gauss points, then
+  // sum_i s_i Dh_i^T W Dh_i U_q + alpha W U_q there, then back to the nodes
+  // with (B^T (x) B^T (x) B^T); D_i = Dh_i B, so this equals the sum over the
+  // terms of (D_i^T (x) B^T (x) B^T) W (D_i (x) B (x) B) u.
+  var_contract<B, false, false, false>(U, X, 0, a.B[0], ne, tid, nthr);
+  __syncthreads();
+  var_contract<B, false, false, false>(X, Y, 1, a.B[1], ne, tid, nthr);
+  __syncthreads();
+  var_contract<B, false, false, false>(Y, X, 2, a.B[2], ne, tid, nthr);
+  __syncthreads();
 #pragma unroll
   for (int term = 0; term < 3; ++term) {
-    const int j = term == 0 ? 1 : 0, k = term == 2 ? 1 : 2;   // the other axes, j < k
-    var_contract<B, false, true, false>(U, X, term, a.D[term], ne, tid, nthr);
+    var_deriv<B>(X, Y, term, a.Dh[term], WA, a.scale[term], term == 0 ? E : nullptr, a.alpha, ne,
+                 tid, nthr);
     __syncthreads();
-    var_contract<B, false, false, false>(X, Y, j, a.B[j], ne, tid, nthr);
-    __syncthreads();
-    var_contract<B, false, false, false>(Y, X, k, a.B[k], ne, tid, nthr);
-    __syncthreads();
-    weigh(X, a.scale[term]);
-    __syncthreads();
-    var_contract<B, true, false, false>(X, Y, k, a.B[k], ne, tid, nthr);
-    __syncthreads();
-    var_contract<B, true, false, false>(Y, X, j, a.B[j], ne, tid, nthr);
-    __syncthreads();
-    if (term == 0) var_contract<B, true, false, false>(X, E, term, a.D[term], ne, tid, nthr);
-    else var_contract<B, true, false, true>(X, E, term, a.D[term], ne, tid, nthr);
+    var_contract<B, true, false, true>(Y, E, term, a.Dh[term], ne, tid, nthr);
     __syncthreads();
   }
-  if (a.alpha != 0.0) {
-    var_contract<B, false, false, false>(U, X, 0, a.B[0], ne, tid, nthr);
-    __syncthreads();
-    var_contract<B, false, false, false>(X, Y, 1, a.B[1], ne, tid, nthr);
-    __syncthreads();
-    var_contract<B, false, false, false>(Y, X, 2, a.B[2], ne, tid, nthr);
-    __syncthreads();
-    weigh(X, a.alpha);
-    __syncthreads();
-    var_contract<B, true, false, false>(X, Y, 2, a.B[2], ne, tid, nthr);
-    __syncthreads();
-    var_contract<B, true, false, false>(Y, X, 1, a.B[1], ne, tid, nthr);
-    __syncthreads();
-    var_contract<B, true, false, true>(X, E, 0, a.B[0], ne, tid, nthr);
-    __syncthreads();
-  }
+  var_contract<B, true, false, false>(E, Y, 0, a.B[0], ne, tid, nthr);
+  __syncthreads();
+  var_contract<B, true, false, false>(Y, U, 1, a.B[1], ne, tid, nthr);
+  __syncthreads();
+  var_contract<B, true, false, false>(U, E, 2, a.B[2], ne, tid, nthr);
+  __syncthreads();
   double* out = elem_out + (rhs * nel + e0) * BBB;
   for (int t = tid; t < ne * BBB; t += nthr) out[t] = E[t];
 }

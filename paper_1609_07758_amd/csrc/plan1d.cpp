@@ -364,6 +364,28 @@ int plan1d_build(int n, int K, Plan1DData* out) {
     out->B[i] = (double)Bq[i];
     out->D[i] = (double)Dq[i];
   }
+  // Barycentric differentiation matrix of the Gauss nodes: off the diagonal
+  // (c_p / c_q) / (x_q - x_p) with c_j = 1 / prod_{m != j} (x_j - x_m); the
+  // diagonal makes every row sum to zero.
+  {
+    std::vector<q128> c(nb, 1);
+    for (int j = 0; j < nb; ++j) {
+      for (int m = 0; m < nb; ++m)
+        if (m != j) c[j] *= gx[j] - gx[m];
+      c[j] = 1 / c[j];
+    }
+    out->Dh.assign(nb * nb, 0);
+    for (int q = 0; q < nb; ++q) {
+      q128 diag = 0;
+      for (int p = 0; p < nb; ++p) {
+        if (p == q) continue;
+        const q128 v = (c[p] / c[q]) / (gx[q] - gx[p]);
+        out->Dh[q * nb + p] = (double)v;
+        diag -= v;
+      }
+      out->Dh[q * nb + q] = (double)diag;
+    }
+  }
   // FFT support: twiddles exp(2 pi i t / K) and sin(pi t / K), t = 0..K-1.
   out->tw.assign(2 * K, 0);
   out->sn.assign(K, 0);

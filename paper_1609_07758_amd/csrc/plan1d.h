@@ -22,6 +22,9 @@ struct Plan1DData {
   // (n+1)-point Gauss-Legendre rule on [-1, 1] and the Lagrange basis there:
   std::vector<double> gx, gw;    // nodes, weights (n+1)
   std::vector<double> B, D;      // B[q (n+1) + r] = e_r(x_q), D[q (n+1) + r] = e_r'(x_q)
+  // differentiation on the Gauss nodes: Dh[q (n+1) + p] = g_p'(x_q) for the
+  // Lagrange basis g_p of the Gauss nodes (Dh = D B^-1; rows sum to zero)
+  std::vector<double> Dh;
 };
 
 // Returns 0 on success, -1 for unsupported (n, K).
