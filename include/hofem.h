@@ -206,8 +206,9 @@ int hofem_apply_coef_operator(hofem_solver solver, const hofem_coef* coef, const
                               double* out_dev, int nrhs, void* ws_dev, size_t ws_bytes,
                               void* stream);
 
-/* out = L u with L the operator of eq. (bvp glob 2), FP64, matrix-free,
- * element by element, the stiffness factors in difference form
+/* out = L u with L the operator of eq. (bvp glob 2), FP64, matrix-free
+ * (sum-factorised products of the 1D element matrices), the stiffness
+ * factors in difference form
  * sum_{l != k} A_kl (v_l - v_k) so that constants are exactly in their
  * kernel.  u_dev != out_dev.  For N = 3 with equal orders the element
  * outputs go through a device buffer of prod K_i (n+1)^3 doubles that the
