@@ -283,7 +283,7 @@ size_t pcg_bytes(const hofem_solver_s* S, const hofem_coef* c) {
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
   size_t b = 4 * al(n * sizeof(double)) + al(n * sizeof(float));
   if (c && c->kind != 0) b += al(varop_elem_bytes(make_varop(S, c, nullptr, nullptr, nullptr, 1)));
-  b += al(2 * kPcgParts * sizeof(double)) + al(16 * sizeof(double));
+  b += al(3 * kPcgParts * sizeof(double)) + al(16 * sizeof(double));   // partial triples
   return b;
 }
 
@@ -301,7 +301,7 @@ PcgWs pcg_carve(const hofem_solver_s* S, const hofem_coef* c, void* ws) {
     w.elem = reinterpret_cast<double*>(p);
     p += al(varop_elem_bytes(make_varop(S, c, nullptr, nullptr, nullptr, 1)));
   }
-  w.partial = reinterpret_cast<double*>(p); p += al(2 * kPcgParts * sizeof(double));
+  w.partial = reinterpret_cast<double*>(p); p += al(3 * kPcgParts * sizeof(double));
   w.scal = reinterpret_cast<double*>(p);
   return w;
 }
@@ -359,7 +359,8 @@ int pcg_run(hofem_solver_s* S, const hofem_coef* c, const PcgWs& w, const double
     HIPCHK(launch_scalar_op(sc, 0, st));                                           // alpha
     {
       LaunchTimer tm(S, st, HOFEM_PASS_UPDATE, -1, 1, (double)n * 48);
-      HIPCHK(launch_cg_update(x, w.r, w.p, w.q, n, sc, w.partial, np, sc + 7, st));  // rr, xx
+      // rr, xx, and r z_old for the flexible beta
+      HIPCHK(launch_cg_update(x, w.r, w.p, w.q, w.z, n, sc, w.partial, np, sc + 7, sc + 10, st));
       tm.done();
     }
     HIPCHK(hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, st));
@@ -372,7 +373,6 @@ int pcg_run(hofem_solver_s* S, const hofem_coef* c, const PcgWs& w, const double
       break;
     }
     if (it == max_iter) break;
-    HIPCHK(launch_dot2(w.r, w.z, nullptr, n, w.partial, np, sc + 10, st));         // r z_old
     if ((rc = precond(w.r, w.z)) != HOFEM_OK) return rc;                           // z = S32 r
     HIPCHK(launch_dot2(w.r, w.z, nullptr, n, w.partial, np, sc + 5, st));          // rz_new
     HIPCHK(launch_scalar_op(sc, 1, st));                                           // beta

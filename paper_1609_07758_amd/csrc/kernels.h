@@ -132,9 +132,9 @@ hipError_t launch_varop(const VarOpArgs& a, double* elem_buf, hipStream_t s);
 // PCG vector kernels (np partial sums, reduced in a fixed order).
 hipError_t launch_dot2(const double* x, const double* y, const double* z, long long n,
                        double* partial, int np, double* out2, hipStream_t s);
-hipError_t launch_cg_update(double* x, double* r, const double* p, const double* q, long long n,
-                            const double* scal, double* partial, int np, double* out2,
-                            hipStream_t s);
+hipError_t launch_cg_update(double* x, double* r, const double* p, const double* q,
+                            const double* z, long long n, const double* scal, double* partial,
+                            int np, double* out2, double* out1, hipStream_t s);
 hipError_t launch_cg_dir(double* p, const double* z, long long n, const double* scal,
                          hipStream_t s);
 // scal[0] = scal[2] / scal[3] (op 0: alpha = rz / pq);

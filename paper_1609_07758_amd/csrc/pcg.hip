@@ -53,15 +53,18 @@ __global__ __launch_bounds__(256) void dot2_kernel(const double* __restrict__ x,
   }
 }
 
-// x += alpha p, r -= alpha q; partial sums of r^2 and x^2 (alpha from device)
+// x += alpha p, r -= alpha q; partial sums of r^2, x^2 and r z (the new
+// residual with the previous preconditioned one, for the flexible beta)
+// (alpha from device)
 __global__ __launch_bounds__(256) void cg_update_kernel(double* __restrict__ x,
                                                         double* __restrict__ r,
                                                         const double* __restrict__ p,
-                                                        const double* __restrict__ q, long long n,
+                                                        const double* __restrict__ q,
+                                                        const double* __restrict__ z, long long n,
                                                         const double* scal, double* partial) {
   __shared__ double sh[4];
   const double alpha = scal[0];
-  double a0 = 0.0, a1 = 0.0;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n;
        i += (long long)gridDim.x * 256) {
     const double xi = x[i] + alpha * p[i];
@@ -70,12 +73,44 @@ __global__ __launch_bounds__(256) void cg_update_kernel(double* __restrict__ x,
     r[i] = ri;
     a0 += ri * ri;
     a1 += xi * xi;
+    a2 += ri * z[i];
   }
   a0 = block_sum(a0, sh);
   a1 = block_sum(a1, sh);
+  a2 = block_sum(a2, sh);
   if (threadIdx.x == 0) {
-    partial[2 * blockIdx.x] = a0;
-    partial[2 * blockIdx.x + 1] = a1;
+    partial[3 * blockIdx.x] = a0;
+    partial[3 * blockIdx.x + 1] = a1;
+    partial[3 * blockIdx.x + 2] = a2;
+  }
+}
+
+// out2[0..1], out1[0] = sums of the interleaved triples partial[0..3 np) in a
+// fixed order
+__global__ void sum3_kernel(const double* partial, int np, double* out2, double* out1) {
+  __shared__ double s0[256], s1[256], s2[256];
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int i = threadIdx.x; i < np; i += 256) {
+    a += partial[3 * i];
+    b += partial[3 * i + 1];
+    c += partial[3 * i + 2];
+  }
+  s0[threadIdx.x] = a;
+  s1[threadIdx.x] = b;
+  s2[threadIdx.x] = c;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      s0[threadIdx.x] += s0[threadIdx.x + w];
+      s1[threadIdx.x] += s1[threadIdx.x + w];
+      s2[threadIdx.x] += s2[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out2[0] = s0[0];
+    out2[1] = s1[0];
+    out1[0] = s2[0];
   }
 }
 
@@ -546,11 +581,11 @@ hipError_t launch_dot2(const double* x, const double* y, const double* z, long l
   return hipGetLastError();
 }
 
-hipError_t launch_cg_update(double* x, double* r, const double* p, const double* q, long long n,
-                            const double* scal, double* partial, int np, double* out2,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(cg_update_kernel, dim3(np), dim3(256), 0, s, x, r, p, q, n, scal, partial);
-  hipLaunchKernelGGL(sum2_kernel, dim3(1), dim3(256), 0, s, partial, np, out2);
+hipError_t launch_cg_update(double* x, double* r, const double* p, const double* q,
+                            const double* z, long long n, const double* scal, double* partial,
+                            int np, double* out2, double* out1, hipStream_t s) {
+  hipLaunchKernelGGL(cg_update_kernel, dim3(np), dim3(256), 0, s, x, r, p, q, z, n, scal, partial);
+  hipLaunchKernelGGL(sum3_kernel, dim3(1), dim3(256), 0, s, partial, np, out2, out1);
   return hipGetLastError();
 }
 
