@@ -184,7 +184,8 @@ int run_list(hofem_solver_s* S, const std::vector<PassSpec>& list, bool f64, con
     if (a.nlines == 0) continue;
     static const int in_bytes[6] = {8, 4, 8, 4, 4, 8}, out_bytes[6] = {8, 4, 4, 8, 16, 8};
     const double bytes = (double)S->per_rhs * nrhs * (in_bytes[dt] + out_bytes[dt]);
-    LaunchTimer tm(S, st, list[i].kind, list[i].axis, f64 ? 1 : 0, bytes);
+    LaunchTimer tm(S, st, list[i].kind == PASS_INV_ACC ? PASS_INV : list[i].kind, list[i].axis,
+                   f64 ? 1 : 0, bytes);
     HIPCHK(launch_pass(list[i].kind, dt, a, st));
     tm.done();
   }
@@ -678,6 +679,8 @@ int hofem_solve(hofem_solver S, int mode, const void* f_dev, void* u_dev, int nr
   bool converged = tol <= 0;
   double host[2] = {0.0, 0.0};
   bool have = false;
+  std::vector<PassSpec> acc_list = list;
+  acc_list.back().kind = PASS_INV_ACC;
   for (; it < max_iter;) {
     OpArgs o;
     rc = make_op(S, static_cast<const double*>(u_dev), static_cast<const double*>(f_dev), r32, 1,
@@ -687,6 +690,14 @@ int hofem_solve(hofem_solver S, int mode, const void* f_dev, void* u_dev, int nr
       LaunchTimer tm(S, st, HOFEM_PASS_OPERATOR, -1, 1, (double)count * (8 + 8 + 4));
       HIPCHK(launch_operator(o, st));
       tm.done();
+    }
+    if (tol <= 0 && it + 1 < max_iter && list.size() > 1) {
+      // a step whose norms nobody reads: the last (inverse) pass adds the
+      // correction to u itself
+      rc = run_list(S, acc_list, false, r32, r32, u_dev, 1, 1, 4, 4, nrhs, st);
+      if (rc != HOFEM_OK) return rc;
+      ++it;
+      continue;
     }
     rc = run_list(S, list, false, r32, r32, r32, 1, 1, 1, 1, nrhs, st);
     if (rc != HOFEM_OK) return rc;

@@ -32,7 +32,9 @@ struct AxisTab {
   int n, K, m;
 };
 
-enum PassKind { PASS_FWD = 0, PASS_INV = 1, PASS_FUSED = 2 };
+// PASS_INV_ACC: the inverse pass adding its result to a double output
+// (FP32 compute, float in; a refinement step's correction).
+enum PassKind { PASS_FWD = 0, PASS_INV = 1, PASS_FUSED = 2, PASS_INV_ACC = 5 };
 
 // Arguments of one line pass along one axis of a C-order grid.
 struct PassArgs {

@@ -704,7 +704,7 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
   // coefficient order (inverse pass).
   auto in_entry = [&](int c, int q) -> T& {
     int s, i;
-    if (MODE == PASS_INV) {
+    if (MODE == PASS_INV || MODE == PASS_INV_ACC) {
       if (q < N - 1) {
         s = q;
         i = 0;
@@ -1149,6 +1149,11 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
       return v;
     };
     constexpr int SU = 8;   // values gathered before their stores are issued
+    // the inverse pass that adds its result to the output (refinement)
+    constexpr bool kAcc = MODE == PASS_INV_ACC;
+    auto store = [&](TOUT& o, T v) {
+      if constexpr (kAcc) o += (TOUT)v; else o = (TOUT)v;
+    };
     if (!cfast) {
       // 16-byte stores from the first 16-byte boundary on
       TOUT* d = dst + L0 * M;
@@ -1162,8 +1167,8 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
         const int c = i / M, q = i - c * M;
         return value(c, q);
       };
-      if (tid < h) d[tid] = (TOUT)val_at(tid);
-      if (tid < total - tail0) d[tail0 + tid] = (TOUT)val_at(tail0 + tid);
+      if (tid < h) store(d[tid], val_at(tid));
+      if (tid < total - tail0) store(d[tail0 + tid], val_at(tail0 + tid));
       vec16<TOUT>* vd = reinterpret_cast<vec16<TOUT>*>(d + h);
       for (int j0 = tid; j0 < nv; j0 += SUV * nthr) {
         vec16<TOUT> val[SUV];
@@ -1176,7 +1181,16 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
 #pragma unroll
         for (int u = 0; u < SUV; ++u) {
           const int j = j0 + u * nthr;
-          if (j < nv) vd[j] = val[u];
+          if (j < nv) {
+            if constexpr (kAcc) {
+              vec16<TOUT> o = vd[j];
+#pragma unroll
+              for (int e = 0; e < VS; ++e) o.v[e] += val[u].v[e];
+              vd[j] = o;
+            } else {
+              vd[j] = val[u];
+            }
+          }
         }
       }
     } else {
@@ -1191,7 +1205,7 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
 #pragma unroll
           for (int u = 0; u < SU; ++u) {
             const int q = q0 + u * qs;
-            if (q < M) d[(long long)q * inner] = (TOUT)val[u];
+            if (q < M) store(d[(long long)q * inner], val[u]);
           }
         }
       }
@@ -1295,6 +1309,9 @@ hipError_t launch_order(int kind, int dt, const PassArgs& a, hipStream_t s) {
       if (dt == 0) return launch_by_k<double, N, PASS_INV, double, double>(a, s);
       if (dt == 1) return launch_by_k<float, N, PASS_INV, float, float>(a, s);
       if (dt == 3) return launch_by_k<float, N, PASS_INV, float, double>(a, s);
+      break;
+    case PASS_INV_ACC:
+      if (dt == 4) return launch_by_k<float, N, PASS_INV_ACC, float, double>(a, s);
       break;
     case PASS_FUSED:
       if (dt == 0) return launch_by_k<double, N, PASS_FUSED, double, double>(a, s);
