@@ -502,28 +502,32 @@ int hofem_solver_create(int N, const hofem_plan1d* plans, const double* X, doubl
     S->per_rhs *= (size_t)d.m;
     ax.hA = d.A;
     ax.hC = d.C;
-    // per-wave-number tables blocked by 64 wave numbers, entries in pairs
-    // (layout in kernels.h)
+    // per-wave-number tables blocked by 64 wave numbers, entries in groups of
+    // 16 bytes: pairs in FP64, quadruples in FP32 (layout in kernels.h)
     const int n = d.n, K = d.K;
-    const size_t NE = (size_t)n * (n - 1) + n, NEP = (NE + 1) / 2, nblk = ((size_t)K - 1 + 63) / 64;
-    std::vector<double> blk(nblk * NEP * 64 * 2, 0.0);
-    auto put = [&](int k, size_t e, double v) {
-      const size_t b = (size_t)(k - 1) / 64, o = (size_t)(k - 1) % 64;
-      blk[((b * NEP + e / 2) * 64 + o) * 2 + (e & 1)] = v;
-    };
-    for (int k = 1; k < K; ++k) {
-      for (int l = 0; l < n; ++l) {
-        for (int c = 0; c < n - 1; ++c)
-          put(k, (size_t)l * (n - 1) + c, d.p[((size_t)(k - 1) * n + l) * (n - 1) + c]);
-        put(k, (size_t)n * (n - 1) + l, d.inorm[(size_t)(k - 1) * n + l]);
+    auto blocked = [&](size_t ge) {
+      const size_t NE = (size_t)n * (n - 1) + n, NEG = (NE + ge - 1) / ge;
+      const size_t nblk = ((size_t)K - 1 + 63) / 64;
+      std::vector<double> blk(nblk * NEG * 64 * ge, 0.0);
+      auto put = [&](int k, size_t e, double v) {
+        const size_t b = (size_t)(k - 1) / 64, o = (size_t)(k - 1) % 64;
+        blk[((b * NEG + e / ge) * 64 + o) * ge + e % ge] = v;
+      };
+      for (int k = 1; k < K; ++k) {
+        for (int l = 0; l < n; ++l) {
+          for (int c = 0; c < n - 1; ++c)
+            put(k, (size_t)l * (n - 1) + c, d.p[((size_t)(k - 1) * n + l) * (n - 1) + c]);
+          put(k, (size_t)n * (n - 1) + l, d.inorm[(size_t)(k - 1) * n + l]);
+        }
       }
-    }
+      return blk;
+    };
     off[i].lam = pk.add_f64(d.lam);
-    off[i].blk64 = pk.add_f64(blk);
+    off[i].blk64 = pk.add_f64(blocked(2));
     off[i].E64 = pk.add_f64(d.E);
     off[i].tw64 = pk.add_f64(d.tw);
     off[i].sn64 = pk.add_f64(d.sn);
-    off[i].blk32 = pk.add_f32(blk);
+    off[i].blk32 = pk.add_f32(blocked(4));
     off[i].E32 = pk.add_f32(d.E);
     off[i].tw32 = pk.add_f32(d.tw);
     off[i].sn32 = pk.add_f32(d.sn);

@@ -17,12 +17,13 @@ int record_hip_error(hipError_t e);
 // l = 1..n, i.e. for each l the wave numbers k are consecutive.
 //
 // The per-wave-number tables are blocked by 64 wave numbers (one wavefront)
-// and hold their entries in pairs: entry e of wave number k sits at
-// (((k-1)/64 * NEP + e/2) * 64 + (k-1) % 64) * 2 + e % 2 with NE = n(n-1) + n,
-// NEP = ceil(NE / 2), e = (l-1)(n-1) + (i-1) for component i of p_k^(l) and
+// and hold their entries in groups of g = 16 bytes / element size (pairs in
+// FP64, quadruples in FP32): entry e of wave number k sits at
+// (((k-1)/64 * NEG + e/g) * 64 + (k-1) % 64) * g + e % g with NE = n(n-1) + n,
+// NEG = ceil(NE / g), e = (l-1)(n-1) + (i-1) for component i of p_k^(l) and
 // e = n(n-1) + l-1 for 1 / ||s_k^(l)||^2, so that a wavefront handling 64
-// consecutive k reads two entries per lane with one load, 64 consecutive
-// pairs.
+// consecutive k reads g entries per lane with one 16-byte load, 64
+// consecutive groups.
 struct AxisTab {
   const void* blk;     // blocked p and 1/||s||^2 (T)
   const void* E;       // e^(l) columns, i (n-1) + l-1

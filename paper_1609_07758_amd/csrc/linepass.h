@@ -485,29 +485,30 @@ __device__ __forceinline__ cx<T> dst_pre(cx<T> xj, cx<T> xkj, T snj, int j) {
           snj * (xj.y + xkj.y) + T(0.5) * (xj.y - xkj.y)};
 }
 
-// The per-wave-number tables hold entries in pairs (see AxisTab): one
-// 16-byte (FP64) or 8-byte (FP32) load brings two entries.
+// The per-wave-number tables hold entries in 16-byte groups (see AxisTab):
+// one load brings two FP64 or four FP32 entries.
 template <typename T>
-struct alignas(2 * sizeof(T)) tpair {
-  T x, y;
+struct alignas(16) tgrp {
+  T v[16 / sizeof(T)];
 };
 
-// Pair 0 of wave number k's table; entry e is in pair e / 2.
+// Group 0 of wave number k's table; entry e is in group e / (16 / sizeof T).
 template <int N, typename T>
-__device__ __forceinline__ const tpair<T>* blk_at(const tpair<T>* blk, int k) {
-  constexpr int NEP = (N * (N - 1) + N + 1) / 2;
-  return blk + (size_t)((k - 1) >> 6) * (NEP * 64) + ((k - 1) & 63);
+__device__ __forceinline__ const tgrp<T>* blk_at(const tgrp<T>* blk, int k) {
+  constexpr int GE = 16 / sizeof(T), NEG = (N * (N - 1) + N + GE - 1) / GE;
+  return blk + (size_t)((k - 1) >> 6) * (NEG * 64) + ((k - 1) & 63);
 }
 
 template <typename T>
-__device__ __forceinline__ T tab_e(const tpair<T>* __restrict__ tb, int e) {
-  const tpair<T> v = tb[(e >> 1) * 64];
-  return (e & 1) ? v.y : v.x;
+__device__ __forceinline__ T tab_e(const tgrp<T>* __restrict__ tb, int e) {
+  constexpr int GE = 16 / sizeof(T);
+  const tgrp<T> g = tb[(e / GE) * 64];
+  return g.v[e % GE];
 }
 
 // The first NT entries of wave number k's table (all of them issued at once).
 template <typename T, int NT>
-__device__ __forceinline__ void load_tab(const tpair<T>* __restrict__ tb, T (&tab)[NT]) {
+__device__ __forceinline__ void load_tab(const tgrp<T>* __restrict__ tb, T (&tab)[NT]) {
 #pragma unroll
   for (int e = 0; e < NT; ++e) tab[e] = tab_e(tb, e);
 }
@@ -534,7 +535,7 @@ __device__ __forceinline__ void inv_apply(const T (&tab)[N * (N - 1) > 0 ? N * (
 // eigenvector l (its N-1 entries, its norm and its eigenvalue) is read once
 // per l and applied to every line.
 template <typename T, int N, int NL>
-__device__ __forceinline__ void fwd_lines(const tpair<T>* __restrict__ tb, const T (&x)[NL][N],
+__device__ __forceinline__ void fwd_lines(const tgrp<T>* __restrict__ tb, const T (&x)[NL][N],
                                           T (&acc)[NL][N]) {
 #pragma unroll
   for (int l = 0; l < N; ++l) {
@@ -553,7 +554,7 @@ __device__ __forceinline__ void fwd_lines(const tpair<T>* __restrict__ tb, const
 }
 
 template <typename T, int N, int NL>
-__device__ __forceinline__ void fused_lines(const tpair<T>* __restrict__ tb, const double* __restrict__ lk,
+__device__ __forceinline__ void fused_lines(const tgrp<T>* __restrict__ tb, const double* __restrict__ lk,
                                             int lstride, const double (&dbase)[NL], double sc,
                                             const T (&x)[NL][N], T (&y)[NL][N]) {
 #pragma unroll
@@ -648,7 +649,7 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
   T* e0a = reinterpret_cast<T*>(denb + cb);                                   // [cb][8] (not tight)
   auto lslots = [&](int c) -> cx<T>* { return slots + (size_t)c * lsp; };
 
-  const tpair<T>* __restrict__ BLK = static_cast<const tpair<T>*>(a.tab.blk);
+  const tgrp<T>* __restrict__ BLK = static_cast<const tgrp<T>*>(a.tab.blk);
   const T* __restrict__ EV = static_cast<const T*>(a.tab.E);
   const cx<T>* __restrict__ TW = static_cast<const cx<T>*>(a.tab.tw);
   const T* __restrict__ SN = static_cast<const T*>(a.tab.sn);
