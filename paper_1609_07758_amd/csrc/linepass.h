@@ -1219,8 +1219,8 @@ struct Shape {
   size_t lds;
 };
 
-// Lines per workgroup and LDS bytes.  Lines that fit two or more to 64 KB
-// (two or more workgroups per CU) use the padded layout; longer lines use the
+// Lines per workgroup and LDS bytes.  Lines that fit two or more to 64 KB use
+// the padded layout (80 KB per workgroup in FP64, 64 KB in FP32); longer lines use the
 // tight one with as many lines (at most kTight) as the CU's LDS share of one
 // workgroup holds: 160 KB divided by the workgroups per CU that the register
 // budget allows.
@@ -1235,7 +1235,11 @@ inline Shape shape_for(int n, int K, size_t cplx_bytes, long long nlines) {
   const size_t per_line = ((size_t)NP * K + 1) * cplx_bytes;
   Shape s;
   s.threads = threads;
-  long long c = (long long)((64 * 1024) / per_line);
+  // padded layout: up to 80 KB per workgroup in FP64 (two workgroups fill
+  // the CU's LDS; strided rows of n = 4, K = 128 lines then span whole cache
+  // lines), 64 KB in FP32
+  long long c = f64 ? (long long)((80 * 1024 - 64) / (per_line + 16 + 8 * (long long)(cplx_bytes / 2)))
+                    : (long long)((64 * 1024) / per_line);
   if (!tight_layout(n, K, (int)cplx_bytes)) {
     // every FFT task of the workgroup in one round
     c = std::min<long long>(c, (long long)(threads / 64) * TPW / NP);
