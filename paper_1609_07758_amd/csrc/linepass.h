@@ -632,6 +632,9 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
   // registers.  Otherwise one pad entry per line (spreads the lines over the
   // LDS banks) and the per-line address and denominator after the slots.
   constexpr int NLB = kTight;   // lines per table read (tight)
+  // S0 summed inside the transform tasks (tight FP64; FP32 has no registers
+  // to spare for it)
+  constexpr bool kS0In = tight && sizeof(T) == 8;
   const int lsp = tight ? NP * K : NP * K + 1;   // complex entries per line
   // Workgroups are dealt round-robin to the 8 XCDs (each with its own L2):
   // renumber them so that every XCD walks one contiguous range of lines, and
@@ -870,7 +873,10 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
     // Direct sine transforms, one task per (line, pair): a task reads its
     // pair into registers (forward pre-combine and sine pre-processing) and
     // transforms it in place.
-    auto fwd_read = [&](cx<T>* tb, bool interior, int j, cx<T> (&v)[R]) {
+    // (with S0IN, also the lane's terms of the pair's S0 sums: entry jj is
+    // element jj + 1, sign (-1)^jj; the node pair of an even order carries
+    // the middle component, its own mirror, in .y)
+    auto fwd_read = [&](cx<T>* tb, bool interior, int j, cx<T> (&v)[R], T& sa, T& sb) {
       T snr[R];   // DST pre-weights sin(pi jj / K) of this lane's task points
       task_sines<T, K, R>(SN, j, snr);
 #pragma unroll
@@ -879,24 +885,45 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
         const cx<T> e0 = tb[sw(jj)], e1 = tb[sw((jj - 1) & (K - 1))];
         const cx<T> m0 = tb[sw((K - jj) & (K - 1))], m1 = tb[sw((K - jj - 1) & (K - 1))];
         v[t] = dst_pre(fwd_in<T, N>(interior, e0, e1), fwd_in<T, N>(interior, m0, m1), snr[t], jj);
+        if constexpr (kS0In) {
+          const bool even = !(jj & 1);
+          sa += interior ? (even ? e0.x : -e0.y) : T(0);
+          sb += interior ? (even ? e0.y : -e0.x) : (N % 2 == 0 ? (even ? e0.y : -e0.y) : T(0));
+        }
       }
     };
     if constexpr (tight) {
-      // tasks in rounds: the sums first
-      s0_sums();
-      if constexpr (N > 1) __syncthreads();
+      // tasks in rounds: the sums first (FP32) or inside the tasks (FP64)
+      if constexpr (!kS0In) {
+        s0_sums();
+        if constexpr (N > 1) __syncthreads();
+      }
       for (int t0 = 0; t0 < ntask; t0 += per_round) {
         const int task = t0 + wave * TPW + lane / G;
         if (task < ntask) {
           const int tc = task / NP, tp = task - tc * NP;
+          const bool interior = tp < NP - 1;
           cx<T>* tb = lslots(tc) + (size_t)tp * K;
           int j = lane & (G - 1);
           asm volatile("" : "+v"(j));   // keeps the lane's address arithmetic inside the loop
           cx<T> v[R];
-          fwd_read(tb, tp < NP - 1, j, v);
+          T sa = T(0), sb = T(0);
+          fwd_read(tb, interior, j, v, sa, sb);
           wave_sync();
           task_fft<T, LOG2K, LRM>(v, tb, j, TW);
           task_post<T, LOG2K, LRM>(tb, j);
+          if constexpr (kS0In && N > 1) {
+            // the pair's S0 into its entry 0, free after the transform
+#pragma unroll
+            for (int off = G / 2; off > 0; off >>= 1) {
+              sa += __shfl_xor(sa, off, 64);
+              sb += __shfl_xor(sb, off, 64);
+            }
+            if (j == 0) {
+              if (interior) tb[sw(0)] = cx<T>{sa, sb};
+              else if (N % 2 == 0) tb[sw(0)].y = sb;
+            }
+          }
         }
       }
     } else {
@@ -907,7 +934,8 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
       cx<T>* tb = lslots(task < ntask ? tc : 0) + (size_t)tp * K;
       const int j = lane & (G - 1);
       cx<T> v[R];
-      if (task < ntask) fwd_read(tb, tp < NP - 1, j, v);
+      T sa = T(0), sb = T(0);
+      if (task < ntask) fwd_read(tb, tp < NP - 1, j, v, sa, sb);
       s0_sums();
       __syncthreads();
       if (task < ntask) {
@@ -916,8 +944,8 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
       }
     }
     __syncthreads();
-    // S0 into entry 0 of its component
-    if constexpr (N > 1) {
+    // S0 into entry 0 of its component (unless the tasks wrote it)
+    if constexpr (N > 1 && !kS0In) {
       if constexpr (tight) {
         if (lane == 0) {
           int r = 0;
