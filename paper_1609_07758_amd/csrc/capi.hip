@@ -130,8 +130,11 @@ struct LaunchTimer {
   }
 };
 
+// il_in / il_out: the pass reads / writes the row-pair interleaved 2D
+// intermediate (PassArgs::ilv_in / ilv_out).
 struct PassSpec {
   int axis, kind;
+  bool il_in = false, il_out = false;
 };
 
 PassArgs make_args(const hofem_solver_s* S, int axis, int kind, bool f64, const void* in, void* out,
@@ -182,6 +185,11 @@ int run_list(hofem_solver_s* S, const std::vector<PassSpec>& list, bool f64, con
     else dt = dt_mid;
     PassArgs a = make_args(S, list[i].axis, list[i].kind, f64, in, out, nrhs);
     if (a.nlines == 0) continue;
+    if (list[i].il_in || list[i].il_out) {
+      const long long rows = ((long long)S->ax[0].m * nrhs) & ~1LL;
+      if (list[i].il_in) a.ilv_in = rows;
+      if (list[i].il_out) a.ilv_out = rows;
+    }
     static const int in_bytes[6] = {8, 4, 8, 4, 4, 8}, out_bytes[6] = {8, 4, 4, 8, 16, 8};
     const double bytes = (double)S->per_rhs * nrhs * (in_bytes[dt] + out_bytes[dt]);
     LaunchTimer tm(S, st, list[i].kind == PASS_INV_ACC ? PASS_INV : list[i].kind, list[i].axis,
@@ -192,11 +200,21 @@ int run_list(hofem_solver_s* S, const std::vector<PassSpec>& list, bool f64, con
   return HOFEM_OK;
 }
 
-std::vector<PassSpec> solve_list(int N) {
+// Passes of a solve.  In 2D, when the row passes take two lines per
+// workgroup, the intermediate between the passes is row-pair interleaved:
+// the row passes then move contiguous blocks and the column pass moves
+// twice the bytes per access.
+std::vector<PassSpec> solve_list(const hofem_solver_s* S, bool f64) {
+  const int N = S->N;
   std::vector<PassSpec> l;
   for (int a = N - 1; a >= 1; --a) l.push_back({a, PASS_FWD});
   l.push_back({0, PASS_FUSED});
   for (int a = 1; a < N; ++a) l.push_back({a, PASS_INV});
+  if (N == 2 && pass_lines_per_workgroup(S->ax[1].n, S->ax[1].K, f64, S->ax[0].m) == 2) {
+    l[0].il_out = true;
+    l[1].il_in = l[1].il_out = true;
+    l[2].il_in = true;
+  }
   return l;
 }
 
@@ -333,7 +351,7 @@ int pcg_run(hofem_solver_s* S, const hofem_coef* c, const PcgWs& w, const double
             double rtol, double utol, int max_iter, hipStream_t st, int* iters, double* rel_res,
             double* rel_upd, bool* converged) {
   const long long n = (long long)S->per_rhs;
-  const std::vector<PassSpec> list = solve_list(S->N);
+  const std::vector<PassSpec> list = solve_list(S, false);
   const int np = (int)std::max<long long>(1, std::min<long long>(kPcgParts, (n + 255) / 256));
   double* sc = w.scal;
   auto precond = [&](const double* in, double* out) {
@@ -630,7 +648,7 @@ int hofem_solve(hofem_solver S, int mode, const void* f_dev, void* u_dev, int nr
                 size_t ws_bytes, int max_iter, double tol, void* stream, hofem_info* info) {
   if (!S || !f_dev || !u_dev || nrhs < 1) return HOFEM_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const std::vector<PassSpec> list = solve_list(S->N);
+  const std::vector<PassSpec> list = solve_list(S, mode == HOFEM_MODE_FP64);
   if (mode == HOFEM_MODE_FP64 || mode == HOFEM_MODE_FP32) {
     const bool f64 = mode == HOFEM_MODE_FP64;
     const int dt = f64 ? 0 : 1;

@@ -45,6 +45,17 @@ struct PassArgs {
   long long inner;     // stride of the axis (product of the later extents)
   long long nlines;    // number of lines (total elements / m)
   int cb;              // lines per workgroup (set by the launcher)
+  // Row-pair interleaved intermediate of a 2D solve: the first ilv rows of
+  // the grid (an even count; rows of all right-hand sides in sequence) are
+  // stored in pairs, row 2g + h of column t at 2g * M1 + 2t + h, the rest
+  // plain.  A pass along the rows then moves its two lines as one
+  // contiguous block, a pass along the columns moves 32 bytes (FP64) per
+  // row pair instead of 16 per row.  ilv_in / ilv_out: for the input /
+  // output, 0 = plain.  Along the rows (inner == 1) only with two lines per
+  // workgroup, and ilv_out only in the forward pass; along the columns
+  // ilv_out only in the passes that end with the scatter.
+  long long ilv_in;
+  long long ilv_out;
   // Denominator of the fused pass: alpha + scale * lam[q] + sum over the
   // other axes of oscale[i] * olam[i][(t / odiv[i]) % omod[i]], t = line % inner.
   double alpha;
@@ -75,6 +86,9 @@ template <> hipError_t launch_pass_order<9>(int, int, const PassArgs&, hipStream
 // in, double out accumulated (out += result), 5 = FP32 compute, double in,
 // double out (stored).
 hipError_t launch_pass(int kind, int dt, const PassArgs& a, hipStream_t s);
+// Lines per workgroup of a pass along a contiguous axis of order n with K
+// elements and nlines lines.
+int pass_lines_per_workgroup(int n, int K, bool f64, long long nlines);
 
 // FP64 matrix-free operator r = f - L u (f may be NULL: r = L u), N = 1..3.
 struct OpArgs {

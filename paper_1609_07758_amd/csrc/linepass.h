@@ -101,6 +101,11 @@ template <typename T>
 struct alignas(16) vec16 {
   T v[16 / sizeof(T)];
 };
+// The values of two lines at one position of a row-pair interleaved block.
+template <typename T>
+struct alignas(2 * sizeof(T)) pair2 {
+  T a, b;
+};
 
 // Elements of type T before the first 16-byte boundary at or after p.
 template <typename T>
@@ -651,6 +656,19 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
   double* denb = reinterpret_cast<double*>(base + cb);                        // [cb] (not tight)
   T* e0a = reinterpret_cast<T*>(denb + cb);                                   // [cb][8] (not tight)
   auto lslots = [&](int c) -> cx<T>* { return slots + (size_t)c * lsp; };
+  // Row-pair interleaved input / output (2D intermediate).  Along the rows:
+  // the workgroup's two lines are one block, value q of line c at 2q + c.
+  // Along the columns: value q of the line whose plain address is b moves
+  // by ilv_shift.
+  const bool pil_in = !cfast && a.ilv_in > 0 && cv == 2 && L0 + 1 < a.ilv_in;
+  const bool pil_out = !cfast && a.ilv_out > 0 && cv == 2 && L0 + 1 < a.ilv_out;
+  const long long MI = (long long)M * inner;
+  // row L = o M + q of column t (plain address L inner + t) sits at
+  // (L - (L & 1)) inner + 2t + (L & 1) when L < ilv
+  auto ilv_shift = [&](long long ilv, long long orow, long long tcol, int q) -> long long {
+    const long long L = orow + q;
+    return L < ilv ? tcol - (L & 1) * (inner - 1) : 0;
+  };
 
   const tgrp<T>* __restrict__ BLK = static_cast<const tgrp<T>*>(a.tab.blk);
   const T* __restrict__ EV = static_cast<const T*>(a.tab.E);
@@ -741,7 +759,14 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
     const int nv = (total - h) / VL;
     const int tail0 = h + nv * VL;
     auto put = [&](int i, TIN v) {
-      const int c = i / M, q = i - c * M;
+      int c, q;
+      if (pil_in) {
+        c = i & 1;
+        q = i >> 1;
+      } else {
+        c = i / M;
+        q = i - c * M;
+      }
       in_entry(c, q) = (T)v;
     };
     if (tid < h) put(tid, sp[tid]);
@@ -769,13 +794,21 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
     const int c = tid & (cb - 1);
     const int qs = nthr >> lcb;
     if (c < cv) {
-      const TIN* sp = src + lbase(c);
+      const long long b = lbase(c);
+      const TIN* sp = src + b;
+      const long long ilv = a.ilv_in;
+      long long orow = 0, tcol = 0;
+      if (ilv > 0) {
+        const long long o = b / MI;
+        orow = o * M;
+        tcol = b - o * MI;
+      }
       for (int q0 = tid >> lcb; q0 < M; q0 += kUnroll * qs) {
         TIN r[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-          const int q = q0 + u * qs;
-          r[u] = sp[(long long)(q < M ? q : 0) * inner];
+          const int q = q0 + u * qs < M ? q0 + u * qs : 0;
+          r[u] = sp[(long long)q * inner + ilv_shift(ilv, orow, tcol, q)];
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
@@ -965,7 +998,15 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
 
     if (MODE == PASS_FWD) {
       // ---- forward block, coefficients to global -------------------------
-      if constexpr (tight) {
+      // output base and step of line c (row-pair interleaved: the pair's
+      // block, step 2)
+      const long long ostep = pil_out ? 2 : inner;
+      auto obase = [&](int c) -> long long { return pil_out ? lbase(0) + c : lbase(c); };
+      // interleaved pair: the two values of a coefficient are adjacent, one
+      // store (when the output is aligned for it)
+      static_assert(kTight == 2 && NLB == 2, "pair stores take two lines");
+      const bool pst = pil_out && ((reinterpret_cast<unsigned long long>(dst) & (2 * sizeof(TOUT) - 1)) == 0);
+      if (tight || pil_out) {
         // one wave number per lane; its table entries are read once for
         // all the lines
         for (int k = 1 + tid; k < K; k += nthr) {
@@ -978,12 +1019,23 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
 #pragma unroll
                 for (int s = 0; s < N; ++s) x[u][s] = at<T, N, K>(lslots(u0 + u < cv ? u0 + u : 0), s, k);
               fwd_lines<T, N, NLB>(blk_at<N>(BLK, k), x, acc);
+              if (pst) {
+                const long long ob = lbase(0) + 2 * ((long long)(N - 1) + (k - 1));
 #pragma unroll
-              for (int u = 0; u < NLB; ++u) {
-                if (u0 + u < cv) {
-                  const long long ob = tbase[u0 + u] + ((long long)(N - 1) + (k - 1)) * inner;
+                for (int l = 0; l < N; ++l) {
+                  pair2<TOUT> v;
+                  v.a = (TOUT)acc[0][l];
+                  v.b = (TOUT)acc[1][l];
+                  *reinterpret_cast<pair2<TOUT>*>(dst + ob + 2LL * l * KM) = v;
+                }
+              } else {
 #pragma unroll
-                  for (int l = 0; l < N; ++l) dst[ob + (long long)l * KM * inner] = (TOUT)acc[u][l];
+                for (int u = 0; u < NLB; ++u) {
+                  if (u0 + u < cv) {
+                    const long long ob = obase(u0 + u) + ((long long)(N - 1) + (k - 1)) * ostep;
+#pragma unroll
+                    for (int l = 0; l < N; ++l) dst[ob + (long long)l * KM * ostep] = (TOUT)acc[u][l];
+                  }
                 }
               }
             }
@@ -1007,9 +1059,9 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
 #pragma unroll
           for (int s = 0; s < N; ++s) x[0][s] = at<T, N, K>(lslots(c), s, k);
           fwd_lines<T, N, 1>(blk_at<N>(BLK, k), x, acc);
-          const long long ob = base[c] + ((long long)(N - 1) + (k - 1)) * inner;
+          const long long ob = obase(c) + ((long long)(N - 1) + (k - 1)) * ostep;
 #pragma unroll
-          for (int l = 0; l < N; ++l) dst[ob + (long long)l * KM * inner] = (TOUT)acc[0][l];
+          for (int l = 0; l < N; ++l) dst[ob + (long long)l * KM * ostep] = (TOUT)acc[0][l];
         }
       }
       // k = 0: w_{0l} = S0 . e^(l) / K
@@ -1020,7 +1072,7 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
           T acc = T(0);
 #pragma unroll
           for (int s = 0; s < N - 1; ++s) acc += EV[s * (N - 1) + l] * at<T, N, K>(lslots(c), s + 1, 0);
-          dst[lbase(c) + (long long)l * inner] = (TOUT)(acc / (T)K);
+          dst[obase(c) + (long long)l * ostep] = (TOUT)(acc / (T)K);
         }
       }
       return;
@@ -1226,7 +1278,15 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
       const int c = tid & (cb - 1);
       const int qs = nthr >> lcb;
       if (c < cv) {
-        TOUT* d = dst + lbase(c);
+        const long long b = lbase(c);
+        TOUT* d = dst + b;
+        const long long ilv = a.ilv_out;
+        long long orow = 0, tcol = 0;
+        if (ilv > 0) {
+          const long long o = b / MI;
+          orow = o * M;
+          tcol = b - o * MI;
+        }
         for (int q0 = tid >> lcb; q0 < M; q0 += SU * qs) {
           T val[SU];
 #pragma unroll
@@ -1234,7 +1294,7 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
 #pragma unroll
           for (int u = 0; u < SU; ++u) {
             const int q = q0 + u * qs;
-            if (q < M) store(d[(long long)q * inner], val[u]);
+            if (q < M) store(d[(long long)q * inner + ilv_shift(ilv, orow, tcol, q)], val[u]);
           }
         }
       }
@@ -1297,6 +1357,13 @@ template <typename T, int N, int LOG2K, int MODE, typename TIN, typename TOUT>
 hipError_t launch_k(const PassArgs& a0, hipStream_t s) {
   const Shape sh = shape_for(N, 1 << LOG2K, sizeof(cx<T>), a0.nlines);
   if (a0.tab.n != N || a0.tab.K != (1 << LOG2K)) return hipErrorInvalidValue;
+  if (a0.ilv_in > 0 || a0.ilv_out > 0) {
+    // the row-pair interleaved forms this kernel implements
+    const bool rows = a0.inner == 1;
+    if (rows && sh.cb != 2) return hipErrorInvalidValue;
+    if (a0.ilv_out > 0 && (rows ? MODE != PASS_FWD : MODE == PASS_FWD)) return hipErrorInvalidValue;
+    if ((a0.ilv_in | a0.ilv_out) & 1) return hipErrorInvalidValue;
+  }
   PassArgs a = a0;
   a.cb = sh.cb;
   auto fn = line_pass<T, N, LOG2K, MODE, TIN, TOUT>;

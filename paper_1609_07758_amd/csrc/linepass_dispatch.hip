@@ -18,4 +18,8 @@ hipError_t launch_pass(int kind, int dt, const PassArgs& a, hipStream_t s) {
   }
 }
 
+int pass_lines_per_workgroup(int n, int K, bool f64, long long nlines) {
+  return lp::shape_for(n, K, f64 ? 16 : 8, nlines).cb;
+}
+
 }  // namespace hofem

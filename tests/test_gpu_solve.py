@@ -108,6 +108,41 @@ def test_nrhs_and_in_place():
         assert rel(got[r], osolve.solve(f[r], orders, Ks, X, 0.5)) < 1e-12
 
 
+# The 2D solve keeps its intermediate row-pair interleaved when the row
+# passes take two lines per workgroup: rows laid out padded and tight, rows
+# of several right-hand sides paired across their boundary, an odd last row.
+ILV_CASES = [
+    ((2, 9), (4, 256), 3),   # FP64 rows padded, 7 rows per right-hand side
+    ((2, 7), (4, 512), 1),   # FP64 rows tight, 7 rows
+    ((3, 7), (2, 512), 2),   # FP64 rows tight, 5 rows per right-hand side
+]
+
+
+@pytest.mark.parametrize("orders,Ks,nrhs", ILV_CASES)
+def test_fp64_2d_row_pair_intermediate(orders, Ks, nrhs):
+    X, alpha = (1.0, 1.0), 0.25
+    shp = workloads.shape(orders, Ks)
+    f = np.stack([workloads.uniform_rhs(shp, seed=10 + s) for s in range(nrhs)])
+    S = H.Solver(orders, Ks, X, alpha)
+    got = host(S.solve(gpu(f), mode="fp64", nrhs=nrhs))
+    for r in range(nrhs):
+        assert rel(got[r], osolve.solve(f[r], orders, Ks, X, alpha)) < 1e-12
+    buf = gpu(f)
+    S.solve(buf, buf, mode="fp64", nrhs=nrhs)          # in place
+    assert np.array_equal(host(buf), got)
+
+
+def test_fp32_2d_row_pair_intermediate():
+    orders, Ks, X = (2, 9), (4, 512), (1.0, 1.0)   # FP32 rows padded, two per workgroup
+    shp = workloads.shape(orders, Ks)
+    f = workloads.uniform_rhs(shp, seed=21)
+    got, _ = run_case(orders, Ks, X, 0.0, f.astype(np.float32), mode="fp32")
+    assert rel(got, osolve.solve(f.astype(np.float32).astype(np.float64), orders, Ks, X, 0.0)) < 1e-5
+    # fixed step count: the steps add their correction in the last pass
+    got_ir, _ = run_case(orders, Ks, X, 0.0, f, mode="fp32_ir", max_iter=3, tol=0.0)
+    assert rel(got_ir, osolve.solve(f, orders, Ks, X, 0.0)) < 1e-4
+
+
 def test_forward_inverse_roundtrip_is_mass_inverse():
     # inverse(forward(y)) = C^-1 y along every axis: check with y = (x)C g.
     orders, Ks = (4, 3), (8, 16)
