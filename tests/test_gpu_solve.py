@@ -115,6 +115,8 @@ ILV_CASES = [
     ((2, 9), (4, 256), 3),   # FP64 rows padded, 7 rows per right-hand side
     ((2, 7), (4, 512), 1),   # FP64 rows tight, 7 rows
     ((3, 7), (2, 512), 2),   # FP64 rows tight, 5 rows per right-hand side
+    ((2, 9), (4, 512), 1),   # FP64 rows tight, n = 9 (two rounds of transform tasks)
+    ((3, 9), (2, 512), 3),   # the same, 15 rows: a lone last row
 ]
 
 
