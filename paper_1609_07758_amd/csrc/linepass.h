@@ -661,6 +661,8 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
   // Along the columns: value q of the line whose plain address is b moves
   // by ilv_shift.
   const bool pil_in = !cfast && a.ilv_in > 0 && cv == 2 && L0 + 1 < a.ilv_in;
+  // one line of an interleaved pair: its values every other entry
+  const bool sil_in = !cfast && a.ilv_in > 0 && cb == 1 && L0 < a.ilv_in;
   const bool pil_out = !cfast && a.ilv_out > 0 && cv == 2 && L0 + 1 < a.ilv_out;
   const long long MI = (long long)M * inner;
   // row L = o M + q of column t (plain address L inner + t) sits at
@@ -748,7 +750,23 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
   // lanes.  Strided axis: lane (q, c) with c = tid mod cb, so adjacent lanes
   // read adjacent lines (adjacent in memory).  kUnroll loads in flight per
   // lane: one round for the longest lines.
-  if (!cfast) {
+  if (sil_in) {
+    const TIN* sp = src + (L0 & ~1LL) * M + (L0 & 1);
+    for (int q0 = tid; q0 < M; q0 += kUnroll * nthr) {
+      TIN r[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int q = q0 + u * nthr < M ? q0 + u * nthr : 0;
+        r[u] = sp[2 * q];
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int q = q0 + u * nthr;
+        if (q < M) in_entry(0, q) = (T)r[u];
+      }
+    }
+    __syncthreads();
+  } else if (!cfast) {
     // 16-byte loads from the first 16-byte boundary on; the elements before
     // it and the last few one by one
     const TIN* sp = src + L0 * M;
@@ -1312,14 +1330,17 @@ struct Shape {
 // tight one with as many lines (at most kTight) as the CU's LDS share of one
 // workgroup holds: 160 KB divided by the workgroups per CU that the register
 // budget allows.
-inline Shape shape_for(int n, int K, size_t cplx_bytes, long long nlines) {
+inline Shape shape_for(int n, int K, size_t cplx_bytes, long long nlines, bool one_line = false) {
   const int NP = (n + 1) / 2;
   const bool f64 = cplx_bytes == 16;
   const int rmax = (f64 && K <= 512) ? 8 : 16;   // as log2_rmax
   const int R = K < rmax ? K : rmax;
   const int G = K / R;
   const int TPW = 64 / G;
-  const int threads = f64 ? threads_for<double>() : threads_for<float>();
+  int threads = f64 ? threads_for<double>() : threads_for<float>();
+  // long FP64 lines one per 256-lane workgroup (two workgroups per CU) for
+  // the inverse pass along the rows
+  if (f64 && one_line && tight_layout(n, K, (int)cplx_bytes)) threads = 256;
   const size_t per_line = ((size_t)NP * K + 1) * cplx_bytes;
   Shape s;
   s.threads = threads;
@@ -1355,12 +1376,14 @@ inline Shape shape_for(int n, int K, size_t cplx_bytes, long long nlines) {
 
 template <typename T, int N, int LOG2K, int MODE, typename TIN, typename TOUT>
 hipError_t launch_k(const PassArgs& a0, hipStream_t s) {
-  const Shape sh = shape_for(N, 1 << LOG2K, sizeof(cx<T>), a0.nlines);
+  constexpr bool kInv = MODE == PASS_INV || MODE == PASS_INV_ACC;
+  const Shape sh = shape_for(N, 1 << LOG2K, sizeof(cx<T>), a0.nlines,
+                             kInv && sizeof(T) == 8 && a0.inner == 1);
   if (a0.tab.n != N || a0.tab.K != (1 << LOG2K)) return hipErrorInvalidValue;
   if (a0.ilv_in > 0 || a0.ilv_out > 0) {
     // the row-pair interleaved forms this kernel implements
     const bool rows = a0.inner == 1;
-    if (rows && sh.cb != 2) return hipErrorInvalidValue;
+    if (rows && sh.cb != 2 && !(sh.cb == 1 && a0.ilv_out == 0)) return hipErrorInvalidValue;
     if (a0.ilv_out > 0 && (rows ? MODE != PASS_FWD : MODE == PASS_FWD)) return hipErrorInvalidValue;
     if ((a0.ilv_in | a0.ilv_out) & 1) return hipErrorInvalidValue;
   }
