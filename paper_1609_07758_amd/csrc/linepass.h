@@ -54,14 +54,16 @@ namespace hofem {
 namespace lp {
 
 constexpr int kMaxCB = 64;         // lines per workgroup (upper bound)
-// Workgroup size: 16 waves (up to 128 VGPRs per lane) in FP32, 8 waves (up
-// to 256) in FP64, whose FFT registers do not fit in 128.  Every workgroup
-// has the maximum size: the load, block and scatter phases use all lanes.
+// Workgroup size: 8 waves (the register budget of waves_per_simd_of decides
+// how many workgroups share a CU); the load, block and scatter phases use
+// all lanes.  The one exception, set by shape_for: the inverse row pass of
+// long FP64 lines runs 4 waves per line, two workgroups per CU.
 template <typename T>
 constexpr int threads_for() { return 512; }
 // global loads in flight per lane: one round for the workgroup's values
 // (at most 64 KB of lines per workgroup in the padded layout; the tight
-// layout's two lines take ceil(2 (nK - 1) / 512) per lane)
+// layout's two lines take ceil(2 (nK - 1) / 512) per lane, and so does one
+// line on 256 lanes)
 template <typename T, int N, int LOG2K, bool TIGHT>
 constexpr int unroll_for() {
   return TIGHT ? (2 * (N * (1 << LOG2K) - 1) + 511) / 512 : (sizeof(T) == 8 && LOG2K >= 10) ? 32 : 16;
@@ -1329,7 +1331,9 @@ struct Shape {
 // the padded layout (80 KB per workgroup in FP64, 64 KB in FP32); longer lines use the
 // tight one with as many lines (at most kTight) as the CU's LDS share of one
 // workgroup holds: 160 KB divided by the workgroups per CU that the register
-// budget allows.
+// budget allows.  one_line: the inverse pass along the rows in FP64, whose
+// long lines then go one per 256-lane workgroup (two per CU, their phases
+// overlapping).
 inline Shape shape_for(int n, int K, size_t cplx_bytes, long long nlines, bool one_line = false) {
   const int NP = (n + 1) / 2;
   const bool f64 = cplx_bytes == 16;
@@ -1338,8 +1342,6 @@ inline Shape shape_for(int n, int K, size_t cplx_bytes, long long nlines, bool o
   const int G = K / R;
   const int TPW = 64 / G;
   int threads = f64 ? threads_for<double>() : threads_for<float>();
-  // long FP64 lines one per 256-lane workgroup (two workgroups per CU) for
-  // the inverse pass along the rows
   if (f64 && one_line && tight_layout(n, K, (int)cplx_bytes)) threads = 256;
   const size_t per_line = ((size_t)NP * K + 1) * cplx_bytes;
   Shape s;
