@@ -145,6 +145,34 @@ def test_fp32_2d_row_pair_intermediate():
     assert rel(got_ir, osolve.solve(f, orders, Ks, X, 0.0)) < 1e-4
 
 
+def test_fp32_refined_row_pairs_across_right_hand_sides():
+    # two right-hand sides of 7 rows: the FP32 passes pair row 6 of the first
+    # with row 0 of the second
+    orders, Ks, X = (2, 9), (4, 512), (1.0, 1.0)
+    shp = workloads.shape(orders, Ks)
+    f = np.stack([workloads.uniform_rhs(shp, seed=30 + s) for s in range(2)])
+    got, _ = run_case(orders, Ks, X, 0.0, f, mode="fp32_ir", nrhs=2, max_iter=3, tol=0.0)
+    for r in range(2):
+        assert rel(got[r], osolve.solve(f[r], orders, Ks, X, 0.0)) < 1e-4
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32"])
+def test_forward_inverse_roundtrip_long_lines(mode):
+    # plain coefficient layout through the long-line passes (two lines per
+    # workgroup forward, one per workgroup inverse in FP64)
+    orders, Ks = (2, 9), (4, 512)
+    shp = workloads.shape(orders, Ks)
+    g = workloads.uniform_rhs(shp, seed=31)
+    y = assembly.apply_mass(g, orders, Ks)
+    S = H.Solver(orders, Ks, (1.0, 1.0), 0.0)
+    dt = torch.float64 if mode == "fp64" else torch.float32
+    back = host(S.inverse(S.forward(gpu(y, dt), mode=mode), mode=mode))
+    # the round trip applies the mass inverse (cond(C) is about 290 per axis
+    # for n = 9, 8e4 in 2D), so its rounding error grows with that condition:
+    # 3e-13 in FP64, 2e-4 in FP32 measured; a wrong layout would give O(1)
+    assert rel(back, g) < (1e-12 if mode == "fp64" else 1e-3)
+
+
 def test_forward_inverse_roundtrip_is_mass_inverse():
     # inverse(forward(y)) = C^-1 y along every axis: check with y = (x)C g.
     orders, Ks = (4, 3), (8, 16)
