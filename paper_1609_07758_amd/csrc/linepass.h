@@ -823,17 +823,50 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
         orow = o * M;
         tcol = b - o * MI;
       }
-      for (int q0 = tid >> lcb; q0 < M; q0 += kUnroll * qs) {
-        TIN r[kUnroll];
+      // Row pairs of the interleaved input: one load brings both rows of the
+      // column (16 bytes in FP64).  Pairs start at even grid rows; the rows
+      // outside whole pairs (at most one at each end) go one by one.
+      const bool pairs = ilv > 0 && ((reinterpret_cast<unsigned long long>(src) & (2 * sizeof(TIN) - 1)) == 0);
+      const int qa = pairs ? (int)(orow & 1) : M;                     // first paired row
+      const long long lim = min((long long)M, ilv - orow);             // rows below ilv
+      const int npair = pairs && lim > qa ? (int)((lim - qa) / 2) : 0;
+      const int qb = qa + 2 * npair;                                   // first row after them
+      if (pairs) {
+        const pair2<TIN>* pp = reinterpret_cast<const pair2<TIN>*>(src + (orow + qa) * inner + 2 * tcol);
+        constexpr int KP = (kUnroll + 1) / 2;
+        for (int p0 = tid >> lcb; p0 < npair; p0 += KP * qs) {
+          pair2<TIN> r[KP];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          const int q = q0 + u * qs < M ? q0 + u * qs : 0;
-          r[u] = sp[(long long)q * inner + ilv_shift(ilv, orow, tcol, q)];
+          for (int u = 0; u < KP; ++u) {
+            const int pi = p0 + u * qs < npair ? p0 + u * qs : 0;
+            r[u] = pp[(long long)pi * inner];                          // rows 2 pi, 2 pi + 1 past qa
+          }
+#pragma unroll
+          for (int u = 0; u < KP; ++u) {
+            const int pi = p0 + u * qs;
+            if (pi < npair) {
+              in_entry(c, qa + 2 * pi) = (T)r[u].a;
+              in_entry(c, qa + 2 * pi + 1) = (T)r[u].b;
+            }
+          }
         }
+        // the rows before the first pair and after the last
+        const int lt = tid >> lcb;
+        const int q = lt < qa ? lt : qb + (lt - qa);
+        if (lt < qa + (M - qb) && q < M) in_entry(c, q) = (T)sp[(long long)q * inner + ilv_shift(ilv, orow, tcol, q)];
+      } else {
+        for (int q0 = tid >> lcb; q0 < M; q0 += kUnroll * qs) {
+          TIN r[kUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          const int q = q0 + u * qs;
-          if (q < M) in_entry(c, q) = (T)r[u];
+          for (int u = 0; u < kUnroll; ++u) {
+            const int q = q0 + u * qs < M ? q0 + u * qs : 0;
+            r[u] = sp[(long long)q * inner + ilv_shift(ilv, orow, tcol, q)];
+          }
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+            const int q = q0 + u * qs;
+            if (q < M) in_entry(c, q) = (T)r[u];
+          }
         }
       }
     }
