@@ -1340,14 +1340,52 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
           orow = o * M;
           tcol = b - o * MI;
         }
-        for (int q0 = tid >> lcb; q0 < M; q0 += SU * qs) {
-          T val[SU];
+        // row pairs of the interleaved output: one store for both rows of
+        // the column (as the column loads)
+        const bool pairs = ilv > 0 && ((reinterpret_cast<unsigned long long>(dst) & (2 * sizeof(TOUT) - 1)) == 0);
+        if (pairs) {
+          const int qa = (int)(orow & 1);
+          const long long lim = min((long long)M, ilv - orow);
+          const int npair = lim > qa ? (int)((lim - qa) / 2) : 0;
+          const int qb = qa + 2 * npair;
+          pair2<TOUT>* pp = reinterpret_cast<pair2<TOUT>*>(dst + (orow + qa) * inner + 2 * tcol);
+          constexpr int SUP = SU / 2;
+          for (int p0 = tid >> lcb; p0 < npair; p0 += SUP * qs) {
+            pair2<TOUT> v[SUP];
 #pragma unroll
-          for (int u = 0; u < SU; ++u) val[u] = value(c, min(q0 + u * qs, M - 1));
+            for (int u = 0; u < SUP; ++u) {
+              const int pi = min(p0 + u * qs, npair - 1);
+              v[u].a = (TOUT)value(c, qa + 2 * pi);
+              v[u].b = (TOUT)value(c, qa + 2 * pi + 1);
+            }
 #pragma unroll
-          for (int u = 0; u < SU; ++u) {
-            const int q = q0 + u * qs;
-            if (q < M) store(d[(long long)q * inner + ilv_shift(ilv, orow, tcol, q)], val[u]);
+            for (int u = 0; u < SUP; ++u) {
+              const int pi = p0 + u * qs;
+              if (pi < npair) {
+                if constexpr (kAcc) {
+                  pair2<TOUT> o = pp[(long long)pi * inner];
+                  o.a += v[u].a;
+                  o.b += v[u].b;
+                  pp[(long long)pi * inner] = o;
+                } else {
+                  pp[(long long)pi * inner] = v[u];
+                }
+              }
+            }
+          }
+          const int lt = tid >> lcb;
+          const int q = lt < qa ? lt : qb + (lt - qa);
+          if (lt < qa + (M - qb) && q < M) store(d[(long long)q * inner + ilv_shift(ilv, orow, tcol, q)], value(c, q));
+        } else {
+          for (int q0 = tid >> lcb; q0 < M; q0 += SU * qs) {
+            T val[SU];
+#pragma unroll
+            for (int u = 0; u < SU; ++u) val[u] = value(c, min(q0 + u * qs, M - 1));
+#pragma unroll
+            for (int u = 0; u < SU; ++u) {
+              const int q = q0 + u * qs;
+              if (q < M) store(d[(long long)q * inner + ilv_shift(ilv, orow, tcol, q)], val[u]);
+            }
           }
         }
       }
