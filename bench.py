@@ -321,7 +321,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--ir-iters", type=int, default=3)
+    ap.add_argument("--ir-iters", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", default="large_2d,batch_2d,cube_3d,varcoef_3d",
                     help="comma-separated workloads; large_2d is the headline")

@@ -24,12 +24,12 @@
  * eq. (bvp glob 2): the load vector int f phi divided by prod_i (h_i / 2).
  *
  * Memory.  Pointers named *_dev are device pointers on the current HIP
- * device, owned by the caller.  Pointers named *_host are host memory owned
- * by the caller.  Handles are owned by the library and released by the
- * matching destroy call.  Solver creation allocates the solver's device
- * tables (a few MB at most) with hipMalloc on the current device; no other
- * call allocates device memory: temporary storage is the caller's
- * workspace, sized by hofem_solver_workspace_bytes.
+ * device, owned by the caller: grids, workspaces and the plans' device
+ * tables (hofem_plan1d_upload).  Pointers named *_host are host memory owned
+ * by the caller.  Handles are host structures owned by the library and
+ * released by the matching destroy call.  No call allocates device memory:
+ * temporary storage is the caller's workspace, sized by the
+ * *_workspace_bytes calls.
  *
  * Streams.  `stream` is a hipStream_t passed as void* (NULL = default
  * stream).  Calls enqueue work and return without synchronising, except
@@ -102,7 +102,8 @@ typedef struct {
  * eigenpairs of eq. (eig_elem).  Computed on the host in binary128 and
  * rounded once.  1 <= n <= 9 (simple element spectra are verified up to 9),
  * K a power of two with 2 <= K <= 1024.  Returns HOFEM_EUNSUPPORTED
- * otherwise.  Plans are immutable and may be shared between threads. */
+ * otherwise.  A plan changes only in hofem_plan1d_upload; otherwise it is
+ * read-only and may be shared between threads. */
 int hofem_plan1d_create(int n, int K, hofem_plan1d* out);
 void hofem_plan1d_destroy(hofem_plan1d plan);
 
@@ -126,15 +127,32 @@ int hofem_plan1d_dim(hofem_plan1d plan, int* m);
  * HOFEM_EINVAL. */
 int hofem_plan1d_table(hofem_plan1d plan, int which, double* out_host, size_t len);
 
+/* Bytes of the plan's device tables: the eigenvalues (FP64), the vectors
+ * p_k^(l) with the norms 1/||s_k^(l)||_C^2 (FP64 and FP32, blocked by 64
+ * wave numbers), e^(l), the FFT twiddles and sin(pi t/K) (FP64 and FP32),
+ * the local matrices and the Gauss rule tables (FP64).  Under 2 MB for
+ * n = 9, K = 1024.  A multiple of 256. */
+int hofem_plan1d_table_bytes(hofem_plan1d plan, size_t* bytes);
+
+/* Copies the plan's device tables into dev_buf (caller-owned device memory
+ * on the current device, 256-byte aligned, at least
+ * hofem_plan1d_table_bytes) and records it in the plan; returns after the
+ * copy has completed (the call waits for `stream`).  dev_buf must stay
+ * allocated and unchanged while any solver created from this plan is in use.
+ * Uploading again re-targets the plan for solvers created afterwards.
+ * HOFEM_EINVAL for a NULL or misaligned buffer or too few bytes. */
+int hofem_plan1d_upload(hofem_plan1d plan, void* dev_buf, size_t bytes, void* stream);
+
 /* ---- N-D solver (device) ---------------------------------------------- */
 
 /* Solver for eq. (bvp glob 2) on (0,X_0) x ... x (0,X_{N-1}), 1 <= N <= 3,
  * with one plan per axis (plans[i] for axis i; the same plan may be used for
  * several axes) and the constant alpha.  Checks that every denominator
  * alpha + sum_i 4 h_i^-2 lambda_i is positive (the condition on alpha of
- * eq. (diff bvp pr2)), else HOFEM_ENOTPOSDEF.  Allocates and uploads the
- * FP64 and FP32 tables on the current device.  The plans may be destroyed
- * after this call. */
+ * eq. (diff bvp pr2)), else HOFEM_ENOTPOSDEF.  Every plan must have been
+ * uploaded (hofem_plan1d_upload) on the current device, else HOFEM_EINVAL;
+ * the solver reads the tables in those device buffers.  The plan handles may
+ * be destroyed after this call, their device buffers may not. */
 int hofem_solver_create(int N, const hofem_plan1d* plans, const double* X, double alpha,
                         hofem_solver* out);
 void hofem_solver_destroy(hofem_solver solver);
@@ -206,16 +224,27 @@ int hofem_apply_coef_operator(hofem_solver solver, const hofem_coef* coef, const
                               double* out_dev, int nrhs, void* ws_dev, size_t ws_bytes,
                               void* stream);
 
+/* Workspace bytes of hofem_apply_operator and hofem_apply_mass: for N = 3
+ * with equal orders the element outputs of one right-hand side,
+ * prod K_i (n+1)^3 doubles (rounded up to 256 bytes); 0 otherwise. */
+int hofem_operator_workspace_bytes(hofem_solver solver, size_t* bytes);
+
 /* out = L u with L the operator of eq. (bvp glob 2), FP64, matrix-free
  * (sum-factorised products of the 1D element matrices), the stiffness
- * factors in difference form
- * sum_{l != k} A_kl (v_l - v_k) so that constants are exactly in their
- * kernel.  u_dev != out_dev.  For N = 3 with equal orders the element
- * outputs go through a device buffer of prod K_i (n+1)^3 doubles that the
- * solver allocates on the first operator apply (this call, FP32_IR or
- * FP32_PCG) and frees in hofem_solver_destroy; HOFEM_ENOMEM if it cannot. */
+ * factors in difference form sum_{l != k} A_kl (v_l - v_k) so that
+ * constants are exactly in their kernel.  u_dev != out_dev.  ws_dev: at least
+ * hofem_operator_workspace_bytes (may be NULL when that is 0); HOFEM_EINVAL
+ * otherwise. */
 int hofem_apply_operator(hofem_solver solver, const double* u_dev, double* out_dev, int nrhs,
-                         void* stream);
+                         void* ws_dev, size_t ws_bytes, void* stream);
+
+/* out = ((x)_i C_i) g: the mass product of eq. (bvp glob 2), which turns
+ * nodal values g of a function into the algebraic right-hand side f^h of
+ * its FEM interpolant (f^h = C g along every axis, the load vector of the
+ * interpolant divided by prod_i (h_i / 2)).  FP64, same kernels, layout and
+ * workspace as hofem_apply_operator; g_dev != out_dev. */
+int hofem_apply_mass(hofem_solver solver, const double* g_dev, double* out_dev, int nrhs,
+                     void* ws_dev, size_t ws_bytes, void* stream);
 
 /* ---- batched form -------------------------------------------------------- */
 

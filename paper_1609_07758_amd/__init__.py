@@ -65,6 +65,8 @@ SIGNATURES = {
     "hofem_plan1d_destroy": (None, [_vp]),
     "hofem_plan1d_dim": (_c_int, [_vp, ctypes.POINTER(_c_int)]),
     "hofem_plan1d_table": (_c_int, [_vp, _c_int, ctypes.POINTER(_c_double), _c_size]),
+    "hofem_plan1d_table_bytes": (_c_int, [_vp, ctypes.POINTER(_c_size)]),
+    "hofem_plan1d_upload": (_c_int, [_vp, _vp, _c_size, _vp]),
     "hofem_solver_create": (_c_int, [_c_int, ctypes.POINTER(_vp), ctypes.POINTER(_c_double), _c_double,
                                      ctypes.POINTER(_vp)]),
     "hofem_solver_destroy": (None, [_vp]),
@@ -74,7 +76,9 @@ SIGNATURES = {
                              ctypes.POINTER(hofem_info)]),
     "hofem_forward": (_c_int, [_vp, _c_int, _vp, _vp, _c_int, _vp]),
     "hofem_inverse": (_c_int, [_vp, _c_int, _vp, _vp, _c_int, _vp]),
-    "hofem_apply_operator": (_c_int, [_vp, _vp, _vp, _c_int, _vp]),
+    "hofem_operator_workspace_bytes": (_c_int, [_vp, ctypes.POINTER(_c_size)]),
+    "hofem_apply_operator": (_c_int, [_vp, _vp, _vp, _c_int, _vp, _c_size, _vp]),
+    "hofem_apply_mass": (_c_int, [_vp, _vp, _vp, _c_int, _vp, _c_size, _vp]),
     "hofem_batch_create": (_c_int, [ctypes.POINTER(hofem_batch_problem), _c_int,
                                     ctypes.POINTER(_vp)]),
     "hofem_batch_destroy": (None, [_vp]),
@@ -161,6 +165,18 @@ def hofem_plan1d_table(plan, which, count):
     return out
 
 
+def hofem_plan1d_table_bytes(plan):
+    b = ctypes.c_size_t()
+    _check(_lib.hofem_plan1d_table_bytes(plan, ctypes.byref(b)), "hofem_plan1d_table_bytes")
+    return b.value
+
+
+def hofem_plan1d_upload(plan, buf, stream=None):
+    """Copies the plan's device tables into `buf` (a uint8 device tensor)."""
+    _check(_lib.hofem_plan1d_upload(plan, _ptr(buf), buf.numel() * buf.element_size(),
+                                    _stream(stream)), "hofem_plan1d_upload")
+
+
 def hofem_solver_create(plans, X, alpha):
     N = len(plans)
     arr = (ctypes.c_void_p * N)(*[p.value if isinstance(p, ctypes.c_void_p) else p for p in plans])
@@ -210,9 +226,23 @@ def hofem_inverse(solver, mode, x, y, nrhs=1, stream=None):
            "hofem_inverse")
 
 
-def hofem_apply_operator(solver, u, out, nrhs=1, stream=None):
-    _check(_lib.hofem_apply_operator(solver, _ptr(u), _ptr(out), int(nrhs), _stream(stream)),
-           "hofem_apply_operator")
+def hofem_operator_workspace_bytes(solver):
+    b = ctypes.c_size_t()
+    _check(_lib.hofem_operator_workspace_bytes(solver, ctypes.byref(b)),
+           "hofem_operator_workspace_bytes")
+    return b.value
+
+
+def hofem_apply_operator(solver, u, out, nrhs=1, ws=None, stream=None):
+    wsb = 0 if ws is None else ws.numel() * ws.element_size()
+    _check(_lib.hofem_apply_operator(solver, _ptr(u), _ptr(out), int(nrhs), _ptr(ws), wsb,
+                                     _stream(stream)), "hofem_apply_operator")
+
+
+def hofem_apply_mass(solver, g, out, nrhs=1, ws=None, stream=None):
+    wsb = 0 if ws is None else ws.numel() * ws.element_size()
+    _check(_lib.hofem_apply_mass(solver, _ptr(g), _ptr(out), int(nrhs), _ptr(ws), wsb,
+                                 _stream(stream)), "hofem_apply_mass")
 
 
 def make_coef(kind=0, c0=1.0, c1=0.0, t=(None, None, None), a=None):
@@ -366,6 +396,13 @@ class Plan1D:
         self.handle = hofem_plan1d_create(n, K)
         self.m = hofem_plan1d_dim(self.handle)
 
+    def upload(self, device="cuda"):
+        """Device tables in a caller-owned uint8 tensor (kept alive by the caller)."""
+        import torch
+        buf = torch.empty(hofem_plan1d_table_bytes(self.handle), dtype=torch.uint8, device=device)
+        hofem_plan1d_upload(self.handle, buf)
+        return buf
+
     def table(self, which):
         n, K = self.n, self.K
         counts = {"lam": self.m, "p": (K - 1) * n * (n - 1), "inorm": (K - 1) * n,
@@ -393,10 +430,17 @@ class Solver:
         self.Ks = [int(k) for k in Ks]
         self.X = [float(x) for x in X]
         self.alpha = float(alpha)
-        plans = [Plan1D(n, K) for n, K in zip(self.orders, self.Ks)]
-        self.shape = tuple(p.m for p in plans)
-        self.handle = hofem_solver_create([p.handle for p in plans], self.X, self.alpha)
-        for p in plans:
+        self.handle = None
+        plans = {}
+        for n, K in zip(self.orders, self.Ks):
+            if (n, K) not in plans:
+                plans[(n, K)] = Plan1D(n, K)
+        # the plans' device tables: caller-owned, alive as long as the solver
+        self._tables = [p.upload() for p in plans.values()]
+        axis_plans = [plans[(n, K)] for n, K in zip(self.orders, self.Ks)]
+        self.shape = tuple(p.m for p in axis_plans)
+        self.handle = hofem_solver_create([p.handle for p in axis_plans], self.X, self.alpha)
+        for p in plans.values():
             p.close()
         self.size = hofem_solver_size(self.handle)
 
@@ -468,10 +512,26 @@ class Solver:
         hofem_inverse(self.handle, mode, x, y, nrhs, stream)
         return y
 
-    def apply_operator(self, u, out=None, nrhs=1, stream=None):
+    def operator_workspace(self, device="cuda"):
+        import torch
+        b = hofem_operator_workspace_bytes(self.handle)
+        return torch.empty(b, dtype=torch.uint8, device=device) if b else None
+
+    def apply_operator(self, u, out=None, nrhs=1, ws=None, stream=None):
         import torch
         out = torch.empty_like(u) if out is None else out
-        hofem_apply_operator(self.handle, u, out, nrhs, stream)
+        if ws is None:
+            ws = self.operator_workspace(u.device)
+        hofem_apply_operator(self.handle, u, out, nrhs, ws, stream)
+        return out
+
+    def apply_mass(self, g, out=None, nrhs=1, ws=None, stream=None):
+        """f^h = (x)_i C_i g: right-hand side of the FEM interpolant of nodal values g."""
+        import torch
+        out = torch.empty_like(g) if out is None else out
+        if ws is None:
+            ws = self.operator_workspace(g.device)
+        hofem_apply_mass(self.handle, g, out, nrhs, ws, stream)
         return out
 
     def set_timing(self, enable=True):

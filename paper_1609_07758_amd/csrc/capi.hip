@@ -22,8 +22,17 @@
 
 using namespace hofem;
 
+// Byte offsets of one plan's tables in its device image (256-byte aligned).
+struct PlanOff {
+  size_t lam, blk64, E64, tw64, sn64, blk32, E32, tw32, sn32, A, C, B, D, Dh, gw;
+};
+
 struct hofem_plan1d_s {
   Plan1DData d;
+  std::vector<unsigned char> image;   // device table image, built at creation
+  PlanOff off{};
+  const unsigned char* dev = nullptr; // the image in the caller's device buffer
+  int device = -1;                    // device of that buffer
 };
 
 namespace {
@@ -92,10 +101,7 @@ struct hofem_solver_s {
   double alpha = 0;
   int device = 0;
   DevAxis ax[3];
-  void* mem = nullptr;
   size_t per_rhs = 0;
-  // element outputs of the 3D operator (allocated on its first use)
-  double* op_elem = nullptr;
   // per-pass timing
   bool timing = false;
   std::vector<hipEvent_t> event_pool;
@@ -204,13 +210,16 @@ int run_list(hofem_solver_s* S, const std::vector<PassSpec>& list, bool f64, con
 // workgroup, the intermediate between the passes is row-pair interleaved:
 // the row passes then move contiguous blocks and the column pass moves
 // twice the bytes per access.
-std::vector<PassSpec> solve_list(const hofem_solver_s* S, bool f64) {
+// The decision uses the launch shape of the forward row pass for all nrhs
+// right-hand sides (m_0 nrhs rows), as the launcher computes it.
+std::vector<PassSpec> solve_list(const hofem_solver_s* S, bool f64, int nrhs) {
   const int N = S->N;
   std::vector<PassSpec> l;
   for (int a = N - 1; a >= 1; --a) l.push_back({a, PASS_FWD});
   l.push_back({0, PASS_FUSED});
   for (int a = 1; a < N; ++a) l.push_back({a, PASS_INV});
-  if (N == 2 && pass_lines_per_workgroup(S->ax[1].n, S->ax[1].K, f64, S->ax[0].m) == 2) {
+  if (N == 2 &&
+      pass_lines_per_workgroup(S->ax[1].n, S->ax[1].K, f64, (long long)S->ax[0].m * nrhs) == 2) {
     l[0].il_out = true;
     l[1].il_in = l[1].il_out = true;
     l[2].il_in = true;
@@ -218,16 +227,39 @@ std::vector<PassSpec> solve_list(const hofem_solver_s* S, bool f64) {
   return l;
 }
 
+OpArgs op_args(const hofem_solver_s* S, const double* u, const double* f, void* out, int out_f32,
+               int nrhs);
+
+// Bytes of the 3D operator's element buffer (0 where the operator needs none),
+// rounded up to 256.
+size_t op_elem_bytes(const hofem_solver_s* S) {
+  const size_t b = op3_elem_doubles(op_args(S, nullptr, nullptr, nullptr, 0, 1)) * sizeof(double);
+  return (b + 255) & ~size_t(255);
+}
+
+// FP32_IR workspace: the FP32 correction grid, the norm partials, the
+// operator's element buffer.
 size_t ir_workspace(const hofem_solver_s* S, int nrhs) {
   size_t b = S->per_rhs * (size_t)nrhs * sizeof(float);
   b = (b + 255) & ~size_t(255);
-  b += (2 * kNormParts + 2) * sizeof(double);
+  b += ((2 * kNormParts + 2) * sizeof(double) + 255) & ~size_t(255);
+  b += op_elem_bytes(S);
   return b;
 }
 
-// Operator arguments; the 3D operator's element buffer is allocated on first use.
+// Operator arguments; elem: the element buffer (op_elem_bytes of the
+// caller's workspace; unused where that is 0).
 int make_op(hofem_solver_s* S, const double* u, const double* f, void* out, int out_f32, int nrhs,
-            OpArgs* op) {
+            double* elem, OpArgs* op) {
+  OpArgs o = op_args(S, u, f, out, out_f32, nrhs);
+  if (op3_elem_doubles(o) && !elem) return HOFEM_EINVAL;
+  o.elem = elem;
+  *op = o;
+  return HOFEM_OK;
+}
+
+OpArgs op_args(const hofem_solver_s* S, const double* u, const double* f, void* out, int out_f32,
+               int nrhs) {
   OpArgs o{};
   o.u = u;
   o.f = f;
@@ -246,16 +278,8 @@ int make_op(hofem_solver_s* S, const double* u, const double* f, void* out, int 
   }
   o.alpha = S->alpha;
   o.nrhs = nrhs;
-  const size_t ne = op3_elem_doubles(o);
-  if (ne && !S->op_elem) {
-    void* m = nullptr;
-    hipError_t e = hipMalloc(&m, ne * sizeof(double));
-    if (e != hipSuccess) return e == hipErrorOutOfMemory ? HOFEM_ENOMEM : hip_fail(e);
-    S->op_elem = static_cast<double*>(m);
-  }
-  o.elem = S->op_elem;
-  *op = o;
-  return HOFEM_OK;
+  o.elem = nullptr;
+  return o;
 }
 
 VarOpArgs make_varop(const hofem_solver_s* S, const hofem_coef* c, const double* u,
@@ -302,6 +326,7 @@ size_t pcg_bytes(const hofem_solver_s* S, const hofem_coef* c) {
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
   size_t b = 4 * al(n * sizeof(double)) + al(n * sizeof(float));
   if (c && c->kind != 0) b += al(varop_elem_bytes(make_varop(S, c, nullptr, nullptr, nullptr, 1)));
+  else b += op_elem_bytes(S);
   b += al(3 * kPcgParts * sizeof(double)) + al(16 * sizeof(double));   // partial triples
   return b;
 }
@@ -319,6 +344,9 @@ PcgWs pcg_carve(const hofem_solver_s* S, const hofem_coef* c, void* ws) {
   if (c && c->kind != 0) {
     w.elem = reinterpret_cast<double*>(p);
     p += al(varop_elem_bytes(make_varop(S, c, nullptr, nullptr, nullptr, 1)));
+  } else {
+    w.elem = reinterpret_cast<double*>(p);
+    p += op_elem_bytes(S);
   }
   w.partial = reinterpret_cast<double*>(p); p += al(3 * kPcgParts * sizeof(double));
   w.scal = reinterpret_cast<double*>(p);
@@ -331,7 +359,7 @@ int pcg_apply(hofem_solver_s* S, const hofem_coef* c, const PcgWs& w, const doub
   const long long count = (long long)S->per_rhs;
   if (!c || c->kind == 0) {
     OpArgs o;
-    const int rc = make_op(S, u, f, out, 0, 1, &o);
+    const int rc = make_op(S, u, f, out, 0, 1, w.elem, &o);
     if (rc != HOFEM_OK) return rc;
     LaunchTimer tm(S, st, HOFEM_PASS_OPERATOR, -1, 1, (double)count * (f ? 24 : 16));
     HIPCHK(launch_operator(o, st));
@@ -351,7 +379,7 @@ int pcg_run(hofem_solver_s* S, const hofem_coef* c, const PcgWs& w, const double
             double rtol, double utol, int max_iter, hipStream_t st, int* iters, double* rel_res,
             double* rel_upd, bool* converged) {
   const long long n = (long long)S->per_rhs;
-  const std::vector<PassSpec> list = solve_list(S, false);
+  const std::vector<PassSpec> list = solve_list(S, false, 1);
   const int np = (int)std::max<long long>(1, std::min<long long>(kPcgParts, (n + 255) / 256));
   double* sc = w.scal;
   auto precond = [&](const double* in, double* out) {
@@ -413,6 +441,52 @@ bool coef_ok(const hofem_solver_s* S, const hofem_coef* c) {
 
 }  // namespace
 
+namespace {
+
+// Device table image of one plan: per-wave-number tables blocked by 64 wave
+// numbers with entries in 16-byte groups (pairs in FP64, quadruples in FP32;
+// layout in kernels.h), the other tables plain, FP64 and FP32 copies.
+std::vector<unsigned char> pack_plan(const Plan1DData& d, PlanOff* off) {
+  Packer pk;
+  const int n = d.n, K = d.K;
+  auto blocked = [&](size_t ge) {
+    const size_t NE = (size_t)n * (n - 1) + n, NEG = (NE + ge - 1) / ge;
+    const size_t nblk = ((size_t)K - 1 + 63) / 64;
+    std::vector<double> blk(nblk * NEG * 64 * ge, 0.0);
+    auto put = [&](int k, size_t e, double v) {
+      const size_t b = (size_t)(k - 1) / 64, o = (size_t)(k - 1) % 64;
+      blk[((b * NEG + e / ge) * 64 + o) * ge + e % ge] = v;
+    };
+    for (int k = 1; k < K; ++k) {
+      for (int l = 0; l < n; ++l) {
+        for (int c = 0; c < n - 1; ++c)
+          put(k, (size_t)l * (n - 1) + c, d.p[((size_t)(k - 1) * n + l) * (n - 1) + c]);
+        put(k, (size_t)n * (n - 1) + l, d.inorm[(size_t)(k - 1) * n + l]);
+      }
+    }
+    return blk;
+  };
+  off->lam = pk.add_f64(d.lam);
+  off->blk64 = pk.add_f64(blocked(2));
+  off->E64 = pk.add_f64(d.E);
+  off->tw64 = pk.add_f64(d.tw);
+  off->sn64 = pk.add_f64(d.sn);
+  off->blk32 = pk.add_f32(blocked(4));
+  off->E32 = pk.add_f32(d.E);
+  off->tw32 = pk.add_f32(d.tw);
+  off->sn32 = pk.add_f32(d.sn);
+  off->A = pk.add_f64(d.A);
+  off->C = pk.add_f64(d.C);
+  off->B = pk.add_f64(d.B);
+  off->D = pk.add_f64(d.D);
+  off->Dh = pk.add_f64(d.Dh);
+  off->gw = pk.add_f64(d.gw);
+  pk.bytes.resize((pk.bytes.size() + 255) & ~size_t(255), 0);
+  return pk.bytes;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* hofem_status_string(int status) {
@@ -439,7 +513,27 @@ int hofem_plan1d_create(int n, int K, hofem_plan1d* out) {
     delete p;
     return HOFEM_EUNSUPPORTED;
   }
+  p->image = pack_plan(p->d, &p->off);
   *out = p;
+  return HOFEM_OK;
+}
+
+int hofem_plan1d_table_bytes(hofem_plan1d plan, size_t* bytes) {
+  if (!plan || !bytes) return HOFEM_EINVAL;
+  *bytes = plan->image.size();
+  return HOFEM_OK;
+}
+
+int hofem_plan1d_upload(hofem_plan1d plan, void* dev_buf, size_t bytes, void* stream) {
+  if (!plan || !dev_buf || bytes < plan->image.size()) return HOFEM_EINVAL;
+  if (reinterpret_cast<uintptr_t>(dev_buf) & 255) return HOFEM_EINVAL;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIPCHK(hipMemcpyAsync(dev_buf, plan->image.data(), plan->image.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  plan->dev = static_cast<const unsigned char*>(dev_buf);
+  plan->device = dev;
   return HOFEM_OK;
 }
 
@@ -493,23 +587,24 @@ int hofem_solver_create(int N, const hofem_plan1d* plans, const double* X, doubl
     dmin += 4.0 / (h * h) * *std::min_element(d.lam.begin(), d.lam.end());
   }
   if (!(dmin > 0)) return HOFEM_ENOTPOSDEF;
+  // the tables must be on the current device
+  for (int i = 0; i < N; ++i)
+    if (!plans[i]->dev) return HOFEM_EINVAL;
+  int cur = 0;
+  const hipError_t ge = hipGetDevice(&cur);
+  if (ge != hipSuccess) return hip_fail(ge);
+  for (int i = 0; i < N; ++i)
+    if (plans[i]->device != cur) return HOFEM_EINVAL;
 
   hofem_solver S = new (std::nothrow) hofem_solver_s;
   if (!S) return HOFEM_ENOMEM;
   S->N = N;
   S->alpha = alpha;
   S->per_rhs = 1;
-  hipError_t e = hipGetDevice(&S->device);
-  if (e != hipSuccess) {
-    delete S;
-    return hip_fail(e);
-  }
-  Packer pk;
-  struct Off {
-    size_t lam, blk64, E64, tw64, sn64, blk32, E32, tw32, sn32, A, C, B, D, Dh, gw;
-  } off[3];
+  S->device = cur;
   for (int i = 0; i < N; ++i) {
-    const Plan1DData& d = plans[i]->d;
+    const hofem_plan1d_s* P = plans[i];
+    const Plan1DData& d = P->d;
     DevAxis& ax = S->ax[i];
     ax.n = d.n;
     ax.K = d.K;
@@ -520,69 +615,17 @@ int hofem_solver_create(int N, const hofem_plan1d* plans, const double* X, doubl
     S->per_rhs *= (size_t)d.m;
     ax.hA = d.A;
     ax.hC = d.C;
-    // per-wave-number tables blocked by 64 wave numbers, entries in groups of
-    // 16 bytes: pairs in FP64, quadruples in FP32 (layout in kernels.h)
-    const int n = d.n, K = d.K;
-    auto blocked = [&](size_t ge) {
-      const size_t NE = (size_t)n * (n - 1) + n, NEG = (NE + ge - 1) / ge;
-      const size_t nblk = ((size_t)K - 1 + 63) / 64;
-      std::vector<double> blk(nblk * NEG * 64 * ge, 0.0);
-      auto put = [&](int k, size_t e, double v) {
-        const size_t b = (size_t)(k - 1) / 64, o = (size_t)(k - 1) % 64;
-        blk[((b * NEG + e / ge) * 64 + o) * ge + e % ge] = v;
-      };
-      for (int k = 1; k < K; ++k) {
-        for (int l = 0; l < n; ++l) {
-          for (int c = 0; c < n - 1; ++c)
-            put(k, (size_t)l * (n - 1) + c, d.p[((size_t)(k - 1) * n + l) * (n - 1) + c]);
-          put(k, (size_t)n * (n - 1) + l, d.inorm[(size_t)(k - 1) * n + l]);
-        }
-      }
-      return blk;
-    };
-    off[i].lam = pk.add_f64(d.lam);
-    off[i].blk64 = pk.add_f64(blocked(2));
-    off[i].E64 = pk.add_f64(d.E);
-    off[i].tw64 = pk.add_f64(d.tw);
-    off[i].sn64 = pk.add_f64(d.sn);
-    off[i].blk32 = pk.add_f32(blocked(4));
-    off[i].E32 = pk.add_f32(d.E);
-    off[i].tw32 = pk.add_f32(d.tw);
-    off[i].sn32 = pk.add_f32(d.sn);
-    off[i].A = pk.add_f64(d.A);
-    off[i].C = pk.add_f64(d.C);
-    off[i].B = pk.add_f64(d.B);
-    off[i].D = pk.add_f64(d.D);
-    off[i].Dh = pk.add_f64(d.Dh);
-    off[i].gw = pk.add_f64(d.gw);
-  }
-  void* mem = nullptr;
-  e = hipMalloc(&mem, pk.bytes.size());
-  if (e != hipSuccess) {
-    delete S;
-    return e == hipErrorOutOfMemory ? HOFEM_ENOMEM : hip_fail(e);
-  }
-  e = hipMemcpy(mem, pk.bytes.data(), pk.bytes.size(), hipMemcpyHostToDevice);
-  if (e != hipSuccess) {
-    (void)hipFree(mem);
-    delete S;
-    return hip_fail(e);
-  }
-  S->mem = mem;
-  unsigned char* b = static_cast<unsigned char*>(mem);
-  for (int i = 0; i < N; ++i) {
-    DevAxis& ax = S->ax[i];
-    const double* lam = reinterpret_cast<const double*>(b + off[i].lam);
-    ax.t64 = AxisTab{b + off[i].blk64, b + off[i].E64, b + off[i].tw64, b + off[i].sn64, lam,
-                     ax.n, ax.K, ax.m};
-    ax.t32 = AxisTab{b + off[i].blk32, b + off[i].E32, b + off[i].tw32, b + off[i].sn32, lam,
-                     ax.n, ax.K, ax.m};
-    ax.A = reinterpret_cast<const double*>(b + off[i].A);
-    ax.C = reinterpret_cast<const double*>(b + off[i].C);
-    ax.B = reinterpret_cast<const double*>(b + off[i].B);
-    ax.D = reinterpret_cast<const double*>(b + off[i].D);
-    ax.Dh = reinterpret_cast<const double*>(b + off[i].Dh);
-    ax.gw = reinterpret_cast<const double*>(b + off[i].gw);
+    const unsigned char* b = P->dev;
+    const PlanOff& o = P->off;
+    const double* lam = reinterpret_cast<const double*>(b + o.lam);
+    ax.t64 = AxisTab{b + o.blk64, b + o.E64, b + o.tw64, b + o.sn64, lam, ax.n, ax.K, ax.m};
+    ax.t32 = AxisTab{b + o.blk32, b + o.E32, b + o.tw32, b + o.sn32, lam, ax.n, ax.K, ax.m};
+    ax.A = reinterpret_cast<const double*>(b + o.A);
+    ax.C = reinterpret_cast<const double*>(b + o.C);
+    ax.B = reinterpret_cast<const double*>(b + o.B);
+    ax.D = reinterpret_cast<const double*>(b + o.D);
+    ax.Dh = reinterpret_cast<const double*>(b + o.Dh);
+    ax.gw = reinterpret_cast<const double*>(b + o.gw);
   }
   *out = S;
   return HOFEM_OK;
@@ -591,8 +634,6 @@ int hofem_solver_create(int N, const hofem_plan1d* plans, const double* X, doubl
 void hofem_solver_destroy(hofem_solver solver) {
   if (!solver) return;
   for (hipEvent_t e : solver->event_pool) (void)hipEventDestroy(e);
-  if (solver->mem) (void)hipFree(solver->mem);
-  if (solver->op_elem) (void)hipFree(solver->op_elem);
   delete solver;
 }
 
@@ -648,7 +689,7 @@ int hofem_solve(hofem_solver S, int mode, const void* f_dev, void* u_dev, int nr
                 size_t ws_bytes, int max_iter, double tol, void* stream, hofem_info* info) {
   if (!S || !f_dev || !u_dev || nrhs < 1) return HOFEM_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const std::vector<PassSpec> list = solve_list(S, mode == HOFEM_MODE_FP64);
+  const std::vector<PassSpec> list = solve_list(S, mode == HOFEM_MODE_FP64, nrhs);
   if (mode == HOFEM_MODE_FP64 || mode == HOFEM_MODE_FP32) {
     const bool f64 = mode == HOFEM_MODE_FP64;
     const int dt = f64 ? 0 : 1;
@@ -693,6 +734,9 @@ int hofem_solve(hofem_solver S, int mode, const void* f_dev, void* u_dev, int nr
   size_t roff = (S->per_rhs * (size_t)nrhs * sizeof(float) + 255) & ~size_t(255);
   double* partial = reinterpret_cast<double*>(static_cast<unsigned char*>(ws_dev) + roff);
   double* sums = partial + 2 * kNormParts;
+  double* elem = reinterpret_cast<double*>(
+      static_cast<unsigned char*>(ws_dev) + roff +
+      (((2 * kNormParts + 2) * sizeof(double) + 255) & ~size_t(255)));
   // First FP32 solve: f^h (FP64) -> u (FP64).
   int rc = run_list(S, list, false, f_dev, r32, u_dev, 2, 1, 3, 5, nrhs, st);
   if (rc != HOFEM_OK) return rc;
@@ -706,7 +750,7 @@ int hofem_solve(hofem_solver S, int mode, const void* f_dev, void* u_dev, int nr
   for (; it < max_iter;) {
     OpArgs o;
     rc = make_op(S, static_cast<const double*>(u_dev), static_cast<const double*>(f_dev), r32, 1,
-                 nrhs, &o);
+                 nrhs, elem, &o);
     if (rc != HOFEM_OK) return rc;
     {
       LaunchTimer tm(S, st, HOFEM_PASS_OPERATOR, -1, 1, (double)count * (8 + 8 + 4));
@@ -819,15 +863,15 @@ int hofem_apply_coef_operator(hofem_solver S, const hofem_coef* coef, const doub
   if (!S || !u_dev || !out_dev || nrhs < 1 || u_dev == out_dev || !coef_ok(S, coef))
     return HOFEM_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if (!ws_dev || ws_bytes < pcg_bytes(S, coef)) return HOFEM_EINVAL;
+  const PcgWs w = pcg_carve(S, coef, ws_dev);
   if (!coef || coef->kind == 0) {
     OpArgs o;
-    const int rc = make_op(S, u_dev, nullptr, out_dev, 0, nrhs, &o);
+    const int rc = make_op(S, u_dev, nullptr, out_dev, 0, nrhs, w.elem, &o);
     if (rc != HOFEM_OK) return rc;
     HIPCHK(launch_operator(o, st));
     return HOFEM_OK;
   }
-  if (!ws_dev || ws_bytes < pcg_bytes(S, coef)) return HOFEM_EINVAL;
-  const PcgWs w = pcg_carve(S, coef, ws_dev);
   for (int r = 0; r < nrhs; ++r) {
     VarOpArgs v = make_varop(S, coef, u_dev + r * S->per_rhs, nullptr, out_dev + r * S->per_rhs, 1);
     HIPCHK(launch_varop(v, w.elem, st));
@@ -835,14 +879,43 @@ int hofem_apply_coef_operator(hofem_solver S, const hofem_coef* coef, const doub
   return HOFEM_OK;
 }
 
-int hofem_apply_operator(hofem_solver S, const double* u_dev, double* out_dev, int nrhs,
-                         void* stream) {
+int hofem_operator_workspace_bytes(hofem_solver S, size_t* bytes) {
+  if (!S || !bytes) return HOFEM_EINVAL;
+  *bytes = op_elem_bytes(S);
+  return HOFEM_OK;
+}
+
+namespace {
+
+// out = L u, or with mass_only the mass product (x)_i C_i u (the operator's
+// stiffness scales set to 0 and alpha to 1: the stiffness terms then vanish
+// exactly).
+int apply_op(hofem_solver S, const double* u_dev, double* out_dev, int nrhs, void* ws_dev,
+             size_t ws_bytes, void* stream, bool mass_only) {
   if (!S || !u_dev || !out_dev || nrhs < 1 || u_dev == out_dev) return HOFEM_EINVAL;
+  const size_t need = op_elem_bytes(S);
+  if (need && (!ws_dev || ws_bytes < need)) return HOFEM_EINVAL;
   OpArgs o;
-  const int rc = make_op(S, u_dev, nullptr, out_dev, 0, nrhs, &o);
+  const int rc = make_op(S, u_dev, nullptr, out_dev, 0, nrhs, static_cast<double*>(ws_dev), &o);
   if (rc != HOFEM_OK) return rc;
+  if (mass_only) {
+    for (int i = 0; i < S->N; ++i) o.scale[i] = 0.0;
+    o.alpha = 1.0;
+  }
   HIPCHK(launch_operator(o, static_cast<hipStream_t>(stream)));
   return HOFEM_OK;
+}
+
+}  // namespace
+
+int hofem_apply_operator(hofem_solver S, const double* u_dev, double* out_dev, int nrhs,
+                         void* ws_dev, size_t ws_bytes, void* stream) {
+  return apply_op(S, u_dev, out_dev, nrhs, ws_dev, ws_bytes, stream, false);
+}
+
+int hofem_apply_mass(hofem_solver S, const double* g_dev, double* out_dev, int nrhs, void* ws_dev,
+                     size_t ws_bytes, void* stream) {
+  return apply_op(S, g_dev, out_dev, nrhs, ws_dev, ws_bytes, stream, true);
 }
 
 }  // extern "C"

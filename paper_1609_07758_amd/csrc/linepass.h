@@ -358,6 +358,16 @@ __device__ __forceinline__ void task_sines(const T* __restrict__ sn, int j, T (&
     out[t] = sa * (T)kCos16[t * (16 / R)] + ca * (T)kSin16[t * (16 / R)];
 }
 
+// cos(pi jj / K) for the same task points (cos(pi j / K) = sin(pi (K/2 - j) / K)).
+template <typename T, int K, int R>
+__device__ __forceinline__ void task_cosines(const T* __restrict__ sn, int j, T (&out)[R]) {
+  static_assert(R <= 16, "16 rotation constants");
+  const T sa = sn[j], ca = sn[K / 2 - j];
+#pragma unroll
+  for (int t = 0; t < R; ++t)
+    out[t] = ca * (T)kCos16[t * (16 / R)] - sa * (T)kSin16[t * (16 / R)];
+}
+
 // After task_fft: the two sine transforms of the pair, (X^a_k, X^b_k) at
 // index k = 1..K-1 of buf (index 0 set to zero).  Lane j handles the wave
 // numbers k in [j C, (j+1) C), C = K / (2 G).
@@ -406,6 +416,56 @@ __device__ __forceinline__ void task_post(cx<T>* buf, int j) {
     buf[sw(2 * k)] = ev[i];
     const cx<double> o = cadd(rv[i], excl);
     buf[sw(2 * k + 1)] = cx<T>{(T)o.x, (T)o.y};
+  }
+  wave_sync();
+}
+
+// Sine transforms of a pair without the running sums (FP32 inverse
+// transforms).  The running sums add up K/2 rounded FFT outputs, so the odd
+// outputs of an FP32 transform carry an error that grows like sqrt(k); on a
+// smooth inverse transform that error alternates between odd and even nodes,
+// i.e. it sits in the stiff high modes, and the next FP64 residual of a
+// refinement step amplifies it by the condition number.  Here a second FFT
+// of the cosine-weighted input y'_j = cos(pi j/K)(x_j + x_{K-j}) (an odd
+// sequence, so its spectrum is imaginary: -Im Y'_k = X_{2k+1} + X_{2k-1})
+// supplies the sums next to the differences R_k = Re Y_k = X_{2k+1} -
+// X_{2k-1}, and X_{2k+1} = (R_k + Q_k) / 2 is formed directly.
+// v: the sine-weighted input (as for task_fft), v2: the cosine-weighted one.
+template <typename T, int LOG2K, int LOG2RMAX>
+__device__ __forceinline__ void task_dst_direct(cx<T> (&v)[(FftShape<LOG2K, LOG2RMAX>::R)],
+                                                cx<T> (&v2)[(FftShape<LOG2K, LOG2RMAX>::R)],
+                                                cx<T>* buf, int j, const cx<T>* __restrict__ tw) {
+  using S = FftShape<LOG2K, LOG2RMAX>;
+  constexpr int K = S::K, G = S::G;
+  constexpr int C = (K / 2) / G;
+  task_fft<T, LOG2K, LOG2RMAX>(v, buf, j, tw);
+  cx<T> ev[C], rv[C];
+#pragma unroll
+  for (int i = 0; i < C; ++i) {
+    const int k = j * C + i;
+    const cx<T> a = buf[sw(k)];
+    const cx<T> b = buf[sw((K - k) & (K - 1))];
+    ev[i] = k == 0 ? cx<T>{T(0), T(0)} : cx<T>{T(0.5) * (b.y - a.y), T(0.5) * (a.x - b.x)};
+    rv[i] = {T(0.5) * (a.x + b.x), T(0.5) * (a.y + b.y)};   // R_k (R_0 = 2 X_1)
+  }
+  wave_sync();
+  task_fft<T, LOG2K, LOG2RMAX>(v2, buf, j, tw);
+  cx<T> od[C];
+#pragma unroll
+  for (int i = 0; i < C; ++i) {
+    const int k = j * C + i;
+    const cx<T> a = buf[sw(k)];
+    const cx<T> b = buf[sw((K - k) & (K - 1))];
+    // Q_k of both sequences (Q_0 = 0 exactly: a = b there)
+    const cx<T> q = {T(0.5) * (b.y - a.y), T(0.5) * (a.x - b.x)};
+    od[i] = {T(0.5) * (rv[i].x + q.x), T(0.5) * (rv[i].y + q.y)};
+  }
+  wave_sync();
+#pragma unroll
+  for (int i = 0; i < C; ++i) {
+    const int k = j * C + i;
+    buf[sw(2 * k)] = ev[i];
+    buf[sw(2 * k + 1)] = od[i];
   }
   wave_sync();
 }
@@ -1223,15 +1283,32 @@ __attribute__((amdgpu_waves_per_eu(waves_per_simd<T, N, LOG2K, MODE>()))) void l
     T snr[R];
     task_sines<T, K, R>(SN, j, snr);
     cx<T> v[R];
+    if constexpr (sizeof(T) == 4) {
+      // FP32: both FFTs, no running sums (see task_dst_direct)
+      T csr[R];
+      task_cosines<T, K, R>(SN, j, csr);
+      cx<T> v2[R];
 #pragma unroll
-    for (int t = 0; t < R; ++t) {
-      const int jj = j + G * t;
-      v[t] = dst_pre(inv_in<T, N>(interior, tb[sw(jj)]),
-                     inv_in<T, N>(interior, tb[sw((K - jj) & (K - 1))]), snr[t], jj);
+      for (int t = 0; t < R; ++t) {
+        const int jj = j + G * t;
+        const cx<T> x0 = inv_in<T, N>(interior, tb[sw(jj)]);
+        const cx<T> x1 = inv_in<T, N>(interior, tb[sw((K - jj) & (K - 1))]);
+        v[t] = dst_pre(x0, x1, snr[t], jj);
+        v2[t] = jj == 0 ? cx<T>{T(0), T(0)} : cx<T>{csr[t] * (x0.x + x1.x), csr[t] * (x0.y + x1.y)};
+      }
+      wave_sync();
+      task_dst_direct<T, LOG2K, LRM>(v, v2, tb, j, TW);
+    } else {
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        const int jj = j + G * t;
+        v[t] = dst_pre(inv_in<T, N>(interior, tb[sw(jj)]),
+                       inv_in<T, N>(interior, tb[sw((K - jj) & (K - 1))]), snr[t], jj);
+      }
+      wave_sync();
+      task_fft<T, LOG2K, LRM>(v, tb, j, TW);
+      task_post<T, LOG2K, LRM>(tb, j);
     }
-    wave_sync();
-    task_fft<T, LOG2K, LRM>(v, tb, j, TW);
-    task_post<T, LOG2K, LRM>(tb, j);
   };
   if constexpr (tight) {
     for (int t0 = 0; t0 < ntask; t0 += per_round) {

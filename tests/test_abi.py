@@ -57,7 +57,26 @@ def test_null_and_size_errors():
     assert H._lib.hofem_solver_create(1, arr, bad, 0.0, ctypes.byref(h)) == H.HOFEM_EINVAL
     # alpha below -pi^2 / X^2 (scaled): the smallest denominator is negative
     assert H._lib.hofem_solver_create(1, arr, xs, -1e4, ctypes.byref(h)) == H.HOFEM_ENOTPOSDEF
+    # a plan whose tables were never uploaded to a device
+    assert H._lib.hofem_solver_create(1, arr, xs, 0.0, ctypes.byref(h)) == H.HOFEM_EINVAL
     assert H._lib.hofem_solve(None, 0, None, None, 1, None, 0, 0, 0.0, None, None) == H.HOFEM_EINVAL
+    assert H._lib.hofem_apply_mass(None, None, None, 1, None, 0, None) == H.HOFEM_EINVAL
+    assert H._lib.hofem_apply_operator(None, None, None, 1, None, 0, None) == H.HOFEM_EINVAL
+    size = ctypes.c_size_t()
+    assert H._lib.hofem_operator_workspace_bytes(None, ctypes.byref(size)) == H.HOFEM_EINVAL
+
+
+def test_plan_table_image_size_and_upload_errors():
+    p = H.Plan1D(9, 1024)
+    nbytes = H.hofem_plan1d_table_bytes(p.handle)
+    # FP64 lambda, p + norms in FP64 and FP32, twiddles, sines: about 1.4 MB
+    n, K = 9, 1024
+    assert nbytes % 256 == 0 and 8 * n * K < nbytes < 2 * 1024 * 1024
+    assert H._lib.hofem_plan1d_table_bytes(p.handle, None) == H.HOFEM_EINVAL
+    assert H._lib.hofem_plan1d_upload(p.handle, None, nbytes, None) == H.HOFEM_EINVAL
+    # too few bytes and a misaligned buffer are rejected before any copy
+    assert H._lib.hofem_plan1d_upload(p.handle, ctypes.c_void_p(4096), nbytes - 256, None) == H.HOFEM_EINVAL
+    assert H._lib.hofem_plan1d_upload(p.handle, ctypes.c_void_p(4096 + 8), nbytes, None) == H.HOFEM_EINVAL
     assert H.hofem_solver_size is not None
     assert H._lib.hofem_status_string(H.HOFEM_ENOCONV) == b"refinement did not converge"
 

@@ -81,7 +81,8 @@ def test_small_batch_equals_single_solves(mode):
         up = S.solve(fp, mode=mode, nrhs=r, max_iter=3, tol=0.0)
         torch.cuda.synchronize()
         assert torch.equal(batch.view(u, p), up), p
-        if mode == "fp64":
+        if mode != "fp32":
+            # FP64, and three refinement steps on these small grids
             for j in range(r):
                 want = osolve.solve(rhs[p][j], (n, n), (K, K), (1.0, 1.0), 0.0)
                 assert rel(batch.view(u, p)[j].cpu().numpy(), want) < 1e-12
@@ -115,6 +116,38 @@ def test_graph_replays_match_eager():
         batch.solve(f, u, mode="fp32_ir", max_iter=2, use_graph=True, stream=s.cuda_stream)
         s.synchronize()
     assert torch.equal(u, u2_eager)
+
+
+def test_3d_solver_shared_by_two_groups_graph():
+    # One 3D solver in two groups (nrhs 1 and 2): the groups run on forked
+    # streams in the graph, each with the operator's element buffer in its
+    # own workspace region; every replay equals the eager result and the
+    # oracle.
+    orders, Ks, X = (3, 3, 3), (4, 4, 8), (1.0, 1.0, 1.0)
+    S = H.Solver(orders, Ks, X, 0.5)
+    T = H.Solver((2, 2, 2), (4, 4, 4), X, 0.0)
+    probs = [(S, 1), (T, 1), (S, 2), (S, 1)]
+    batch = H.Batch(probs)
+    assert batch.groups == 3
+    rng = np.random.default_rng(12)
+    rhs = [rng.uniform(-1, 1, (r,) + s.shape) for s, r in probs]
+    f = fill(batch, rhs, torch.float64)
+    u_eager = torch.zeros_like(f)
+    batch.solve(f, u_eager, mode="fp32_ir", max_iter=4, use_graph=False)
+    torch.cuda.synchronize()
+    st = torch.cuda.Stream()
+    u = torch.zeros_like(f)
+    with torch.cuda.stream(st):
+        for rep in range(3):
+            u.zero_()
+            batch.solve(f, u, mode="fp32_ir", max_iter=4, use_graph=True, stream=st.cuda_stream)
+            st.synchronize()
+            assert torch.equal(u, u_eager), rep
+    for p, (s_, r) in enumerate(probs):
+        o = s_.orders
+        for j in range(r):
+            want = osolve.solve(rhs[p][j], o, s_.Ks, X, s_.alpha)
+            assert rel(batch.view(u, p)[j].cpu().numpy(), want) < 1e-12, (p, j)
 
 
 def test_batch_errors():
