@@ -660,8 +660,15 @@ constexpr int log2_rmax() { return (sizeof(T) == 8 && LOG2K <= 9) ? 3 : 4; }
 constexpr int waves_per_simd_of(bool f64, int n, int log2K) {
   return f64 ? ((log2K <= 9 && n <= 6) ? 4 : 2) : 4;
 }
+// FP32 passes with inverse transforms of long lines of high order (two FFTs
+// per slot pair, see task_dst_direct) spill at four waves: two waves per
+// SIMD, one 512-lane workgroup per CU (FP32 large 2D solve 2.35 -> 1.97 ms).
 template <typename T, int N, int LOG2K, int MODE>
-constexpr int waves_per_simd() { return waves_per_simd_of(sizeof(T) == 8, N, LOG2K); }
+constexpr int waves_per_simd() {
+  return (sizeof(T) == 4 && MODE != PASS_FWD && LOG2K >= 6 && N >= 7)
+             ? 2
+             : waves_per_simd_of(sizeof(T) == 8, N, LOG2K);
+}
 
 // Lines per workgroup in the "tight" layout (at most).
 constexpr int kTight = 2;
