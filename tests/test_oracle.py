@@ -324,8 +324,8 @@ def _table1():
     return rows
 
 
-@pytest.mark.parametrize("kappa,n", [(3, n) for n in range(2, 10)] + [(4, n) for n in range(2, 10)]
-                         + [(5, n) for n in range(2, 7)])
+@pytest.mark.parametrize("kappa,n", [(3, n) for n in range(1, 10)] + [(4, n) for n in range(1, 10)]
+                         + [(5, n) for n in range(1, 7)] + [(6, 1), (7, 1)])
 def test_table1(kappa, n):
     paper = _table1()[kappa][n - 1]
     K = 2 ** kappa
