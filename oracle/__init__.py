@@ -27,8 +27,14 @@ What it computes, step by step (each module cites the passage it follows):
                 (x)V^T f^h by dense products along every axis (eq. (decomp v 2)).
 * ``load``      the load vector f^h of a given f by (n+1)-point Gauss
                 quadrature, and grid coordinates (Section 2, paragraph 5).
+* ``varcoef``   the variable-coefficient operator -div(a grad u) + alpha u
+                by (n+1)-point Gauss quadrature: assembled, matrix-free, and
+                a sparse direct solve.
 * ``pcg``       a plain preconditioned CG for the variable-coefficient
-                operator, used to check the GPU PCG.
+                operator (exact constant-coefficient solve as the
+                preconditioner); its iteration counts stand beside the GPU's.
+* ``timestep``  implicit time stepping (heat: backward Euler; wave: the
+                implicit three-level scheme), one solve per step.
 
 Parity status: every function is pinned by a test in ``tests/`` against
 values the paper prints, closed forms, invariants or brute force.

@@ -212,3 +212,23 @@ def test_load_of_polynomial_is_exact():
     got = varcoef.load(fv, ns, Ks)
     ref = load.load_separable([(1.0, [lambda x: x ** 2, lambda y: y])], ns, Ks, Xs)
     assert np.max(np.abs(got - ref)) <= 1e-14 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("N,n,K", [(2, 3, 4), (3, 2, 4)])
+def test_oracle_pcg_matches_sparse_direct(N, n, K):
+    # CG preconditioned by the constant-coefficient solve converges to the
+    # sparse direct solution; with 0.5 <= a <= 1.5 the preconditioned
+    # operator has condition number <= 3, so the CG bound gives at most
+    # about 22 iterations to 1e-10 (energy norm)
+    from oracle import pcg
+    ns, Ks, Xs = [n] * N, [K] * N, [1.0] * N
+    rng = np.random.default_rng(3)
+    a = rng.uniform(0.5, 1.5, (K ** N, (n + 1) ** N))
+    f = rng.uniform(-1, 1, tuple(n * K - 1 for _ in range(N)))
+    u, it, res = pcg.pcg(f, ns, Ks, Xs, 0.0, a, rtol=1e-10)
+    want = varcoef.solve(f, ns, Ks, Xs, 0.0, a)
+    assert res <= 1e-10 and 1 <= it <= 22
+    assert np.linalg.norm(u - want) / np.linalg.norm(want) < 1e-9
+    # a = 1: the preconditioner is exact, the start is the solution
+    u1, it1, _ = pcg.pcg(f, ns, Ks, Xs, 0.0, np.ones_like(a), rtol=1e-10)
+    assert it1 == 0
