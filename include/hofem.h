@@ -57,7 +57,8 @@ enum hofem_status {
   HOFEM_ENOTPOSDEF = -3,    /* alpha makes the operator indefinite */
   HOFEM_ENOCONV = -4,       /* refinement did not reach the tolerance */
   HOFEM_EHIP = -5,          /* HIP runtime failure */
-  HOFEM_ENOMEM = -6         /* host or device allocation failed */
+  HOFEM_ENOMEM = -6,        /* host or device allocation failed */
+  HOFEM_ETOOBIG = -7        /* the problem exceeds hofem_solve_ir_noalloc's fixed scratch */
 };
 
 /* Arithmetic of a solve. */
@@ -245,6 +246,23 @@ int hofem_apply_operator(hofem_solver solver, const double* u_dev, double* out_d
  * workspace as hofem_apply_operator; g_dev != out_dev. */
 int hofem_apply_mass(hofem_solver solver, const double* g_dev, double* out_dev, int nrhs,
                      void* ws_dev, size_t ws_bytes, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): hofem_solve
+ * in mode HOFEM_MODE_FP32_IR (f_dev, u_dev double, f_dev != u_dev; max_iter,
+ * tol, info as there) with its workspace taken from a scratch buffer of
+ * 64 MiB that the library holds in device memory, one per device, from the
+ * library's load until the process ends.  The problem must fit it:
+ * hofem_solver_workspace_bytes(solver, HOFEM_MODE_FP32_IR, nrhs) <= 64 MiB
+ * (the FP32 residual grid of nrhs right-hand sides, 16 KB of norm partials
+ * and, in 3D with equal orders, the operator's element outputs; about 16
+ * million unknowns in all), else HOFEM_ETOOBIG before any work.  Allocates
+ * nothing and records no timing events.  Every call on a device shares that
+ * device's scratch: calls that overlap on one device (other streams, other
+ * threads) race and must be serialised by the caller.  The scratch keeps the
+ * last call's contents; each call writes every scratch byte it reads. */
+int hofem_solve_ir_noalloc(hofem_solver solver, const double* f_dev, double* u_dev, int nrhs,
+                           int max_iter, double tol, void* stream, hofem_info* info);
 
 /* ---- batched form -------------------------------------------------------- */
 

@@ -30,6 +30,7 @@ HOFEM_ENOTPOSDEF = -3
 HOFEM_ENOCONV = -4
 HOFEM_EHIP = -5
 HOFEM_ENOMEM = -6
+HOFEM_ETOOBIG = -7
 
 MODES = {"fp64": 0, "fp32": 1, "fp32_ir": 2, "fp32_pcg": 3}
 TABLES = {"lam": 0, "p": 1, "inorm": 2, "E": 3, "A": 4, "C": 5, "gx": 6, "gw": 7, "B": 8, "D": 9}
@@ -74,6 +75,8 @@ SIGNATURES = {
     "hofem_solver_workspace_bytes": (_c_int, [_vp, _c_int, _c_int, ctypes.POINTER(_c_size)]),
     "hofem_solve": (_c_int, [_vp, _c_int, _vp, _vp, _c_int, _vp, _c_size, _c_int, _c_double, _vp,
                              ctypes.POINTER(hofem_info)]),
+    "hofem_solve_ir_noalloc": (_c_int, [_vp, _vp, _vp, _c_int, _c_int, _c_double, _vp,
+                                        ctypes.POINTER(hofem_info)]),
     "hofem_forward": (_c_int, [_vp, _c_int, _vp, _vp, _c_int, _vp]),
     "hofem_inverse": (_c_int, [_vp, _c_int, _vp, _vp, _c_int, _vp]),
     "hofem_operator_workspace_bytes": (_c_int, [_vp, ctypes.POINTER(_c_size)]),
@@ -213,6 +216,16 @@ def hofem_solve(solver, mode, f, u, nrhs=1, ws=None, max_iter=0, tol=0.0, stream
     if st == HOFEM_ENOCONV and not raise_noconv:
         return info, st
     _check(st, "hofem_solve")
+    return info, st
+
+
+def hofem_solve_ir_noalloc(solver, f, u, nrhs=1, max_iter=4, tol=0.0, stream=None,
+                           want_info=False):
+    """FP32 solve with FP64 refinement whose workspace is the library's own scratch."""
+    info = hofem_info() if want_info else None
+    st = _lib.hofem_solve_ir_noalloc(solver, _ptr(f), _ptr(u), int(nrhs), int(max_iter),
+                                     float(tol), _stream(stream),
+                                     ctypes.byref(info) if info is not None else None)
     return info, st
 
 

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -38,6 +39,8 @@ struct hofem_plan1d_s {
 namespace {
 
 thread_local int g_last_hip = 0;
+// Set while an entry point that must not allocate runs: no timing events.
+thread_local bool g_no_events = false;
 
 int hip_fail(hipError_t e) {
   g_last_hip = (int)e;
@@ -120,7 +123,7 @@ struct LaunchTimer {
   bool on = false;
   LaunchTimer(hofem_solver_s* s, hipStream_t stream, int kind, int axis, int fp64, double bytes)
       : S(s), st(stream) {
-    if (!S->timing || S->records.size() >= kMaxRecords) return;
+    if (g_no_events || !S->timing || S->records.size() >= kMaxRecords) return;
     const size_t need = 2 * (S->records.size() + 1);
     while (S->event_pool.size() < need) {
       hipEvent_t e;
@@ -498,6 +501,7 @@ const char* hofem_status_string(int status) {
     case HOFEM_ENOCONV: return "refinement did not converge";
     case HOFEM_EHIP: return "HIP runtime error";
     case HOFEM_ENOMEM: return "out of memory";
+    case HOFEM_ETOOBIG: return "problem exceeds the library's fixed scratch buffer";
     default: return "unknown status";
   }
 }
@@ -916,6 +920,61 @@ int hofem_apply_operator(hofem_solver S, const double* u_dev, double* out_dev, i
 int hofem_apply_mass(hofem_solver S, const double* g_dev, double* out_dev, int nrhs, void* ws_dev,
                      size_t ws_bytes, void* stream) {
   return apply_op(S, g_dev, out_dev, nrhs, ws_dev, ws_bytes, stream, true);
+}
+
+}  // extern "C"
+
+// ---- FP32_IR with the library's own scratch (no allocation) ---------------
+namespace {
+
+// Scratch of hofem_solve_ir_noalloc: one copy per device, held until the
+// process ends.  Host code never uses the symbol itself (a host stand-in),
+// only its device address from hipGetSymbolAddress, kept per device.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of this device's scratch (looked up once per device, with
+// that device current).
+int scratch_of_device(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return HOFEM_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol);
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return HOFEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hofem_solve_ir_noalloc(hofem_solver S, const double* f_dev, double* u_dev, int nrhs,
+                           int max_iter, double tol, void* stream, hofem_info* info) {
+  if (!S || !f_dev || !u_dev || nrhs < 1 || f_dev == u_dev) return HOFEM_EINVAL;
+  if (max_iter < 0 || !std::isfinite(tol)) return HOFEM_EINVAL;
+  if (ir_workspace(S, nrhs) > kScratchBytes) return HOFEM_ETOOBIG;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != S->device) return HOFEM_EINVAL;
+  void* ws = nullptr;
+  const int rc = scratch_of_device(dev, &ws);
+  if (rc != HOFEM_OK) return rc;
+  // every byte the refinement reads from the scratch is written first in
+  // the same call (the residual grid by the operator, the norm partials by
+  // the norm kernels, the 3D element outputs by the operator), so nothing
+  // needs clearing
+  g_no_events = true;
+  const int st = hofem_solve(S, HOFEM_MODE_FP32_IR, f_dev, u_dev, nrhs, ws, kScratchBytes,
+                             max_iter, tol, stream, info);
+  g_no_events = false;
+  return st;
 }
 
 }  // extern "C"
