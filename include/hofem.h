@@ -247,6 +247,62 @@ int hofem_apply_operator(hofem_solver solver, const double* u_dev, double* out_d
 int hofem_apply_mass(hofem_solver solver, const double* g_dev, double* out_dev, int nrhs,
                      void* ws_dev, size_t ws_bytes, void* stream);
 
+/* Non-homogeneous Dirichlet data u = b on the boundary (Section 2,
+ * paragraph 4: the general case reduces to zero data through a modified
+ * f^h).  With g_b the FEM function that takes the values b at the boundary
+ * grid points and 0 inside,
+ *   out = f^h - (L g_b) at the interior points,
+ * L the scaled operator of eq. (bvp glob 2) assembled with the boundary
+ * points (element matrices sum_i 4 h_i^-2 A_i (x) C_others + alpha (x) C).
+ * Solving L u_0 = out (any mode) gives the interior values of the solution;
+ * on the boundary it is b.  b_ext_dev: the extended grid
+ * [nrhs][m_0 + 2]..[m_{N-1} + 2] (double) of all grid points including the
+ * boundary, in the same C order; only its boundary entries (index 0 or
+ * m_i + 1 along some axis) are read.  f_dev: [nrhs][m_0]..[m_{N-1}] or NULL
+ * (zero load); out_dev may equal f_dev, not b_ext_dev.  FP64. */
+int hofem_dirichlet_rhs(hofem_solver solver, const double* b_ext_dev, const double* f_dev,
+                        double* out_dev, int nrhs, void* stream);
+
+/* ---- implicit time stepping -------------------------------------------- */
+
+/* Implicit time stepping with the fast solve, the use the paper names for
+ * time-dependent problems (Section 1; Section 2, paragraph 4).  Each step is
+ * one system of eq. (bvp glob 2) of the stepper's solver, whose alpha carries
+ * the time step dt:
+ *   HOFEM_SCHEME_HEAT  u_t - Lap u = f, backward Euler, alpha = 1/dt:
+ *                      L u^{n+1} = f^h + alpha ((x)_i C_i) u^n
+ *   HOFEM_SCHEME_WAVE  u_tt - Lap u = f, the implicit three-level scheme
+ *                      (u^{n+1} - 2u^n + u^{n-1})/dt^2 - Lap u^{n+1} = f,
+ *                      alpha = 1/dt^2:
+ *                      L u^{n+1} = f^h + alpha ((x)_i C_i)(2u^n - u^{n-1})
+ * A step is one mass product by the operator kernels and one FP64 solve by
+ * algorithm (a) (plus one vector kernel for the wave scheme). */
+enum hofem_scheme { HOFEM_SCHEME_HEAT = 0, HOFEM_SCHEME_WAVE = 1 };
+
+typedef struct hofem_stepper_s* hofem_stepper;
+
+/* A stepper for `solver` (alpha > 0, else HOFEM_EINVAL).  The solver must
+ * outlive the stepper. */
+int hofem_stepper_create(hofem_solver solver, int scheme, hofem_stepper* out);
+void hofem_stepper_destroy(hofem_stepper stepper);
+
+/* Workspace of hofem_stepper_run for nrhs right-hand sides: one FP64 grid
+ * (two for the wave scheme) and the operator's element buffer. */
+int hofem_stepper_workspace_bytes(hofem_stepper stepper, int nrhs, size_t* bytes);
+
+/* Advances u_dev (in: u^n, out: u^{n+nsteps}) by nsteps steps.  f_dev: the
+ * load f^h, constant in time ([nrhs][grid] double), or NULL for zero.
+ * uprev_dev: the wave scheme's previous level (in: u^{n-1}, out:
+ * u^{n+nsteps-1}; unused and may be NULL for the heat scheme).  u_dev,
+ * uprev_dev and f_dev must be distinct.  use_graph != 0 and a non-NULL
+ * stream: the first step of the first call runs eagerly, then one step is
+ * captured into a HIP graph (once per set of buffers and nrhs) and replayed
+ * for the remaining steps; results do not depend on use_graph.  Calls on one
+ * stepper must not overlap. */
+int hofem_stepper_run(hofem_stepper stepper, const double* f_dev, double* u_dev,
+                      double* uprev_dev, int nrhs, int nsteps, void* ws_dev, size_t ws_bytes,
+                      int use_graph, void* stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): hofem_solve
  * in mode HOFEM_MODE_FP32_IR (f_dev, u_dev double, f_dev != u_dev; max_iter,

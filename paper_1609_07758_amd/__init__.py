@@ -82,6 +82,11 @@ SIGNATURES = {
     "hofem_operator_workspace_bytes": (_c_int, [_vp, ctypes.POINTER(_c_size)]),
     "hofem_apply_operator": (_c_int, [_vp, _vp, _vp, _c_int, _vp, _c_size, _vp]),
     "hofem_apply_mass": (_c_int, [_vp, _vp, _vp, _c_int, _vp, _c_size, _vp]),
+    "hofem_dirichlet_rhs": (_c_int, [_vp, _vp, _vp, _vp, _c_int, _vp]),
+    "hofem_stepper_create": (_c_int, [_vp, _c_int, ctypes.POINTER(_vp)]),
+    "hofem_stepper_destroy": (None, [_vp]),
+    "hofem_stepper_workspace_bytes": (_c_int, [_vp, _c_int, ctypes.POINTER(_c_size)]),
+    "hofem_stepper_run": (_c_int, [_vp, _vp, _vp, _vp, _c_int, _c_int, _vp, _c_size, _c_int, _vp]),
     "hofem_batch_create": (_c_int, [ctypes.POINTER(hofem_batch_problem), _c_int,
                                     ctypes.POINTER(_vp)]),
     "hofem_batch_destroy": (None, [_vp]),
@@ -339,6 +344,68 @@ def hofem_batch_solve(batch, mode, f, u, ws=None, max_iter=0, use_graph=True, st
                                   1 if use_graph else 0, _stream(stream)), "hofem_batch_solve")
 
 
+def hofem_dirichlet_rhs(solver, b_ext, f, out, nrhs=1, stream=None):
+    _check(_lib.hofem_dirichlet_rhs(solver, _ptr(b_ext), _ptr(f), _ptr(out), int(nrhs),
+                                    _stream(stream)), "hofem_dirichlet_rhs")
+
+
+SCHEMES = {"heat": 0, "wave": 1}
+
+
+def hofem_stepper_create(solver, scheme):
+    h = ctypes.c_void_p()
+    _check(_lib.hofem_stepper_create(solver, SCHEMES[scheme] if isinstance(scheme, str) else scheme,
+                                     ctypes.byref(h)), "hofem_stepper_create")
+    return h
+
+
+def hofem_stepper_destroy(stepper):
+    _lib.hofem_stepper_destroy(stepper)
+
+
+def hofem_stepper_workspace_bytes(stepper, nrhs=1):
+    b = ctypes.c_size_t()
+    _check(_lib.hofem_stepper_workspace_bytes(stepper, int(nrhs), ctypes.byref(b)),
+           "hofem_stepper_workspace_bytes")
+    return b.value
+
+
+def hofem_stepper_run(stepper, f, u, uprev, nrhs, nsteps, ws, use_graph=True, stream=None):
+    wsb = 0 if ws is None else ws.numel() * ws.element_size()
+    _check(_lib.hofem_stepper_run(stepper, _ptr(f), _ptr(u), _ptr(uprev), int(nrhs), int(nsteps),
+                                  _ptr(ws), wsb, 1 if use_graph else 0, _stream(stream)),
+           "hofem_stepper_run")
+
+
+class Stepper:
+    """Implicit time stepping ('heat': backward Euler, alpha = 1/dt; 'wave':
+    implicit three-level scheme, alpha = 1/dt^2) with a Solver's fast solve."""
+
+    def __init__(self, solver, scheme="heat", nrhs=1):
+        import torch
+        self.solver = solver
+        self.scheme = scheme
+        self.nrhs = int(nrhs)
+        self.handle = hofem_stepper_create(solver.handle, scheme)
+        self.ws = torch.empty(hofem_stepper_workspace_bytes(self.handle, self.nrhs),
+                              dtype=torch.uint8, device="cuda")
+
+    def run(self, u, nsteps, f=None, uprev=None, use_graph=True, stream=None):
+        hofem_stepper_run(self.handle, f, u, uprev, self.nrhs, nsteps, self.ws, use_graph, stream)
+        return u
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            hofem_stepper_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Batch:
     """Independent problems solved together: problems = [(Solver, nrhs), ...].
 
@@ -545,6 +612,15 @@ class Solver:
         if ws is None:
             ws = self.operator_workspace(g.device)
         hofem_apply_mass(self.handle, g, out, nrhs, ws, stream)
+        return out
+
+    def dirichlet_rhs(self, b_ext, f=None, out=None, nrhs=1, stream=None):
+        """f^h with the boundary values of b_ext (extended grid, m_i + 2 per axis) moved in."""
+        import torch
+        if out is None:
+            out = torch.empty((nrhs,) + self.shape if nrhs > 1 else self.shape,
+                              dtype=torch.float64, device=b_ext.device)
+        hofem_dirichlet_rhs(self.handle, b_ext, f, out, nrhs, stream)
         return out
 
     def set_timing(self, enable=True):

@@ -20,6 +20,7 @@
 #include "hofem.h"
 #include "kernels.h"
 #include "plan1d.h"
+#include "solver.h"
 
 using namespace hofem;
 
@@ -490,6 +491,35 @@ std::vector<unsigned char> pack_plan(const Plan1DData& d, PlanOff* off) {
 
 }  // namespace
 
+namespace hofem {
+
+size_t solver_unknowns(const hofem_solver_s* S) { return S->per_rhs; }
+double solver_alpha(const hofem_solver_s* S) { return S->alpha; }
+int solver_device(const hofem_solver_s* S) { return S->device; }
+size_t solver_op_elem_bytes(const hofem_solver_s* S) { return op_elem_bytes(S); }
+
+int solver_solve_fp64(hofem_solver_s* S, const double* in, double* out, int nrhs, hipStream_t st) {
+  const std::vector<PassSpec> list = solve_list(S, true, nrhs);
+  return run_list(S, list, true, in, out, out, 0, 0, 0, 0, nrhs, st);
+}
+
+int solver_mass_update(hofem_solver_s* S, const double* f, const double* w, double* out,
+                       double coef, double* elem, int nrhs, hipStream_t st) {
+  OpArgs o;
+  // out = f - L' w with L' = -coef (x)C (f given), or out = L' w with
+  // L' = coef (x)C (f NULL)
+  const int rc = make_op(S, w, f, out, 0, nrhs, elem, &o);
+  if (rc != HOFEM_OK) return rc;
+  for (int i = 0; i < S->N; ++i) o.scale[i] = 0.0;
+  o.alpha = f ? -coef : coef;
+  LaunchTimer tm(S, st, HOFEM_PASS_OPERATOR, -1, 1, (double)S->per_rhs * nrhs * (f ? 24 : 16));
+  HIPCHK(launch_operator(o, st));
+  tm.done();
+  return HOFEM_OK;
+}
+
+}  // namespace hofem
+
 extern "C" {
 
 const char* hofem_status_string(int status) {
@@ -911,6 +941,15 @@ int apply_op(hofem_solver S, const double* u_dev, double* out_dev, int nrhs, voi
 }
 
 }  // namespace
+
+int hofem_dirichlet_rhs(hofem_solver S, const double* b_ext_dev, const double* f_dev,
+                        double* out_dev, int nrhs, void* stream) {
+  if (!S || !b_ext_dev || !out_dev || nrhs < 1) return HOFEM_EINVAL;
+  if (static_cast<const void*>(b_ext_dev) == static_cast<const void*>(out_dev)) return HOFEM_EINVAL;
+  OpArgs o = op_args(S, nullptr, nullptr, out_dev, 0, nrhs);
+  HIPCHK(launch_dirichlet_lift(o, b_ext_dev, f_dev, out_dev, static_cast<hipStream_t>(stream)));
+  return HOFEM_OK;
+}
 
 int hofem_apply_operator(hofem_solver S, const double* u_dev, double* out_dev, int nrhs,
                          void* ws_dev, size_t ws_bytes, void* stream) {

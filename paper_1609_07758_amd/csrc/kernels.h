@@ -1,5 +1,6 @@
 // Internal interface between the solver (capi.hip) and the device kernels
-// (kernels.hip).  Plain structs of device pointers and sizes.
+// (line passes in linepass.h / linepass.hip, operators in operator.hip,
+// vector kernels in pcg.hip).  Plain structs of device pointers and sizes.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -112,6 +113,10 @@ struct OpArgs {
 hipError_t launch_operator(const OpArgs& a, hipStream_t s);
 // Element buffer the 3D operator needs (0 when it needs none).
 size_t op3_elem_doubles(const OpArgs& a);
+// out = f - (L_ext b)|interior for Dirichlet values b on the extended grid
+// [nrhs][m_0+2]..[m_{N-1}+2] (f may be NULL).
+hipError_t launch_dirichlet_lift(const OpArgs& a, const double* bext, const double* f,
+                                 double* out, hipStream_t s);
 
 // u += delta over `count` elements with per-workgroup partial sums of
 // delta^2 and u^2 (nparts workgroups), reduced to out[0..1] by a second

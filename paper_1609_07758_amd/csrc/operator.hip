@@ -720,6 +720,92 @@ __global__ __launch_bounds__(256) void axpy_kernel(const float* delta, double* u
     u[i] += (double)delta[i];
 }
 
+// Boundary lift of non-homogeneous Dirichlet data (Section 2, paragraph 4:
+// the general case reduces to zero data through f^h).  For every interior
+// point q: out[q] = f[q] - sum over the elements E containing q and the
+// local nodes c of E on the boundary of K_E[r(q), c] b[c], with K_E the
+// scaled element matrix sum_d s_d A_d (x)_{e != d} C_e + alpha (x)_e C_e and
+// b the boundary values on the extended grid (m_d + 2 points per axis).
+// Points whose elements do not touch the boundary keep f.
+template <int N>
+__global__ void dirichlet_lift_kernel(OpArgs a, const double* __restrict__ bext,
+                                      const double* __restrict__ f, double* __restrict__ out,
+                                      long long total) {
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  long long rem = t;
+  int g[3];                       // extended index along each axis, 1..m_d
+  long long eper = 1;
+  for (int d = N - 1; d >= 0; --d) {
+    g[d] = (int)(rem % a.m[d]) + 1;
+    rem /= a.m[d];
+    eper *= a.m[d] + 2;
+  }
+  const long long rhs = rem;
+  // candidate elements along each axis: one (interior point of an element)
+  // or two (mesh node)
+  int e0[3], ne[3];
+  bool near = false;
+  for (int d = 0; d < N; ++d) {
+    const int n = a.n[d];
+    if (g[d] % n == 0) {
+      e0[d] = g[d] / n - 1;
+      ne[d] = 2;
+    } else {
+      e0[d] = g[d] / n;
+      ne[d] = 1;
+    }
+    if (e0[d] == 0 || e0[d] + ne[d] - 1 == a.K[d] - 1) near = true;
+  }
+  const double fv = f ? f[t] : 0.0;
+  if (!near) {
+    out[t] = fv;
+    return;
+  }
+  const double* bx = bext + rhs * eper;
+  double acc = 0.0;
+  const int ncomb = (N > 0 ? ne[0] : 1) * (N > 1 ? ne[1] : 1) * (N > 2 ? ne[2] : 1);
+  for (int comb = 0; comb < ncomb; ++comb) {
+    int cc = comb;
+    int r[3], e[3];
+    for (int d = N - 1; d >= 0; --d) {
+      e[d] = e0[d] + cc % ne[d];
+      cc /= ne[d];
+      r[d] = g[d] - a.n[d] * e[d];
+    }
+    // local nodes c of element e on the boundary
+    int nl = 1;
+    for (int d = 0; d < N; ++d) nl *= a.n[d] + 1;
+    for (int lc = 0; lc < nl; ++lc) {
+      int c[3], G[3];
+      int x = lc;
+      bool bnd = false;
+      for (int d = N - 1; d >= 0; --d) {
+        c[d] = x % (a.n[d] + 1);
+        x /= a.n[d] + 1;
+        G[d] = a.n[d] * e[d] + c[d];
+        if (G[d] == 0 || G[d] == a.m[d] + 1) bnd = true;
+      }
+      if (!bnd) continue;
+      long long bi = 0;
+      for (int d = 0; d < N; ++d) bi = bi * (a.m[d] + 2) + G[d];
+      const double bv = bx[bi];
+      // K_E[r, c]
+      double mass = 1.0;
+      for (int d = 0; d < N; ++d) mass *= a.C[d][r[d] * (a.n[d] + 1) + c[d]];
+      double kv = a.alpha * mass;
+      for (int d = 0; d < N; ++d) {
+        double term = a.scale[d] * a.A[d][r[d] * (a.n[d] + 1) + c[d]];
+        for (int o = 0; o < N; ++o)
+          if (o != d) term *= a.C[o][r[o] * (a.n[o] + 1) + c[o]];
+        kv += term;
+      }
+      acc += kv * bv;
+    }
+  }
+  out[t] = fv - acc;
+}
+
 }  // namespace
 
 hipError_t launch_operator(const OpArgs& a, hipStream_t s) {
@@ -800,6 +886,21 @@ hipError_t launch_axpy(const float* delta, double* u, long long count, hipStream
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(axpy_kernel, dim3((unsigned)blocks), dim3(256), 0, s, delta, u, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_dirichlet_lift(const OpArgs& a, const double* bext, const double* f,
+                                 double* out, hipStream_t s) {
+  long long total = a.nrhs;
+  for (int i = 0; i < a.N; ++i) total *= a.m[i];
+  if (total == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((total + 255) / 256);
+  switch (a.N) {
+    case 1: hipLaunchKernelGGL(dirichlet_lift_kernel<1>, dim3(blocks), dim3(256), 0, s, a, bext, f, out, total); break;
+    case 2: hipLaunchKernelGGL(dirichlet_lift_kernel<2>, dim3(blocks), dim3(256), 0, s, a, bext, f, out, total); break;
+    case 3: hipLaunchKernelGGL(dirichlet_lift_kernel<3>, dim3(blocks), dim3(256), 0, s, a, bext, f, out, total); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
