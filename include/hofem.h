@@ -66,8 +66,10 @@ enum hofem_mode {
   HOFEM_MODE_FP64 = 0,     /* FP64 transforms; f, u are double */
   HOFEM_MODE_FP32 = 1,     /* FP32 transforms with FP32 accumulation; f, u are float */
   HOFEM_MODE_FP32_IR = 2,  /* FP32 transforms + FP64 iterative refinement; f, u are double */
-  HOFEM_MODE_FP32_PCG = 3  /* CG on the FP64 operator preconditioned by the FP32 solve;
+  HOFEM_MODE_FP32_PCG = 3, /* CG on the FP64 operator preconditioned by the FP32 solve;
                               f, u are double */
+  HOFEM_MODE_FP64_B = 4    /* algorithm (b): FP64 transforms along axes 0..N-2, banded
+                              solves along axis N-1; f, u are double */
 };
 
 typedef struct hofem_plan1d_s* hofem_plan1d;
@@ -171,6 +173,13 @@ int hofem_solver_workspace_bytes(hofem_solver solver, int mode, int nrhs, size_t
  * Step (1) of algorithm (a) (the mass solve) is not performed: applying the
  * direct transforms to f^h itself gives the same coefficients, because the
  * transforms take y = C w as their input.
+ * Mode HOFEM_MODE_FP64_B runs algorithm (b) of Section 2, paragraph 4
+ * instead: direct transforms along axes 0..N-2, then along axis N-1 for
+ * every combination of the other axes' modes the banded SPD system
+ * (4 h^-2 A + mu C) v = phi of eq. (sys x1 2), mu = alpha + sum of the other
+ * axes' 4 h_i^-2 lambda_i (static condensation of the element-interior
+ * points, cyclic reduction of the mesh-node system), then inverse
+ * transforms along axes N-2..0.  Same result, FP64, no workspace.
  *   f_dev, u_dev : [nrhs][m_0]..[m_{N-1}], double (FP64, FP32_IR) or float
  *                  (FP32).  u_dev == f_dev (in place) is allowed for FP64
  *                  and FP32, not for FP32_IR.
@@ -375,7 +384,8 @@ enum hofem_pass_kind {
   HOFEM_PASS_INVERSE = 1,   /* inverse transform along one axis */
   HOFEM_PASS_FUSED = 2,     /* direct transform, division, inverse transform */
   HOFEM_PASS_OPERATOR = 3,  /* FP64 residual / operator apply */
-  HOFEM_PASS_UPDATE = 4     /* refinement update and norms */
+  HOFEM_PASS_UPDATE = 4,    /* refinement update and norms */
+  HOFEM_PASS_BANDED = 5     /* banded solves of algorithm (b) along one axis */
 };
 
 typedef struct {

@@ -32,7 +32,7 @@ HOFEM_EHIP = -5
 HOFEM_ENOMEM = -6
 HOFEM_ETOOBIG = -7
 
-MODES = {"fp64": 0, "fp32": 1, "fp32_ir": 2, "fp32_pcg": 3}
+MODES = {"fp64": 0, "fp32": 1, "fp32_ir": 2, "fp32_pcg": 3, "fp64_b": 4}
 TABLES = {"lam": 0, "p": 1, "inorm": 2, "E": 3, "A": 4, "C": 5, "gx": 6, "gw": 7, "B": 8, "D": 9}
 
 # Names and signatures of every entry point of include/hofem.h.
@@ -58,7 +58,7 @@ class hofem_pass_time(ctypes.Structure):
                 ("launches", ctypes.c_longlong), ("ms", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
-PASS_KINDS = {0: "forward", 1: "inverse", 2: "fused", 3: "operator", 4: "update"}
+PASS_KINDS = {0: "forward", 1: "inverse", 2: "fused", 3: "operator", 4: "update", 5: "banded"}
 
 
 SIGNATURES = {

@@ -41,7 +41,7 @@ def _jobs():
         jobs.append(([HIPCC] + HIP_FLAGS + [f"-DHOFEM_ORDER={n}", "-c",
                                             os.path.join(CSRC, "linepass.hip"), "-o", o], o))
     for src in ("linepass_dispatch.hip", "operator.hip", "pcg.hip", "capi.hip", "batch.hip",
-                "timestep.hip"):
+                "timestep.hip", "banded.hip"):
         o = os.path.join(OUT_DIR, src.replace(".hip", ".o"))
         jobs.append(([HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", o], o))
     return jobs

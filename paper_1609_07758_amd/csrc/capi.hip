@@ -243,6 +243,51 @@ size_t op_elem_bytes(const hofem_solver_s* S) {
 
 // FP32_IR workspace: the FP32 correction grid, the norm partials, the
 // operator's element buffer.
+// Algorithm (b): transforms along axes 0..N-2, banded solves along N-1.
+int solve_alg_b(hofem_solver_s* S, const double* f, double* u, int nrhs, hipStream_t st) {
+  const int N = S->N, b = N - 1;
+  const DevAxis& X = S->ax[b];
+  std::vector<PassSpec> fw, inv;
+  for (int a = 0; a < b; ++a) fw.push_back({a, PASS_FWD});
+  for (int a = b - 1; a >= 0; --a) inv.push_back({a, PASS_INV});
+  const double* bin = f;
+  if (!fw.empty()) {
+    const int rc = run_list(S, fw, true, f, u, u, 0, 0, 0, 0, nrhs, st);
+    if (rc != HOFEM_OK) return rc;
+    bin = u;
+  }
+  BandArgs a{};
+  a.in = bin;
+  a.out = u;
+  a.n = X.n;
+  a.K = X.K;
+  a.m = X.m;
+  a.scale = X.scale;
+  a.A = X.A;
+  a.C = X.C;
+  a.others = 1;
+  for (int i = 0; i < b; ++i) a.others *= S->ax[i].m;
+  a.nlines = a.others * nrhs;
+  a.alpha = S->alpha;
+  a.nother = 0;
+  for (int i = 0; i < b; ++i) {
+    long long div = 1;
+    for (int j = i + 1; j < b; ++j) div *= S->ax[j].m;
+    a.olam[a.nother] = S->ax[i].t64.lam;
+    a.oscale[a.nother] = S->ax[i].scale;
+    a.odiv[a.nother] = div;
+    a.omod[a.nother] = S->ax[i].m;
+    ++a.nother;
+  }
+  {
+    LaunchTimer tm(S, st, HOFEM_PASS_BANDED, b, 1, (double)S->per_rhs * nrhs * 16);
+    HIPCHK(launch_banded(a, st));
+    tm.done();
+  }
+  if (!inv.empty()) return run_list(S, inv, true, u, u, u, 0, 0, 0, 0, nrhs, st);
+  return HOFEM_OK;
+}
+
 size_t ir_workspace(const hofem_solver_s* S, int nrhs) {
   size_t b = S->per_rhs * (size_t)nrhs * sizeof(float);
   b = (b + 255) & ~size_t(255);
@@ -712,7 +757,8 @@ int hofem_solver_workspace_bytes(hofem_solver solver, int mode, int nrhs, size_t
   if (!solver || !bytes || nrhs < 1) return HOFEM_EINVAL;
   switch (mode) {
     case HOFEM_MODE_FP64:
-    case HOFEM_MODE_FP32: *bytes = 0; return HOFEM_OK;
+    case HOFEM_MODE_FP32:
+    case HOFEM_MODE_FP64_B: *bytes = 0; return HOFEM_OK;
     case HOFEM_MODE_FP32_IR: *bytes = ir_workspace(solver, nrhs); return HOFEM_OK;
     case HOFEM_MODE_FP32_PCG: *bytes = pcg_bytes(solver, nullptr); return HOFEM_OK;
     default: return HOFEM_EINVAL;
@@ -723,6 +769,13 @@ int hofem_solve(hofem_solver S, int mode, const void* f_dev, void* u_dev, int nr
                 size_t ws_bytes, int max_iter, double tol, void* stream, hofem_info* info) {
   if (!S || !f_dev || !u_dev || nrhs < 1) return HOFEM_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if (mode == HOFEM_MODE_FP64_B) {
+    const int rc = solve_alg_b(S, static_cast<const double*>(f_dev), static_cast<double*>(u_dev),
+                               nrhs, st);
+    if (rc != HOFEM_OK) return rc;
+    if (info) *info = hofem_info{0, 0.0, 0.0};
+    return HOFEM_OK;
+  }
   const std::vector<PassSpec> list = solve_list(S, mode == HOFEM_MODE_FP64, nrhs);
   if (mode == HOFEM_MODE_FP64 || mode == HOFEM_MODE_FP32) {
     const bool f64 = mode == HOFEM_MODE_FP64;

@@ -118,6 +118,28 @@ size_t op3_elem_doubles(const OpArgs& a);
 hipError_t launch_dirichlet_lift(const OpArgs& a, const double* bext, const double* f,
                                  double* out, hipStream_t s);
 
+// Banded solves of algorithm (b) along the contiguous axis: every line L
+// (nlines of them, m = nK - 1 values each, contiguous) solves
+// (scale A + mu C) v = in with mu = alpha + sum_i oscale[i] *
+// olam[i][(t / odiv[i]) % omod[i]], t = L % others; in == out allowed.
+struct BandArgs {
+  const double* in;
+  double* out;
+  int n, K, m;
+  double scale;
+  const double* A;     // local stiffness (n+1)^2, device
+  const double* C;     // local mass (n+1)^2, device
+  long long nlines;
+  long long others;    // lines per right-hand side
+  double alpha;
+  int nother;
+  const double* olam[2];
+  double oscale[2];
+  long long odiv[2];
+  long long omod[2];
+};
+hipError_t launch_banded(const BandArgs& a, hipStream_t s);
+
 // u += delta over `count` elements with per-workgroup partial sums of
 // delta^2 and u^2 (nparts workgroups), reduced to out[0..1] by a second
 // launch (fixed order: deterministic).

@@ -1,7 +1,8 @@
 """Parity at full size, in the launch configurations the benchmark times.
 
 large_2d (n = 9, K = 1024 per axis, 84,916,225 unknowns) and cube_3d (n = 4,
-K = 128 per axis, 133,432,831 unknowns): the FP64 solve, the FP32 solve with
+K = 128 per axis, 133,432,831 unknowns): the FP64 solve by algorithms (a)
+and (b), the FP32 solve with
 four FP64 refinement steps and the FP32-preconditioned CG form (relative
 update 1e-13) against the oracle's exact dense solve, relative l2 <= 1e-12
 over all unknowns; the unrefined FP32 solve within 1e-5.
@@ -31,6 +32,7 @@ def check(cfg, f):
     S = H.Solver(cfg["orders"], cfg["Ks"], cfg["X"], cfg["alpha"])
     fd = torch.from_numpy(f).to(DEV)
     u64 = S.solve(fd, mode="fp64").cpu().numpy()
+    ub = S.solve(fd, mode="fp64_b").cpu().numpy()
     uir = S.solve(fd, mode="fp32_ir", max_iter=4, tol=0.0).cpu().numpy()
     u32 = S.solve(fd.float(), mode="fp32").double().cpu().numpy()
     upcg, info, st = S.solve(fd, mode="fp32_pcg", max_iter=40, tol=1e-13, want_info=True)
@@ -40,9 +42,11 @@ def check(cfg, f):
     S.close()
     want = osolve.solve(f, cfg["orders"], cfg["Ks"], cfg["X"], cfg["alpha"])
     e64, eir, e32, epcg = rel(u64, want), rel(uir, want), rel(u32, want), rel(upcg, want)
-    print(f"fp64 {e64:.3e}  fp32+4 steps {eir:.3e}  fp32 {e32:.3e}  "
+    eb = rel(ub, want)
+    print(f"fp64 {e64:.3e}  algorithm (b) {eb:.3e}  fp32+4 steps {eir:.3e}  fp32 {e32:.3e}  "
           f"fp32_pcg {epcg:.3e} ({info.iterations} iterations)")
     assert e64 <= 1e-12
+    assert eb <= 1e-12
     assert eir <= 1e-12
     assert e32 <= 1e-5
     assert epcg <= 1e-12

@@ -69,6 +69,29 @@ def test_fp64_solve_matches_oracle(orders, Ks, X, alpha):
     assert rel(got, want) < 1e-12
 
 
+@pytest.mark.parametrize("orders,Ks,X,alpha", CASES)
+def test_algorithm_b_matches_oracle(orders, Ks, X, alpha):
+    # algorithm (b): transforms along the leading axes, banded solves along
+    # the last one; the same unique solution
+    shp = workloads.shape(orders, Ks)
+    f = workloads.uniform_rhs(shp, seed=0)
+    got, _ = run_case(orders, Ks, X, alpha, f, mode="fp64_b")
+    want = osolve.solve(f, orders, Ks, X, alpha)
+    assert rel(got, want) < 1e-12
+
+
+def test_algorithm_b_nrhs_and_in_place():
+    orders, Ks, X = (3, 9), (8, 64), (1.0, 1.0)
+    shp = workloads.shape(orders, Ks)
+    f = np.stack([workloads.uniform_rhs(shp, seed=s) for s in range(2)])
+    S = H.Solver(orders, Ks, X, 0.25)
+    buf = gpu(f)
+    S.solve(buf, buf, mode="fp64_b", nrhs=2)
+    got = host(buf)
+    for r in range(2):
+        assert rel(got[r], osolve.solve(f[r], orders, Ks, X, 0.25)) < 1e-12
+
+
 def test_small_2d_manufactured_rhs():
     # u = sin(pi x) sin(2 pi y), f = 5 pi^2 u, 3-point Gauss load vector.
     cfg = workloads.CONFIGS["small_2d"]
