@@ -39,7 +39,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
-KERNEL_SOURCES = ("linepass.h", "linepass.hip", "linepass_dispatch.hip", "capi.hip")
+# the line-pass sources: their hash keys the committed HBM counter summary
+# (and the autotuner's cache)
+KERNEL_SOURCES = ("linepass.h", "linepass.hip", "linepass_dispatch.hip", "kernels.h")
 
 
 def kernel_sha():
@@ -84,6 +86,17 @@ def time_calls(torch, fn, steps, warmup, stream=None):
     return start.elapsed_time(stop) / steps
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(cfg, f_host, u_gpu64, others):
     """Time the oracle's dense solve on the host; return the record and the
     parity of the GPU solutions against it."""
@@ -109,6 +122,7 @@ def cpu_baseline(cfg, f_host, u_gpu64, others):
     for name, u in others.items():
         parity[name + "_rel_l2"] = float(np.linalg.norm(u - ref) / nref)
     rec = {"value": M / t_apply, "unit": "unknowns/s", "cores": int(threads), "kind": "oracle",
+           "cpu_model": cpu_model(),
            "sample": f"whole {cfg['name']} right-hand side ({M} unknowns) through the oracle's "
                      f"dense eigenvector products (FP64, {t_apply:.1f} s); eigen data and dense V "
                      f"construction timed apart: {t_setup:.1f} s"}
@@ -141,6 +155,25 @@ def bench_headline(args, torch, H, np, workloads, dev):
     ms64 = time_calls(torch, lambda: S.solve(f64, u64, mode="fp64"), args.steps, 0)
     passes64 = S.pass_times()
     S.set_timing(False)
+
+    if args.profile_fp64:
+        # counter runs: the FP64 solves alone
+        S.close()
+        return {"value": M / (ms64 * 1e-3), "ms_per_step": ms64,
+                "config": {"workload": "large_2d", "profile_fp64_only": True}}
+
+    log("large_2d: algorithm (b)")
+    ub = torch.empty_like(f64)
+    S.set_timing(True)
+    ms_b = time_calls(torch, lambda: S.solve(f64, ub, mode="fp64_b"), args.steps, args.warmup)
+    passes_b = S.pass_times()
+    S.set_timing(False)
+
+    log("large_2d: autotuned launch shapes (FP64)")
+    tune = S.autotune("fp64", nrhs=1, reps=3, f=f64, u=u64)
+    ms64_tuned = time_calls(torch, lambda: S.solve(f64, u64, mode="fp64"), args.steps, args.warmup)
+    H.hofem_solver_tune_reset(S.handle)
+    S.solve(f64, u64, mode="fp64")
 
     log("large_2d: FP32 + refinement")
     S.set_timing(True)
@@ -176,15 +209,24 @@ def bench_headline(args, torch, H, np, workloads, dev):
     achieved = dom["bytes"] / (avg_ms * 1e-3) / 1e9
     kind = f"{dom['kind']}_axis{dom['axis']}_fp64"
     traffic = measured_traffic("large_2d", kind)
+    tot_bytes = sum(p["bytes"] * p["launches"] for p in passes64)
+    tot_ms = sum(p["ms"] for p in passes64)
     rec = {
         "value": M / (ms64 * 1e-3),
         "ms_per_step": ms64,
+        "hbm_all_passes": {"algorithmic_bytes_per_solve": tot_bytes / max(1, args.steps),
+                           "gbs": tot_bytes / (tot_ms * 1e-3) / 1e9,
+                           "frac": tot_bytes / (tot_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "algorithm_b": {"unknowns_per_s": M / (ms_b * 1e-3), "ms_per_step": ms_b,
+                        "passes": [dict(p, avg_ms=p["ms"] / p["launches"]) for p in passes_b]},
+        "autotune_fp64": {"ms_default": ms64, "ms_tuned": ms64_tuned, "passes": tune},
         "config": {"workload": "large_2d", "N": 2, "order_n": cfg["orders"][0],
                    "K_per_axis": cfg["Ks"][0], "unknowns": M, "rhs": "uniform[-1,1) seed 0",
                    "alpha": cfg["alpha"]},
         "fp32_refined": {"unknowns_per_s": M / (ms_ir * 1e-3), "ms_per_step": ms_ir,
                          "refinement_steps": args.ir_iters, "speedup_vs_fp64": ms64 / ms_ir,
                          "rel_l2_vs_fp64_gpu": dist(uir),
+                         "algorithm_b_rel_l2_vs_fp64_gpu": dist(ub),
                          "rel_l2_vs_fp64_gpu_by_steps": hist},
         "fp32_pcg": {"unknowns_per_s": M / (ms_pcg * 1e-3), "ms_per_solve": ms_pcg,
                      "iterations": pcg_info.get("it"), "rel_update": pcg_info.get("upd"),
@@ -204,7 +246,8 @@ def bench_headline(args, torch, H, np, workloads, dev):
         log("large_2d: CPU oracle")
         base, parity = cpu_baseline(cfg, f_host, u64.cpu().numpy(),
                                     {"fp32_refined": uir.cpu().numpy(),
-                                     "fp32_pcg": upcg.cpu().numpy()})
+                                     "fp32_pcg": upcg.cpu().numpy(),
+                                     "algorithm_b": ub.cpu().numpy()})
         rec["cpu_baseline"] = base
         rec["parity_vs_oracle"] = parity
     else:
@@ -242,10 +285,43 @@ def bench_batch(args, torch, H, np, workloads, dev):
                                                   stream=s.cuda_stream), steps, 2, s)
     torch.cuda.synchronize()
     err = float(torch.linalg.vector_norm(uir - u) / torch.linalg.vector_norm(u))
+    B.close()
+
+    # per-(n, K) groups: one FP64 solve of a group's right-hand sides, the
+    # default launch shapes against the autotuned ones
+    log("batch_2d: per-(n, K) groups, default vs autotuned shapes")
+    counts = {}
+    for n, K in pairs:
+        counts[(n, K)] = counts.get((n, K), 0) + 1
+    breakdown = []
+    for (n, K), cnt in sorted(counts.items()):
+        S = solvers[(n, K)]
+        r = cnt * cfg["nrhs"]
+        fg = torch.rand(r * S.size, dtype=torch.float64, device=dev) * 2 - 1
+        ug = torch.empty_like(fg)
+        t_def = time_calls(torch, lambda: S.solve(fg, ug, mode="fp64", nrhs=r), steps, 1)
+        S.autotune("fp64", nrhs=r, reps=2, f=fg, u=ug)
+        t_tun = time_calls(torch, lambda: S.solve(fg, ug, mode="fp64", nrhs=r), steps, 1)
+        breakdown.append({"n": n, "K": K, "problems": cnt, "unknowns": r * S.size,
+                          "ms_default": t_def, "ms_tuned": t_tun,
+                          "unknowns_per_s_tuned": r * S.size / (t_tun * 1e-3)})
+        del fg, ug
+    B = H.Batch(probs)          # fresh graph with the tuned shapes
+    f2 = torch.empty(B.total, dtype=torch.float64, device=dev)
+    for p, arr in enumerate(workloads.batch_rhs(pairs, cfg["nrhs"], seed=0)):
+        B.view(f2, p).copy_(torch.from_numpy(arr))
+    u2 = torch.empty_like(f2)
+    with torch.cuda.stream(s):
+        ms64_tuned = time_calls(torch, lambda: B.solve(f2, u2, mode="fp64", use_graph=True,
+                                                       stream=s.cuda_stream), steps, 2, s)
+    torch.cuda.synchronize()
     rec = {"workload": "batch_2d", "problems": len(pairs), "groups": B.groups,
            "rhs_per_problem": cfg["nrhs"], "unknowns": B.total,
            "fp64": {"unknowns_per_s": B.total / (ms64 * 1e-3), "ms_per_batch": ms64,
-                    "ms_per_batch_without_graph": ms64_eager},
+                    "ms_per_batch_without_graph": ms64_eager,
+                    "ms_per_batch_tuned": ms64_tuned,
+                    "unknowns_per_s_tuned": B.total / (ms64_tuned * 1e-3)},
+           "per_n_K": breakdown,
            "fp32_refined": {"unknowns_per_s": B.total / (ms_ir * 1e-3), "ms_per_batch": ms_ir,
                             "refinement_steps": args.ir_iters, "rel_l2_vs_fp64_gpu": err}}
     B.close()
@@ -323,6 +399,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--ir-iters", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-fp64", action="store_true",
+                    help="large_2d FP64 solves only (for profiler counter runs)")
     ap.add_argument("--only", default="large_2d,batch_2d,cube_3d,varcoef_3d",
                     help="comma-separated workloads; large_2d is the headline")
     ap.add_argument("--calibration-copy", action="store_true",

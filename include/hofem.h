@@ -410,6 +410,54 @@ int hofem_solver_set_timing(hofem_solver solver, int enable);
 int hofem_solver_pass_times(hofem_solver solver, hofem_pass_time* out_host, int max_entries,
                             int* count);
 
+/* ---- autotuner of the line passes' launch shapes ------------------------- */
+
+/* A pass's launch shape: lines per workgroup and workgroup size. */
+typedef struct {
+  int kind;             /* HOFEM_PASS_FORWARD, _INVERSE or _FUSED */
+  int axis;
+  int fp64;             /* 1: FP64 pass, 0: FP32 */
+  int cb;               /* lines per workgroup */
+  int threads;          /* lanes per workgroup (256 or 512) */
+  long long nlines;     /* lines of the pass it was tuned for (0: forced) */
+  double ms_default;    /* one solve with the default shape (ms) */
+  double ms_tuned;      /* one solve with the chosen shape (ms) */
+} hofem_tune_entry;
+
+/* Launch shapes the pass (kind, axis, precision) of a solve of nrhs
+ * right-hand sides can run with, the default first: out to cb_host /
+ * threads_host (at most max_entries), their number to *count.  Every shape
+ * gives the same result up to rounding order. */
+int hofem_pass_shape_candidates(hofem_solver solver, int kind, int axis, int fp64, int nrhs,
+                                int* cb_host, int* threads_host, int max_entries, int* count);
+
+/* Forces a shape on one pass of this solver (cb = 0: back to the default).
+ * A shape the pass cannot run makes later solves fail with HOFEM_EHIP. */
+int hofem_pass_set_shape(hofem_solver solver, int kind, int axis, int fp64, int cb, int threads);
+
+/* Autotunes the launch shapes of the passes of `mode` (FP64, FP32 or
+ * FP32_IR) for nrhs right-hand sides, one pass after another: every
+ * candidate shape is timed over `reps` whole solves (HIP events on `stream`;
+ * one refinement step for FP32_IR) on the given buffers and workspace, and
+ * the fastest is kept for the solver's later solves.  Waits for the stream.
+ * Reports one entry per pass (at most max_entries) and their number. */
+int hofem_solver_autotune(hofem_solver solver, int mode, const void* f_dev, void* u_dev, int nrhs,
+                          void* ws_dev, size_t ws_bytes, int reps, void* stream,
+                          hofem_tune_entry* out_host, int max_entries, int* count);
+
+/* Tuning cache on disk (text, one line per tuned pass, keyed by the kernel
+ * build's hash, n, K, precision, pass kind, stride and line count): save
+ * merges the solver's tuned shapes into `path`; load applies the matching
+ * entries for a solve of `mode` with nrhs right-hand sides (*applied: how
+ * many; a missing file applies none).  reset drops every tuned or forced
+ * shape. */
+int hofem_solver_tune_save(hofem_solver solver, const char* path);
+int hofem_solver_tune_load(hofem_solver solver, const char* path, int mode, int nrhs, int* applied);
+int hofem_solver_tune_reset(hofem_solver solver);
+
+/* Hash of the line-pass kernel sources this library was built from. */
+const char* hofem_kernel_hash(void);
+
 /* Human-readable name of a status code (static string). */
 const char* hofem_status_string(int status);
 

@@ -61,6 +61,12 @@ class hofem_pass_time(ctypes.Structure):
 PASS_KINDS = {0: "forward", 1: "inverse", 2: "fused", 3: "operator", 4: "update", 5: "banded"}
 
 
+class hofem_tune_entry(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("axis", ctypes.c_int), ("fp64", ctypes.c_int),
+                ("cb", ctypes.c_int), ("threads", ctypes.c_int), ("nlines", ctypes.c_longlong),
+                ("ms_default", ctypes.c_double), ("ms_tuned", ctypes.c_double)]
+
+
 SIGNATURES = {
     "hofem_plan1d_create": (_c_int, [_c_int, _c_int, ctypes.POINTER(_vp)]),
     "hofem_plan1d_destroy": (None, [_vp]),
@@ -102,6 +108,17 @@ SIGNATURES = {
     "hofem_solver_set_timing": (_c_int, [_vp, _c_int]),
     "hofem_solver_pass_times": (_c_int, [_vp, ctypes.POINTER(hofem_pass_time), _c_int,
                                          ctypes.POINTER(_c_int)]),
+    "hofem_pass_shape_candidates": (_c_int, [_vp, _c_int, _c_int, _c_int, _c_int,
+                                             ctypes.POINTER(_c_int), ctypes.POINTER(_c_int), _c_int,
+                                             ctypes.POINTER(_c_int)]),
+    "hofem_pass_set_shape": (_c_int, [_vp, _c_int, _c_int, _c_int, _c_int, _c_int]),
+    "hofem_solver_autotune": (_c_int, [_vp, _c_int, _vp, _vp, _c_int, _vp, _c_size, _c_int, _vp,
+                                       ctypes.POINTER(hofem_tune_entry), _c_int,
+                                       ctypes.POINTER(_c_int)]),
+    "hofem_solver_tune_save": (_c_int, [_vp, ctypes.c_char_p]),
+    "hofem_solver_tune_load": (_c_int, [_vp, ctypes.c_char_p, _c_int, _c_int, ctypes.POINTER(_c_int)]),
+    "hofem_solver_tune_reset": (_c_int, [_vp]),
+    "hofem_kernel_hash": (ctypes.c_char_p, []),
     "hofem_status_string": (ctypes.c_char_p, [_c_int]),
     "hofem_last_hip_error": (_c_int, []),
 }
@@ -466,6 +483,53 @@ def hofem_solver_pass_times(solver, max_entries=64):
                  launches=a.launches, ms=a.ms, bytes=a.bytes) for a in arr[:cnt.value]]
 
 
+def hofem_pass_shape_candidates(solver, kind, axis, fp64, nrhs=1):
+    cb = (ctypes.c_int * 64)()
+    thr = (ctypes.c_int * 64)()
+    cnt = ctypes.c_int()
+    k = {"forward": 0, "inverse": 1, "fused": 2}.get(kind, kind)
+    _check(_lib.hofem_pass_shape_candidates(solver, k, int(axis), 1 if fp64 else 0, int(nrhs), cb, thr,
+                                            64, ctypes.byref(cnt)), "hofem_pass_shape_candidates")
+    return [(cb[i], thr[i]) for i in range(min(cnt.value, 64))]
+
+
+def hofem_pass_set_shape(solver, kind, axis, fp64, cb, threads):
+    k = {"forward": 0, "inverse": 1, "fused": 2}.get(kind, kind)
+    _check(_lib.hofem_pass_set_shape(solver, k, int(axis), 1 if fp64 else 0, int(cb), int(threads)),
+           "hofem_pass_set_shape")
+
+
+def hofem_solver_autotune(solver, mode, f, u, nrhs=1, ws=None, reps=3, stream=None):
+    arr = (hofem_tune_entry * 16)()
+    cnt = ctypes.c_int()
+    wsb = 0 if ws is None else ws.numel() * ws.element_size()
+    _check(_lib.hofem_solver_autotune(solver, MODES[mode], _ptr(f), _ptr(u), int(nrhs), _ptr(ws), wsb,
+                                      int(reps), _stream(stream), arr, 16, ctypes.byref(cnt)),
+           "hofem_solver_autotune")
+    return [dict(kind=PASS_KINDS.get(e.kind, str(e.kind)), axis=e.axis, fp64=bool(e.fp64), cb=e.cb,
+                 threads=e.threads, nlines=e.nlines, ms_default=e.ms_default, ms_tuned=e.ms_tuned)
+            for e in arr[:min(cnt.value, 16)]]
+
+
+def hofem_solver_tune_save(solver, path):
+    _check(_lib.hofem_solver_tune_save(solver, os.fsencode(path)), "hofem_solver_tune_save")
+
+
+def hofem_solver_tune_load(solver, path, mode, nrhs=1):
+    n = ctypes.c_int()
+    _check(_lib.hofem_solver_tune_load(solver, os.fsencode(path), MODES[mode], int(nrhs),
+                                       ctypes.byref(n)), "hofem_solver_tune_load")
+    return n.value
+
+
+def hofem_solver_tune_reset(solver):
+    _check(_lib.hofem_solver_tune_reset(solver), "hofem_solver_tune_reset")
+
+
+def hofem_kernel_hash():
+    return _lib.hofem_kernel_hash().decode()
+
+
 # ---- convenience wrappers -------------------------------------------------
 
 class Plan1D:
@@ -622,6 +686,24 @@ class Solver:
                               dtype=torch.float64, device=b_ext.device)
         hofem_dirichlet_rhs(self.handle, b_ext, f, out, nrhs, stream)
         return out
+
+    def autotune(self, mode="fp64", nrhs=1, reps=3, cache=None, f=None, u=None, stream=None):
+        """Tunes the passes' launch shapes for `mode` on synthetic data (or f, u);
+        with `cache`, shapes found there are applied and fresh results saved."""
+        import torch
+        if cache is not None and hofem_solver_tune_load(self.handle, cache, mode, nrhs) > 0:
+            return None
+        dt = torch.float32 if mode == "fp32" else torch.float64
+        if f is None:
+            g = torch.Generator(device="cuda").manual_seed(0)
+            f = torch.rand(nrhs * self.size, dtype=dt, device="cuda", generator=g) * 2 - 1
+        if u is None:
+            u = torch.empty_like(f)
+        ws = self.workspace(mode, nrhs, f.device) if mode == "fp32_ir" else None
+        rep = hofem_solver_autotune(self.handle, mode, f, u, nrhs, ws, reps, stream)
+        if cache is not None:
+            hofem_solver_tune_save(self.handle, cache)
+        return rep
 
     def set_timing(self, enable=True):
         hofem_solver_set_timing(self.handle, enable)

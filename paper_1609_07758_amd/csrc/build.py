@@ -30,6 +30,16 @@ def _run(cmd):
     subprocess.run(cmd, check=True)
 
 
+def kernel_hash():
+    """Hash of the line-pass sources (keys the autotuner's cache)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("linepass.h", "linepass.hip", "linepass_dispatch.hip", "kernels.h"):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def _jobs():
     """(command, object) for every translation unit; the line passes are
     compiled once per element order."""
@@ -43,7 +53,8 @@ def _jobs():
     for src in ("linepass_dispatch.hip", "operator.hip", "pcg.hip", "capi.hip", "batch.hip",
                 "timestep.hip", "banded.hip"):
         o = os.path.join(OUT_DIR, src.replace(".hip", ".o"))
-        jobs.append(([HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", o], o))
+        extra = [f'-DHOFEM_KERNEL_HASH="{kernel_hash()}"'] if src == "capi.hip" else []
+        jobs.append(([HIPCC] + HIP_FLAGS + extra + ["-c", os.path.join(CSRC, src), "-o", o], o))
     return jobs
 
 

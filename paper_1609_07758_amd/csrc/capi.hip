@@ -12,7 +12,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -110,6 +114,8 @@ struct hofem_solver_s {
   bool timing = false;
   std::vector<hipEvent_t> event_pool;
   std::vector<TimedLaunch> records;
+  // launch shapes chosen by the autotuner (or forced), per (kind, axis, fp64)
+  std::vector<hofem_tune_entry> tune;
 };
 
 namespace {
@@ -195,6 +201,13 @@ int run_list(hofem_solver_s* S, const std::vector<PassSpec>& list, bool f64, con
     else dt = dt_mid;
     PassArgs a = make_args(S, list[i].axis, list[i].kind, f64, in, out, nrhs);
     if (a.nlines == 0) continue;
+    const int tkind = list[i].kind == PASS_INV_ACC ? PASS_INV : list[i].kind;
+    for (const hofem_tune_entry& t : S->tune) {
+      if (t.kind == tkind && t.axis == list[i].axis && t.fp64 == (f64 ? 1 : 0)) {
+        a.cb_req = t.cb;
+        a.threads_req = t.threads;
+      }
+    }
     if (list[i].il_in || list[i].il_out) {
       const long long rows = ((long long)S->ax[0].m * nrhs) & ~1LL;
       if (list[i].il_in) a.ilv_in = rows;
@@ -1013,6 +1026,237 @@ int hofem_apply_mass(hofem_solver S, const double* g_dev, double* out_dev, int n
                      size_t ws_bytes, void* stream) {
   return apply_op(S, g_dev, out_dev, nrhs, ws_dev, ws_bytes, stream, true);
 }
+
+}  // extern "C"
+
+// ---- autotuner of the line passes' launch shapes ----------------------------
+namespace {
+
+#ifndef HOFEM_KERNEL_HASH
+#define HOFEM_KERNEL_HASH "unhashed"
+#endif
+
+struct PassKey {
+  int kind, axis, fp64;
+};
+
+// The distinct (kind, axis, precision) passes of a mode's solve.
+std::vector<PassKey> mode_passes(const hofem_solver_s* S, int mode, int nrhs) {
+  std::vector<PassKey> keys;
+  const bool f64 = mode == HOFEM_MODE_FP64;
+  for (const PassSpec& p : solve_list(S, f64, nrhs)) {
+    const PassKey k{p.kind == PASS_INV_ACC ? PASS_INV : p.kind, p.axis, f64 ? 1 : 0};
+    bool seen = false;
+    for (const PassKey& q : keys) seen = seen || (q.kind == k.kind && q.axis == k.axis && q.fp64 == k.fp64);
+    if (!seen) keys.push_back(k);
+  }
+  return keys;
+}
+
+long long pass_lines(const hofem_solver_s* S, int axis, int nrhs) {
+  long long others = 1;
+  for (int i = 0; i < S->N; ++i)
+    if (i != axis) others *= S->ax[i].m;
+  return others * nrhs;
+}
+
+void set_shape(hofem_solver_s* S, const PassKey& k, int cb, int threads, long long nlines = 0) {
+  for (auto it = S->tune.begin(); it != S->tune.end(); ++it) {
+    if (it->kind == k.kind && it->axis == k.axis && it->fp64 == k.fp64) {
+      S->tune.erase(it);
+      break;
+    }
+  }
+  if (cb > 0) S->tune.push_back(hofem_tune_entry{k.kind, k.axis, k.fp64, cb, threads, nlines, 0.0, 0.0});
+}
+
+}  // namespace
+
+extern "C" {
+
+int hofem_pass_shape_candidates(hofem_solver S, int kind, int axis, int fp64, int nrhs,
+                                int* cb_host, int* threads_host, int max_entries, int* count) {
+  if (!S || !count || axis < 0 || axis >= S->N || nrhs < 1 || max_entries < 0) return HOFEM_EINVAL;
+  if (kind != PASS_FWD && kind != PASS_INV && kind != PASS_FUSED) return HOFEM_EINVAL;
+  if (max_entries > 0 && (!cb_host || !threads_host)) return HOFEM_EINVAL;
+  const DevAxis& X = S->ax[axis];
+  const bool rows = axis == S->N - 1;
+  *count = pass_shape_candidates(X.n, X.K, fp64 != 0, pass_lines(S, axis, nrhs),
+                                 kind == PASS_INV && fp64 && rows, cb_host, threads_host,
+                                 max_entries);
+  return HOFEM_OK;
+}
+
+int hofem_pass_set_shape(hofem_solver S, int kind, int axis, int fp64, int cb, int threads) {
+  if (!S || axis < 0 || axis >= S->N || cb < 0) return HOFEM_EINVAL;
+  if (kind != PASS_FWD && kind != PASS_INV && kind != PASS_FUSED) return HOFEM_EINVAL;
+  if (cb > 0 && threads != 256 && threads != 512) return HOFEM_EINVAL;
+  set_shape(S, PassKey{kind, axis, fp64 ? 1 : 0}, cb, threads);
+  return HOFEM_OK;
+}
+
+int hofem_solver_autotune(hofem_solver S, int mode, const void* f_dev, void* u_dev, int nrhs,
+                          void* ws_dev, size_t ws_bytes, int reps, void* stream,
+                          hofem_tune_entry* out_host, int max_entries, int* count) {
+  if (!S || !f_dev || !u_dev || nrhs < 1 || reps < 1 || !count || max_entries < 0) return HOFEM_EINVAL;
+  if (mode != HOFEM_MODE_FP64 && mode != HOFEM_MODE_FP32 && mode != HOFEM_MODE_FP32_IR) return HOFEM_EINVAL;
+  if (mode == HOFEM_MODE_FP32_IR && f_dev == u_dev) return HOFEM_EINVAL;
+  if (max_entries > 0 && !out_host) return HOFEM_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return HOFEM_EHIP;
+  }
+  const bool timing = S->timing;
+  S->timing = false;
+  // one solve of the mode (one refinement step for FP32_IR), ms per solve;
+  // < 0 when the shape cannot run
+  auto measure = [&]() -> double {
+    auto one = [&]() {
+      return hofem_solve(S, mode, f_dev, u_dev, nrhs, ws_dev, ws_bytes, 1, 0.0, st, nullptr);
+    };
+    if (one() != HOFEM_OK) return -1.0;
+    if (hipEventRecord(e0, st) != hipSuccess) return -1.0;
+    for (int r = 0; r < reps; ++r)
+      if (one() != HOFEM_OK) return -1.0;
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return -1.0;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.0;
+    return ms / reps;
+  };
+  int rc = HOFEM_OK;
+  std::vector<hofem_tune_entry> done;
+  for (const PassKey& k : mode_passes(S, mode, nrhs)) {
+    set_shape(S, k, 0, 0);
+    const double t_def = measure();
+    if (t_def < 0) {
+      rc = HOFEM_EHIP;
+      break;
+    }
+    int cand_cb[64], cand_thr[64];
+    int nc = 0;
+    hofem_pass_shape_candidates(S, k.kind, k.axis, k.fp64, nrhs, cand_cb, cand_thr, 64, &nc);
+    int best_cb = 0, best_thr = 0;
+    double best = t_def;
+    for (int c = 1; c < nc; ++c) {       // candidate 0 is the default
+      set_shape(S, k, cand_cb[c], cand_thr[c]);
+      const double t = measure();
+      (void)hipGetLastError();
+      if (t >= 0 && t < best) {
+        best = t;
+        best_cb = cand_cb[c];
+        best_thr = cand_thr[c];
+      }
+    }
+    const long long nl = pass_lines(S, k.axis, nrhs);
+    set_shape(S, k, best_cb, best_thr, nl);
+    if (best_cb == 0) {
+      // the default won: record it as such
+      best_cb = cand_cb[0];
+      best_thr = cand_thr[0];
+    }
+    done.push_back(hofem_tune_entry{k.kind, k.axis, k.fp64, best_cb, best_thr, nl, t_def, best});
+  }
+  S->timing = timing;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != HOFEM_OK) return rc;
+  const int n = std::min<int>((int)done.size(), max_entries);
+  for (int i = 0; i < n; ++i) out_host[i] = done[i];
+  *count = (int)done.size();
+  return HOFEM_OK;
+}
+
+// Tuning cache on disk: one text line per tuned pass,
+//   <kernel hash> <n> <K> <fp64> <kind> <rows> <nlines> <cb> <threads> <ms default> <ms tuned>
+// (rows: the pass runs along the contiguous axis).  A shape applies to a
+// pass of the same kernels, order, K, precision, kind, stride and line count.
+int hofem_solver_tune_save(hofem_solver S, const char* path) {
+  if (!S || !path) return HOFEM_EINVAL;
+  std::vector<std::string> lines;
+  auto key_of = [](const std::string& l) {
+    std::istringstream is(l);
+    std::string k, w;
+    for (int i = 0; i < 7 && (is >> w); ++i) k += w + " ";
+    return k;
+  };
+  std::vector<std::string> fresh;
+  for (const hofem_tune_entry& t : S->tune) {
+    if (t.nlines <= 0) continue;   // forced shapes are not cached
+    const DevAxis& X = S->ax[t.axis];
+    std::ostringstream os;
+    os << HOFEM_KERNEL_HASH << " " << X.n << " " << X.K << " " << t.fp64 << " " << t.kind << " "
+       << (t.axis == S->N - 1 ? 1 : 0) << " " << t.nlines << " " << t.cb << " " << t.threads << " "
+       << t.ms_default << " " << t.ms_tuned;
+    fresh.push_back(os.str());
+  }
+  {
+    std::ifstream in(path);
+    std::string l;
+    while (std::getline(in, l)) {
+      if (l.empty()) continue;
+      bool replaced = false;
+      for (const std::string& f : fresh) replaced = replaced || key_of(f) == key_of(l);
+      if (!replaced) lines.push_back(l);
+    }
+  }
+  for (const std::string& f : fresh) lines.push_back(f);
+  const std::string tmp = std::string(path) + ".tmp";
+  {
+    std::ofstream out(tmp, std::ios::trunc);
+    if (!out) return HOFEM_EINVAL;
+    for (const std::string& l : lines) out << l << "\n";
+    if (!out) return HOFEM_EINVAL;
+  }
+  if (std::rename(tmp.c_str(), path) != 0) return HOFEM_EINVAL;
+  return HOFEM_OK;
+}
+
+int hofem_solver_tune_load(hofem_solver S, const char* path, int mode, int nrhs, int* applied) {
+  if (!S || !path || nrhs < 1 || !applied) return HOFEM_EINVAL;
+  if (mode != HOFEM_MODE_FP64 && mode != HOFEM_MODE_FP32 && mode != HOFEM_MODE_FP32_IR) return HOFEM_EINVAL;
+  *applied = 0;
+  std::ifstream in(path);
+  if (!in) return HOFEM_OK;   // no cache yet
+  struct Row {
+    std::string hash;
+    int n, K, fp64, kind, rows;
+    long long nlines;
+    int cb, threads;
+  };
+  std::vector<Row> rows;
+  std::string l;
+  while (std::getline(in, l)) {
+    std::istringstream is(l);
+    Row r;
+    if (is >> r.hash >> r.n >> r.K >> r.fp64 >> r.kind >> r.rows >> r.nlines >> r.cb >> r.threads)
+      rows.push_back(r);
+  }
+  for (const PassKey& k : mode_passes(S, mode, nrhs)) {
+    const DevAxis& X = S->ax[k.axis];
+    const long long nl = pass_lines(S, k.axis, nrhs);
+    const int isrow = k.axis == S->N - 1 ? 1 : 0;
+    for (const Row& r : rows) {
+      if (r.hash == HOFEM_KERNEL_HASH && r.n == X.n && r.K == X.K && r.fp64 == k.fp64 &&
+          r.kind == k.kind && r.rows == isrow && r.nlines == nl) {
+        set_shape(S, k, r.cb, r.threads, nl);
+        ++*applied;
+        break;
+      }
+    }
+  }
+  return HOFEM_OK;
+}
+
+int hofem_solver_tune_reset(hofem_solver S) {
+  if (!S) return HOFEM_EINVAL;
+  S->tune.clear();
+  return HOFEM_OK;
+}
+
+const char* hofem_kernel_hash(void) { return HOFEM_KERNEL_HASH; }
 
 }  // extern "C"
 

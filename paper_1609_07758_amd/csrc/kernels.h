@@ -46,6 +46,10 @@ struct PassArgs {
   long long inner;     // stride of the axis (product of the later extents)
   long long nlines;    // number of lines (total elements / m)
   int cb;              // lines per workgroup (set by the launcher)
+  // requested launch shape (the autotuner's candidates): lines per
+  // workgroup and workgroup size, 0 = the default of shape_for; a request
+  // the kernel cannot run is refused with hipErrorInvalidValue
+  int cb_req, threads_req;
   // Row-pair interleaved intermediate of a 2D solve: the first ilv rows of
   // the grid (an even count; rows of all right-hand sides in sequence) are
   // stored in pairs, row 2g + h of column t at 2g * M1 + 2t + h, the rest
@@ -90,6 +94,10 @@ hipError_t launch_pass(int kind, int dt, const PassArgs& a, hipStream_t s);
 // Lines per workgroup of a pass along a contiguous axis of order n with K
 // elements and nlines lines.
 int pass_lines_per_workgroup(int n, int K, bool f64, long long nlines);
+// Launch shapes a pass of order n, K can run with (lines per workgroup,
+// workgroup size), the default first; at most `max` of them.
+int pass_shape_candidates(int n, int K, bool f64, long long nlines, bool one_line, int* cb,
+                          int* threads, int max);
 
 // FP64 matrix-free operator r = f - L u (f may be NULL: r = L u), N = 1..3.
 struct OpArgs {

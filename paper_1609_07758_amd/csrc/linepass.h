@@ -1531,11 +1531,51 @@ inline Shape shape_for(int n, int K, size_t cplx_bytes, long long nlines, bool o
   return s;
 }
 
+// A requested shape (cb lines per workgroup of `threads` lanes): the
+// layout is fixed by (n, K); the padded layout runs every transform task in
+// one round, so cb pairs of tasks must fit the workgroup's waves; the tight
+// layout holds at most kTight lines.  False when the kernel cannot run it.
+inline bool shape_request(int n, int K, size_t cplx_bytes, long long nlines, int cb, int threads,
+                          Shape* out) {
+  if (threads != 256 && threads != 512) return false;
+  if (cb < 1 || (cb & (cb - 1)) || cb > kMaxCB) return false;
+  const int NP = (n + 1) / 2;
+  const bool f64 = cplx_bytes == 16;
+  const int rmax = (f64 && K <= 512) ? 8 : 16;
+  const int R = K < rmax ? K : rmax;
+  const int TPW = 64 / (K / R);
+  Shape s;
+  s.threads = threads;
+  s.cb = cb;
+  if (tight_layout(n, K, (int)cplx_bytes)) {
+    if (cb > kTight) return false;
+    // FP32 tight passes sum S0 in a separate phase, one wave per (line,
+    // component), each wave keeping at most two sums
+    if (!f64 && n > 1 && cb * (n - 1) > 2 * (threads / 64)) return false;
+    s.tight = 1;
+    s.lds = (size_t)cb * NP * K * cplx_bytes;
+  } else {
+    if (cb * NP > (threads / 64) * TPW) return false;
+    s.tight = 0;
+    const size_t per_line = ((size_t)NP * K + 1) * cplx_bytes;
+    s.lds = (size_t)cb * per_line + (size_t)cb * 16 + (size_t)cb * 8 * (cplx_bytes / 2);
+  }
+  if (s.lds > 160 * 1024) return false;
+  if ((long long)cb > 2 * nlines && cb > 1) return false;   // mostly idle workgroups
+  *out = s;
+  return true;
+}
+
 template <typename T, int N, int LOG2K, int MODE, typename TIN, typename TOUT>
 hipError_t launch_k(const PassArgs& a0, hipStream_t s) {
   constexpr bool kInv = MODE == PASS_INV || MODE == PASS_INV_ACC;
-  const Shape sh = shape_for(N, 1 << LOG2K, sizeof(cx<T>), a0.nlines,
-                             kInv && sizeof(T) == 8 && a0.inner == 1);
+  Shape sh = shape_for(N, 1 << LOG2K, sizeof(cx<T>), a0.nlines,
+                       kInv && sizeof(T) == 8 && a0.inner == 1);
+  if (a0.cb_req > 0 || a0.threads_req > 0) {
+    if (!shape_request(N, 1 << LOG2K, sizeof(cx<T>), a0.nlines, a0.cb_req > 0 ? a0.cb_req : sh.cb,
+                       a0.threads_req > 0 ? a0.threads_req : sh.threads, &sh))
+      return hipErrorInvalidValue;
+  }
   if (a0.tab.n != N || a0.tab.K != (1 << LOG2K)) return hipErrorInvalidValue;
   if (a0.ilv_in > 0 || a0.ilv_out > 0) {
     // the row-pair interleaved forms this kernel implements
