@@ -198,6 +198,15 @@ int hofem_solve(hofem_solver solver, int mode, const void* f_dev, void* u_dev, i
                 void* ws_dev, size_t ws_bytes, int max_iter, double tol, void* stream,
                 hofem_info* info);
 
+/* With enable != 0, hofem_solve calls that do not synchronise (modes FP64,
+ * FP32, FP64_B, and FP32_IR with tol <= 0; info NULL; a non-NULL stream)
+ * run from a HIP graph: the first call of each mode runs eagerly, the next
+ * one captures the whole solve (every pass and refinement step) and later
+ * calls with the same mode, buffers, nrhs and max_iter replay it with one
+ * graph launch.  Results do not depend on the setting.  A solve captured
+ * into the graph records no timing events.  Off by default. */
+int hofem_solver_set_graph(hofem_solver solver, int enable);
+
 /* Direct F_n-transforms along every axis (step (2) of algorithm (a)):
  * out = coefficients w_{k l} of eq. (decomp phi 2) of C^-1 in, in coefficient
  * order per axis (see hofem_plan1d_table).  mode FP64 (double) or FP32

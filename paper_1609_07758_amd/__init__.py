@@ -106,6 +106,7 @@ SIGNATURES = {
     "hofem_apply_coef_operator": (_c_int, [_vp, ctypes.POINTER(hofem_coef), _vp, _vp, _c_int, _vp,
                                            _c_size, _vp]),
     "hofem_solver_set_timing": (_c_int, [_vp, _c_int]),
+    "hofem_solver_set_graph": (_c_int, [_vp, _c_int]),
     "hofem_solver_pass_times": (_c_int, [_vp, ctypes.POINTER(hofem_pass_time), _c_int,
                                          ctypes.POINTER(_c_int)]),
     "hofem_pass_shape_candidates": (_c_int, [_vp, _c_int, _c_int, _c_int, _c_int,
@@ -707,6 +708,10 @@ class Solver:
 
     def set_timing(self, enable=True):
         hofem_solver_set_timing(self.handle, enable)
+
+    def set_graph(self, enable=True):
+        """Replay non-synchronising solves from a HIP graph (captured on the second call)."""
+        _check(_lib.hofem_solver_set_graph(self.handle, 1 if enable else 0), "hofem_solver_set_graph")
 
     def pass_times(self):
         return hofem_solver_pass_times(self.handle)

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -116,6 +117,16 @@ struct hofem_solver_s {
   std::vector<TimedLaunch> records;
   // launch shapes chosen by the autotuner (or forced), per (kind, axis, fp64)
   std::vector<hofem_tune_entry> tune;
+  // HIP-graph replay of whole solves (hofem_solver_set_graph): one graph for
+  // the last (mode, buffers, nrhs, steps); modes run eagerly once first
+  bool use_graph = false;
+  bool capturing = false;
+  bool warm[8] = {false, false, false, false, false, false, false, false};
+  hipGraphExec_t exec = nullptr;
+  int g_mode = -1, g_nrhs = 0, g_iter = -1;
+  const void* g_f = nullptr;
+  void* g_u = nullptr;
+  void* g_ws = nullptr;
 };
 
 namespace {
@@ -130,7 +141,7 @@ struct LaunchTimer {
   bool on = false;
   LaunchTimer(hofem_solver_s* s, hipStream_t stream, int kind, int axis, int fp64, double bytes)
       : S(s), st(stream) {
-    if (g_no_events || !S->timing || S->records.size() >= kMaxRecords) return;
+    if (g_no_events || S->capturing || !S->timing || S->records.size() >= kMaxRecords) return;
     const size_t need = 2 * (S->records.size() + 1);
     while (S->event_pool.size() < need) {
       hipEvent_t e;
@@ -389,7 +400,7 @@ size_t pcg_bytes(const hofem_solver_s* S, const hofem_coef* c) {
   size_t b = 4 * al(n * sizeof(double)) + al(n * sizeof(float));
   if (c && c->kind != 0) b += al(varop_elem_bytes(make_varop(S, c, nullptr, nullptr, nullptr, 1)));
   else b += op_elem_bytes(S);
-  b += al(3 * kPcgParts * sizeof(double)) + al(16 * sizeof(double));   // partial triples
+  b += al(3 * kPcgParts * sizeof(double)) + al(64 * sizeof(double));   // partials, scalars
   return b;
 }
 
@@ -454,14 +465,26 @@ int pcg_run(hofem_solver_s* S, const hofem_coef* c, const PcgWs& w, const double
   HIPCHK(hipMemcpyAsync(w.p, w.z, n * sizeof(double), hipMemcpyDeviceToDevice, st));
   HIPCHK(launch_dot2(w.r, w.z, w.r, n, w.partial, np, sc + 2, st));   // rz, (rr -> sc[3])
   HIPCHK(launch_dot2(f, f, nullptr, n, w.partial, np, sc + 9, st));    // ff
-  double h[16];
-  HIPCHK(hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, st));
+  HIPCHK(launch_cg_init(sc, rtol, utol, st));
+  double h[64];
+  HIPCHK(hipMemcpyAsync(h, sc, 16 * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   const double ff = h[9] > 0 ? h[9] : 1.0;
   *rel_res = std::sqrt(h[3] / ff);
   *rel_upd = 0.0;
   *iters = 0;
   *converged = (rtol > 0 && *rel_res <= rtol);
+  // The device records the first step that meets the tolerance and freezes
+  // the iterate from then on; the host looks only at predicted steps (the
+  // criterion falls about geometrically), at most 8 steps apart.
+  auto crit = [&](const double* hs) {   // criterion value of a history slot and its target
+    return rtol > 0 ? hs[0] : (hs[1] > 0 ? hs[2] * hs[2] * hs[3] / hs[1] : 0.0);
+  };
+  const double target = rtol > 0 ? rtol * rtol * ff : utol * utol;
+  double prev = rtol > 0 ? h[3] : -1.0;
+  int next_check = std::min(max_iter, 1);
+  auto t_look = std::chrono::steady_clock::now();
+  int it_look = 0;
   for (int it = 1; it <= max_iter && !*converged; ++it) {
     if ((rc = pcg_apply(S, c, w, w.p, nullptr, w.q, st)) != HOFEM_OK) return rc;   // q = A p
     HIPCHK(launch_dot2(w.p, w.q, w.p, n, w.partial, np, sc + 3, st));              // pq, pp
@@ -472,14 +495,39 @@ int pcg_run(hofem_solver_s* S, const hofem_coef* c, const PcgWs& w, const double
       HIPCHK(launch_cg_update(x, w.r, w.p, w.q, w.z, n, sc, w.partial, np, sc + 7, sc + 10, st));
       tm.done();
     }
-    HIPCHK(hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    *iters = it;
-    *rel_res = std::sqrt(h[7] / ff);
-    *rel_upd = h[8] > 0 ? std::fabs(h[0]) * std::sqrt(h[4] / h[8]) : 0.0;
-    if ((rtol > 0 && *rel_res <= rtol) || (utol > 0 && *rel_upd <= utol)) {
-      *converged = true;
-      break;
+    HIPCHK(launch_cg_record(sc, st));
+    if (it == next_check || it == max_iter) {
+      HIPCHK(hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      const int conv = (int)h[16];
+      const int at = conv > 0 ? conv : it;
+      const double* hs = h + 32 + 4 * ((at - 1) & 7);
+      *iters = at;
+      *rel_res = std::sqrt(hs[0] / ff);
+      *rel_upd = hs[1] > 0 ? std::fabs(hs[2]) * std::sqrt(hs[3] / hs[1]) : 0.0;
+      if (conv > 0) {
+        *converged = true;
+        break;
+      }
+      // next look: a look costs one host round trip (tens of microseconds),
+      // a step taken after convergence costs a step; where steps are cheap,
+      // look half way to where the criterion is predicted to reach its target
+      // (geometric extrapolation from the last two steps), otherwise after
+      // every step
+      const auto t_now = std::chrono::steady_clock::now();
+      const double step_ms =
+          std::chrono::duration<double, std::milli>(t_now - t_look).count() / (it - it_look);
+      t_look = t_now;
+      it_look = it;
+      const double now = crit(hs);
+      const double before = it >= 2 ? crit(h + 32 + 4 * ((it - 2) & 7)) : prev;
+      int steps = 1;
+      if (step_ms < 0.25 && before > 0 && now > 0 && now < before && target > 0 && now > target) {
+        const double need = std::log(target / now) / std::log(now / before);
+        steps = std::min((int)std::floor(need / 2.0), it);
+      }
+      next_check = std::min(max_iter, it + std::max(1, std::min(8, steps)));
+      prev = now;
     }
     if (it == max_iter) break;
     if ((rc = precond(w.r, w.z)) != HOFEM_OK) return rc;                           // z = S32 r
@@ -723,8 +771,19 @@ int hofem_solver_create(int N, const hofem_plan1d* plans, const double* X, doubl
   return HOFEM_OK;
 }
 
+int hofem_solver_set_graph(hofem_solver S, int enable) {
+  if (!S) return HOFEM_EINVAL;
+  S->use_graph = enable != 0;
+  if (!S->use_graph && S->exec) {
+    (void)hipGraphExecDestroy(S->exec);
+    S->exec = nullptr;
+  }
+  return HOFEM_OK;
+}
+
 void hofem_solver_destroy(hofem_solver solver) {
   if (!solver) return;
+  if (solver->exec) (void)hipGraphExecDestroy(solver->exec);
   for (hipEvent_t e : solver->event_pool) (void)hipEventDestroy(e);
   delete solver;
 }
@@ -782,6 +841,55 @@ int hofem_solve(hofem_solver S, int mode, const void* f_dev, void* u_dev, int nr
                 size_t ws_bytes, int max_iter, double tol, void* stream, hofem_info* info) {
   if (!S || !f_dev || !u_dev || nrhs < 1) return HOFEM_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
+  // graph replay: solves without host synchronisation, on a stream that can
+  // be captured
+  const bool graphable = mode == HOFEM_MODE_FP64 || mode == HOFEM_MODE_FP32 ||
+                         mode == HOFEM_MODE_FP64_B || (mode == HOFEM_MODE_FP32_IR && tol <= 0);
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (S->use_graph && st != nullptr && hipStreamIsCapturing(st, &cap) != hipSuccess) return HOFEM_EHIP;
+  if (S->use_graph && !S->capturing && graphable && !info && st != nullptr && mode >= 0 &&
+      mode < 8 && max_iter >= 0 && cap == hipStreamCaptureStatusNone) {
+    if (!S->warm[mode]) {
+      // eager first: one-time kernel set-up must not happen inside a capture
+      S->capturing = true;   // (no timing events and no nested graph)
+      const int rc = hofem_solve(S, mode, f_dev, u_dev, nrhs, ws_dev, ws_bytes, max_iter, tol,
+                                 stream, nullptr);
+      S->capturing = false;
+      if (rc == HOFEM_OK) S->warm[mode] = true;
+      return rc;
+    }
+    if (!(S->exec && S->g_mode == mode && S->g_f == f_dev && S->g_u == u_dev && S->g_ws == ws_dev &&
+          S->g_nrhs == nrhs && S->g_iter == max_iter)) {
+      if (S->exec) (void)hipGraphExecDestroy(S->exec);
+      S->exec = nullptr;
+      HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      S->capturing = true;
+      const int rc = hofem_solve(S, mode, f_dev, u_dev, nrhs, ws_dev, ws_bytes, max_iter, tol,
+                                 stream, nullptr);
+      S->capturing = false;
+      hipGraph_t graph = nullptr;
+      const hipError_t e = hipStreamEndCapture(st, &graph);
+      if (rc != HOFEM_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+      }
+      if (e != hipSuccess) return hip_fail(e);
+      const hipError_t ei = hipGraphInstantiate(&S->exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ei != hipSuccess) {
+        S->exec = nullptr;
+        return hip_fail(ei);
+      }
+      S->g_mode = mode;
+      S->g_f = f_dev;
+      S->g_u = u_dev;
+      S->g_ws = ws_dev;
+      S->g_nrhs = nrhs;
+      S->g_iter = max_iter;
+    }
+    HIPCHK(hipGraphLaunch(S->exec, st));
+    return HOFEM_OK;
+  }
   if (mode == HOFEM_MODE_FP64_B) {
     const int rc = solve_alg_b(S, static_cast<const double*>(f_dev), static_cast<double*>(u_dev),
                                nrhs, st);
@@ -1061,6 +1169,10 @@ long long pass_lines(const hofem_solver_s* S, int axis, int nrhs) {
 }
 
 void set_shape(hofem_solver_s* S, const PassKey& k, int cb, int threads, long long nlines = 0) {
+  if (S->exec) {   // a captured solve keeps its launch shapes: capture again
+    (void)hipGraphExecDestroy(S->exec);
+    S->exec = nullptr;
+  }
   for (auto it = S->tune.begin(); it != S->tune.end(); ++it) {
     if (it->kind == k.kind && it->axis == k.axis && it->fp64 == k.fp64) {
       S->tune.erase(it);
@@ -1253,6 +1365,10 @@ int hofem_solver_tune_load(hofem_solver S, const char* path, int mode, int nrhs,
 int hofem_solver_tune_reset(hofem_solver S) {
   if (!S) return HOFEM_EINVAL;
   S->tune.clear();
+  if (S->exec) {
+    (void)hipGraphExecDestroy(S->exec);
+    S->exec = nullptr;
+  }
   return HOFEM_OK;
 }
 

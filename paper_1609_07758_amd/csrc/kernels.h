@@ -192,5 +192,9 @@ hipError_t launch_cg_dir(double* p, const double* z, long long n, const double* 
 // scal[0] = scal[2] / scal[3] (op 0: alpha = rz / pq);
 // scal[1] = scal[5] / scal[2], scal[2] = scal[5] (op 1: beta, rz <- rz_new)
 hipError_t launch_scalar_op(double* scal, int op, hipStream_t s);
+// records a step's statistics and the first converged step (scal[16..19, 32..63])
+hipError_t launch_cg_record(double* scal, hipStream_t s);
+// sets the convergence thresholds (scal[16..19]) from ||f||^2 in scal[9]
+hipError_t launch_cg_init(double* scal, double rtol, double utol, hipStream_t s);
 
 }  // namespace hofem

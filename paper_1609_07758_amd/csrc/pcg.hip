@@ -114,14 +114,40 @@ __global__ void sum3_kernel(const double* partial, int np, double* out2, double*
   }
 }
 
+// Once the device has recorded convergence (scal[16] != 0) alpha and beta
+// are 0: the iterate and the residual stay at the converged step while the
+// host has not looked yet.
 __global__ void scalar_op_kernel(double* scal, int op) {
+  const bool frozen = scal[16] != 0.0;
   if (op == 0) {
-    scal[0] = scal[2] / scal[3];
+    scal[0] = (frozen || scal[3] == 0.0) ? 0.0 : scal[2] / scal[3];
   } else {
     // beta = r_new (z_new - z_old) / (r_old z_old): the flexible form, which
     // tolerates a preconditioner that is symmetric only up to FP32 rounding
-    scal[1] = (scal[5] - scal[10]) / scal[2];
+    scal[1] = (frozen || scal[2] == 0.0) ? 0.0 : (scal[5] - scal[10]) / scal[2];
     scal[2] = scal[5];
+  }
+}
+
+// After an update: the step's statistics go to history slot (it - 1) mod 8
+// (rr, xx, alpha, pp at scal[32 + 4 slot ..]) and the first step that meets
+// the tolerance is recorded in scal[16]: ||r||^2 <= scal[17] (relative
+// residual, when scal[17] >= 0) or alpha^2 pp <= scal[18] xx (relative
+// update, when scal[18] >= 0).  scal[19] counts the steps.
+__global__ void cg_record_kernel(double* scal) {
+  const double it = scal[19] + 1.0;
+  scal[19] = it;
+  const int slot = ((int)it - 1) & 7;
+  const double rr = scal[7], xx = scal[8], al = scal[0], pp = scal[4];
+  double* h = scal + 32 + 4 * slot;
+  h[0] = rr;
+  h[1] = xx;
+  h[2] = al;
+  h[3] = pp;
+  if (scal[16] == 0.0) {
+    const bool res_ok = scal[17] >= 0.0 && rr <= scal[17];
+    const bool upd_ok = scal[18] >= 0.0 && al * al * pp <= scal[18] * xx;
+    if (res_ok || upd_ok) scal[16] = it;
   }
 }
 
@@ -591,6 +617,26 @@ hipError_t launch_cg_update(double* x, double* r, const double* p, const double*
 
 hipError_t launch_scalar_op(double* scal, int op, hipStream_t s) {
   hipLaunchKernelGGL(scalar_op_kernel, dim3(1), dim3(1), 0, s, scal, op);
+  return hipGetLastError();
+}
+
+// Convergence thresholds from ||f||^2 = scal[9] (0 taken as 1); nothing
+// recorded yet.
+__global__ void cg_init_kernel(double* scal, double rtol, double utol) {
+  const double ff = scal[9] > 0.0 ? scal[9] : 1.0;
+  scal[16] = 0.0;
+  scal[17] = rtol > 0.0 ? rtol * rtol * ff : -1.0;
+  scal[18] = utol > 0.0 ? utol * utol : -1.0;
+  scal[19] = 0.0;
+}
+
+hipError_t launch_cg_init(double* scal, double rtol, double utol, hipStream_t s) {
+  hipLaunchKernelGGL(cg_init_kernel, dim3(1), dim3(1), 0, s, scal, rtol, utol);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_record(double* scal, hipStream_t s) {
+  hipLaunchKernelGGL(cg_record_kernel, dim3(1), dim3(1), 0, s, scal);
   return hipGetLastError();
 }
 

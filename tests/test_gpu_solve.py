@@ -323,3 +323,38 @@ def test_deterministic_fp64():
     a = host(S.solve(f))
     b = host(S.solve(f))
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32", "fp64_b", "fp32_ir"])
+def test_graph_replay_of_single_solves(mode):
+    # hofem_solver_set_graph: eager first call, captured second, replays
+    # after; every replay equals the eager result, with eager work and host
+    # synchronisation between replays, and reads the current right-hand side
+    orders, Ks, X = (9, 9), (64, 32), (1.0, 1.0)
+    S = H.Solver(orders, Ks, X, 0.0)
+    dt = torch.float32 if mode == "fp32" else torch.float64
+    f = gpu(workloads.uniform_rhs(S.shape, seed=41), dt)
+    ws = S.workspace(mode) if mode == "fp32_ir" else None
+    ref = S.solve(f, mode=mode, max_iter=3, tol=0.0, ws=ws)
+    torch.cuda.synchronize()
+    ref = ref.clone()
+    S.set_graph(True)
+    s = torch.cuda.Stream()
+    u = torch.empty_like(f)
+    with torch.cuda.stream(s):
+        for rep in range(4):
+            u.zero_()
+            S.solve(f, u, mode=mode, max_iter=3, tol=0.0, ws=ws, stream=s.cuda_stream)
+            s.synchronize()
+            assert torch.equal(u, ref), rep
+            tmp = torch.randn(1 << 18, device=DEV, dtype=torch.float64)
+            float(tmp.sum())
+        f2 = gpu(workloads.uniform_rhs(S.shape, seed=42), dt)
+        f.copy_(f2)
+        S.solve(f, u, mode=mode, max_iter=3, tol=0.0, ws=ws, stream=s.cuda_stream)
+        s.synchronize()
+    S.set_graph(False)
+    ref2 = S.solve(f2, mode=mode, max_iter=3, tol=0.0, ws=ws)
+    torch.cuda.synchronize()
+    assert torch.equal(u, ref2)
+    S.close()
