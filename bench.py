@@ -169,6 +169,41 @@ def bench_headline(args, torch, H, np, workloads, dev):
     passes_b = S.pass_times()
     S.set_timing(False)
 
+    log("large_2d: implicit heat steps and the Dirichlet lift")
+    # implicit time stepping (backward Euler, dt = 1e-3: alpha = 1000) and
+    # the boundary lift of Dirichlet data, at the same size
+    Sh = H.Solver(cfg["orders"], cfg["Ks"], cfg["X"], 1000.0)
+    Th = H.Stepper(Sh, "heat")
+    uh = f64.clone()
+    sh_stream = torch.cuda.Stream()
+    with torch.cuda.stream(sh_stream):
+        Th.run(uh, 2, f=f64, use_graph=True, stream=sh_stream.cuda_stream)
+        ms_heat = time_calls(torch, lambda: Th.run(uh, 10, f=f64, use_graph=True,
+                                                    stream=sh_stream.cuda_stream), 2, 1,
+                             sh_stream) / 10
+    torch.cuda.synchronize()
+    Th.close()
+    Sh.close()
+    bext = torch.rand(tuple(m + 2 for m in shp), dtype=torch.float64, device=dev)
+    lift = torch.empty_like(f64)
+    ms_lift = time_calls(torch, lambda: S.dirichlet_rhs(bext, f64, out=lift), args.steps,
+                         args.warmup)
+    del bext, lift, uh
+
+    log("large_2d: periodic axes")
+    # the same orders and meshes with both axes periodic (alpha = 1): Bloch
+    # waves, m = nK per axis
+    Sp = H.Solver(cfg["orders"], cfg["Ks"], cfg["X"], 1.0, bcs=("periodic", "periodic"))
+    fp = torch.rand(Sp.size, dtype=torch.float64, device=dev)
+    up = torch.empty_like(fp)
+    Sp.set_timing(True)
+    ms_per = time_calls(torch, lambda: Sp.solve(fp, up, mode="fp64"), args.steps, args.warmup)
+    passes_per = Sp.pass_times()
+    Sp.set_timing(False)
+    M_per = Sp.size
+    Sp.close()
+    del fp, up
+
     log("large_2d: autotuned launch shapes (FP64)")
     tune = S.autotune("fp64", nrhs=1, reps=3, f=f64, u=u64)
     ms64_tuned = time_calls(torch, lambda: S.solve(f64, u64, mode="fp64"), args.steps, args.warmup)
@@ -220,6 +255,15 @@ def bench_headline(args, torch, H, np, workloads, dev):
         "algorithm_b": {"unknowns_per_s": M / (ms_b * 1e-3), "ms_per_step": ms_b,
                         "passes": [dict(p, avg_ms=p["ms"] / p["launches"]) for p in passes_b]},
         "autotune_fp64": {"ms_default": ms64, "ms_tuned": ms64_tuned, "passes": tune},
+        "heat_steps": {"alpha": 1000.0, "ms_per_step": ms_heat,
+                       "unknowns_per_s": M / (ms_heat * 1e-3),
+                       "note": "backward Euler step: mass update + FP64 solve, HIP-graph replay"},
+        "dirichlet_lift": {"ms": ms_lift, "unknowns_per_s": M / (ms_lift * 1e-3)},
+        "periodic_fp64": {"unknowns": M_per, "alpha": 1.0, "ms_per_step": ms_per,
+                          "unknowns_per_s": M_per / (ms_per * 1e-3),
+                          "passes": [dict(p, avg_ms=p["ms"] / p["launches"],
+                                          gbs=p["bytes"] / (p["ms"] / p["launches"] * 1e-3) / 1e9)
+                                     for p in passes_per]},
         "config": {"workload": "large_2d", "N": 2, "order_n": cfg["orders"][0],
                    "K_per_axis": cfg["Ks"][0], "unknowns": M, "rhs": "uniform[-1,1) seed 0",
                    "alpha": cfg["alpha"]},

@@ -108,9 +108,30 @@ typedef struct {
  * otherwise.  A plan changes only in hofem_plan1d_upload; otherwise it is
  * read-only and may be shared between threads. */
 int hofem_plan1d_create(int n, int K, hofem_plan1d* out);
+
+/* Boundary condition of an axis: the Introduction notes that other standard
+ * conditions fit the method.  A periodic axis identifies x = 0 with x = X:
+ * its m = nK unknowns are, for cell j = 0..K-1, the mesh node j (q = n j) and
+ * the interior points s = 1..n-1 of element j+1 (q = n j + s).  The pencil is
+ * then block circulant; its eigenvectors are Bloch waves w_{k,l} e^{i 2 pi k j/K}
+ * with w_{k,l} (n complex values, w^H C_k w = 1) the eigenvectors of the n x n
+ * Hermitian pencil of wave number k = 0..K/2 (K - k gives the conjugates).
+ * Coefficients of a periodic axis are real, l-major: q = l K + t with t = 0
+ * for k = 0, t = 2k-1 and 2k for the real and imaginary parts of k = 1..K/2-1,
+ * t = K-1 for k = K/2; lambda_{k,l} is listed at every t of k.  Periodic axes
+ * run in HOFEM_MODE_FP64 only (hofem_solve, hofem_forward, hofem_inverse);
+ * every other entry point returns HOFEM_EUNSUPPORTED for a solver with a
+ * periodic axis.  An all-periodic solver needs alpha > 0 (the constants have
+ * lambda = 0): otherwise hofem_solver_create returns HOFEM_ENOTPOSDEF. */
+enum hofem_bc { HOFEM_BC_DIRICHLET = 0, HOFEM_BC_PERIODIC = 1 };
+
+/* hofem_plan1d_create with a boundary condition (enum hofem_bc; else
+ * HOFEM_EINVAL).  hofem_plan1d_create(n, K, out) is
+ * hofem_plan1d_create_bc(n, K, HOFEM_BC_DIRICHLET, out). */
+int hofem_plan1d_create_bc(int n, int K, int bc, hofem_plan1d* out);
 void hofem_plan1d_destroy(hofem_plan1d plan);
 
-/* Number of unknowns m = nK - 1 of the plan's axis. */
+/* Number of unknowns of the plan's axis: m = nK - 1 (Dirichlet), nK (periodic). */
 int hofem_plan1d_dim(hofem_plan1d plan, int* m);
 
 /* Host copies of the plan's tables, for inspection and tests.  `which`:
@@ -124,6 +145,11 @@ int hofem_plan1d_dim(hofem_plan1d plan, int* m);
  *   7  its weights w_q                                    (n+1 values)
  *   8  basis values e_r(x_q) at index q (n+1) + r         ((n+1)^2 values)
  *   9  basis derivatives e_r'(x_q) at index q (n+1) + r   ((n+1)^2 values)
+ *  10  periodic plans: Re w_{k,l,s} at index (k n + l) n + s, k = 0..K/2 ((K/2+1) n^2)
+ *  11  periodic plans: Im w_{k,l,s}, the same layout
+ * Tables 1 and 2 exist for Dirichlet plans only, 10 and 11 for periodic
+ * plans only (HOFEM_EINVAL otherwise); table 0 of a periodic plan holds its
+ * m = nK eigenvalues in the periodic coefficient order.
  * The coefficient index of a line is q = l-1 for k = 0 (l = 1..n-1) and
  * q = (n-1) + (l-1)(K-1) + (k-1) for k = 1..K-1 (l = 1..n): for each l the
  * wave numbers are consecutive.  `len` must equal the count; otherwise

@@ -35,6 +35,8 @@ What it computes, step by step (each module cites the passage it follows):
                 preconditioner); its iteration counts stand beside the GPU's.
 * ``timestep``  implicit time stepping (heat: backward Euler; wave: the
                 implicit three-level scheme), one solve per step.
+* ``periodic``  periodic axes: the assembled periodic pencil and a sparse
+                direct solve corrected with exactly evaluated residuals.
 
 Parity status: every function is pinned by a test in ``tests/`` against
 values the paper prints, closed forms, invariants or brute force.

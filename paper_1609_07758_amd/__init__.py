@@ -33,7 +33,9 @@ HOFEM_ENOMEM = -6
 HOFEM_ETOOBIG = -7
 
 MODES = {"fp64": 0, "fp32": 1, "fp32_ir": 2, "fp32_pcg": 3, "fp64_b": 4}
-TABLES = {"lam": 0, "p": 1, "inorm": 2, "E": 3, "A": 4, "C": 5, "gx": 6, "gw": 7, "B": 8, "D": 9}
+TABLES = {"lam": 0, "p": 1, "inorm": 2, "E": 3, "A": 4, "C": 5, "gx": 6, "gw": 7, "B": 8, "D": 9,
+          "wr": 10, "wi": 11}
+BCS = {"dirichlet": 0, "periodic": 1}
 
 # Names and signatures of every entry point of include/hofem.h.
 _c_int, _c_double, _c_size, _vp = ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p
@@ -69,6 +71,7 @@ class hofem_tune_entry(ctypes.Structure):
 
 SIGNATURES = {
     "hofem_plan1d_create": (_c_int, [_c_int, _c_int, ctypes.POINTER(_vp)]),
+    "hofem_plan1d_create_bc": (_c_int, [_c_int, _c_int, _c_int, ctypes.POINTER(_vp)]),
     "hofem_plan1d_destroy": (None, [_vp]),
     "hofem_plan1d_dim": (_c_int, [_vp, ctypes.POINTER(_c_int)]),
     "hofem_plan1d_table": (_c_int, [_vp, _c_int, ctypes.POINTER(_c_double), _c_size]),
@@ -170,6 +173,14 @@ def _stream(stream):
 def hofem_plan1d_create(n, K):
     h = ctypes.c_void_p()
     _check(_lib.hofem_plan1d_create(int(n), int(K), ctypes.byref(h)), "hofem_plan1d_create")
+    return h
+
+
+def hofem_plan1d_create_bc(n, K, bc):
+    h = ctypes.c_void_p()
+    b = BCS[bc] if isinstance(bc, str) else int(bc)
+    _check(_lib.hofem_plan1d_create_bc(int(n), int(K), b, ctypes.byref(h)),
+           "hofem_plan1d_create_bc")
     return h
 
 
@@ -534,11 +545,12 @@ def hofem_kernel_hash():
 # ---- convenience wrappers -------------------------------------------------
 
 class Plan1D:
-    """1D eigen data for order n and K elements (host, binary128 precompute)."""
+    """1D eigen data for order n and K elements (host, binary128 precompute);
+    bc "dirichlet" or "periodic"."""
 
-    def __init__(self, n, K):
-        self.n, self.K = int(n), int(K)
-        self.handle = hofem_plan1d_create(n, K)
+    def __init__(self, n, K, bc="dirichlet"):
+        self.n, self.K, self.bc = int(n), int(K), bc
+        self.handle = hofem_plan1d_create_bc(n, K, bc)
         self.m = hofem_plan1d_dim(self.handle)
 
     def upload(self, device="cuda"):
@@ -552,7 +564,8 @@ class Plan1D:
         n, K = self.n, self.K
         counts = {"lam": self.m, "p": (K - 1) * n * (n - 1), "inorm": (K - 1) * n,
                   "E": (n - 1) ** 2, "A": (n + 1) ** 2, "C": (n + 1) ** 2,
-                  "gx": n + 1, "gw": n + 1, "B": (n + 1) ** 2, "D": (n + 1) ** 2}
+                  "gx": n + 1, "gw": n + 1, "B": (n + 1) ** 2, "D": (n + 1) ** 2,
+                  "wr": (K // 2 + 1) * n * n, "wi": (K // 2 + 1) * n * n}
         return hofem_plan1d_table(self.handle, which, counts[which])
 
     def close(self):
@@ -570,19 +583,23 @@ class Plan1D:
 class Solver:
     """Solver of (sum_i 4 h_i^-2 A_i (x) C_others + alpha (x)C) v = f^h on a box."""
 
-    def __init__(self, orders, Ks, X, alpha=0.0):
+    def __init__(self, orders, Ks, X, alpha=0.0, bcs=None):
         self.orders = [int(n) for n in orders]
         self.Ks = [int(k) for k in Ks]
         self.X = [float(x) for x in X]
         self.alpha = float(alpha)
+        self.bcs = list(bcs) if bcs is not None else ["dirichlet"] * len(self.orders)
+        if len(self.bcs) != len(self.orders):
+            raise ValueError("one boundary condition per axis")
         self.handle = None
         plans = {}
-        for n, K in zip(self.orders, self.Ks):
-            if (n, K) not in plans:
-                plans[(n, K)] = Plan1D(n, K)
+        keys = list(zip(self.orders, self.Ks, self.bcs))
+        for key in keys:
+            if key not in plans:
+                plans[key] = Plan1D(*key)
         # the plans' device tables: caller-owned, alive as long as the solver
         self._tables = [p.upload() for p in plans.values()]
-        axis_plans = [plans[(n, K)] for n, K in zip(self.orders, self.Ks)]
+        axis_plans = [plans[key] for key in keys]
         self.shape = tuple(p.m for p in axis_plans)
         self.handle = hofem_solver_create([p.handle for p in axis_plans], self.X, self.alpha)
         for p in plans.values():

@@ -66,6 +66,7 @@ namespace {
   } while (0)
 
 struct DevAxis {
+  int bc = 0;                   // 0: Dirichlet, 1: periodic
   int n = 0, K = 0, m = 0;
   double X = 0, scale = 0;
   AxisTab t64{}, t32{};
@@ -228,7 +229,12 @@ int run_list(hofem_solver_s* S, const std::vector<PassSpec>& list, bool f64, con
     const double bytes = (double)S->per_rhs * nrhs * (in_bytes[dt] + out_bytes[dt]);
     LaunchTimer tm(S, st, list[i].kind == PASS_INV_ACC ? PASS_INV : list[i].kind, list[i].axis,
                    f64 ? 1 : 0, bytes);
-    HIPCHK(launch_pass(list[i].kind, dt, a, st));
+    if (S->ax[list[i].axis].bc == 1) {
+      if (dt != 0) return HOFEM_EUNSUPPORTED;   // periodic axes: FP64 passes only
+      HIPCHK(launch_periodic(list[i].kind, a, st));
+    } else {
+      HIPCHK(launch_pass(list[i].kind, dt, a, st));
+    }
     tm.done();
   }
   return HOFEM_OK;
@@ -246,7 +252,7 @@ std::vector<PassSpec> solve_list(const hofem_solver_s* S, bool f64, int nrhs) {
   for (int a = N - 1; a >= 1; --a) l.push_back({a, PASS_FWD});
   l.push_back({0, PASS_FUSED});
   for (int a = 1; a < N; ++a) l.push_back({a, PASS_INV});
-  if (N == 2 &&
+  if (N == 2 && S->ax[0].bc == 0 && S->ax[1].bc == 0 &&
       pass_lines_per_workgroup(S->ax[1].n, S->ax[1].K, f64, (long long)S->ax[0].m * nrhs) == 2) {
     l[0].il_out = true;
     l[1].il_in = l[1].il_out = true;
@@ -310,6 +316,14 @@ int solve_alg_b(hofem_solver_s* S, const double* f, double* u, int nrhs, hipStre
   }
   if (!inv.empty()) return run_list(S, inv, true, u, u, u, 0, 0, 0, 0, nrhs, st);
   return HOFEM_OK;
+}
+
+// Every axis Dirichlet (the operator, refinement, CG, algorithm (b), the
+// Dirichlet lift and time stepping are built for Dirichlet axes only).
+bool all_dirichlet(const hofem_solver_s* S) {
+  for (int i = 0; i < S->N; ++i)
+    if (S->ax[i].bc != 0) return false;
+  return true;
 }
 
 size_t ir_workspace(const hofem_solver_s* S, int nrhs) {
@@ -559,6 +573,28 @@ namespace {
 std::vector<unsigned char> pack_plan(const Plan1DData& d, PlanOff* off) {
   Packer pk;
   const int n = d.n, K = d.K;
+  if (d.bc == 1) {
+    // periodic: eigenvalues, Bloch eigenvectors (complex, FP64), twiddles,
+    // local and Gauss tables; the FP32 and Dirichlet-only slots point at the
+    // twiddles (no pass reads them)
+    std::vector<double> w(2 * d.wr.size());
+    for (size_t i = 0; i < d.wr.size(); ++i) {
+      w[2 * i] = d.wr[i];
+      w[2 * i + 1] = d.wi[i];
+    }
+    off->lam = pk.add_f64(d.lam);
+    off->blk64 = pk.add_f64(w);
+    off->tw64 = pk.add_f64(d.tw);
+    off->E64 = off->sn64 = off->blk32 = off->E32 = off->tw32 = off->sn32 = off->tw64;
+    off->A = pk.add_f64(d.A);
+    off->C = pk.add_f64(d.C);
+    off->B = pk.add_f64(d.B);
+    off->D = pk.add_f64(d.D);
+    off->Dh = pk.add_f64(d.Dh);
+    off->gw = pk.add_f64(d.gw);
+    pk.bytes.resize((pk.bytes.size() + 255) & ~size_t(255), 0);
+    return pk.bytes;
+  }
   auto blocked = [&](size_t ge) {
     const size_t NE = (size_t)n * (n - 1) + n, NEG = (NE + ge - 1) / ge;
     const size_t nblk = ((size_t)K - 1 + 63) / 64;
@@ -600,6 +636,7 @@ std::vector<unsigned char> pack_plan(const Plan1DData& d, PlanOff* off) {
 namespace hofem {
 
 size_t solver_unknowns(const hofem_solver_s* S) { return S->per_rhs; }
+bool solver_all_dirichlet(const hofem_solver_s* S) { return all_dirichlet(S); }
 double solver_alpha(const hofem_solver_s* S) { return S->alpha; }
 int solver_device(const hofem_solver_s* S) { return S->device; }
 size_t solver_op_elem_bytes(const hofem_solver_s* S) { return op_elem_bytes(S); }
@@ -645,11 +682,18 @@ const char* hofem_status_string(int status) {
 int hofem_last_hip_error(void) { return g_last_hip; }
 
 int hofem_plan1d_create(int n, int K, hofem_plan1d* out) {
+  return hofem_plan1d_create_bc(n, K, HOFEM_BC_DIRICHLET, out);
+}
+
+int hofem_plan1d_create_bc(int n, int K, int bc, hofem_plan1d* out) {
   if (!out) return HOFEM_EINVAL;
+  if (bc != HOFEM_BC_DIRICHLET && bc != HOFEM_BC_PERIODIC) return HOFEM_EINVAL;
   if (n < 1 || n > 9 || K < 2 || K > 1024 || (K & (K - 1)) != 0) return HOFEM_EUNSUPPORTED;
   hofem_plan1d p = new (std::nothrow) hofem_plan1d_s;
   if (!p) return HOFEM_ENOMEM;
-  if (plan1d_build(n, K, &p->d) != 0) {
+  const int rc = bc == HOFEM_BC_PERIODIC ? plan1d_build_periodic(n, K, &p->d)
+                                         : plan1d_build(n, K, &p->d);
+  if (rc != 0) {
     delete p;
     return HOFEM_EUNSUPPORTED;
   }
@@ -691,6 +735,8 @@ int hofem_plan1d_table(hofem_plan1d plan, int which, double* out_host, size_t le
   const int n = d.n, K = d.K;
   const std::vector<double>* v = nullptr;
   size_t count = 0;
+  const bool dirichlet_only = which == 1 || which == 2, periodic_only = which == 10 || which == 11;
+  if ((dirichlet_only && d.bc != 0) || (periodic_only && d.bc != 1)) return HOFEM_EINVAL;
   switch (which) {
     case 0: v = &d.lam; count = d.m; break;
     case 1: v = &d.p; count = (size_t)(K - 1) * n * (n - 1); break;
@@ -702,6 +748,8 @@ int hofem_plan1d_table(hofem_plan1d plan, int which, double* out_host, size_t le
     case 7: v = &d.gw; count = (size_t)(n + 1); break;
     case 8: v = &d.B; count = (size_t)(n + 1) * (n + 1); break;
     case 9: v = &d.D; count = (size_t)(n + 1) * (n + 1); break;
+    case 10: v = &d.wr; count = (size_t)(K / 2 + 1) * n * n; break;
+    case 11: v = &d.wi; count = (size_t)(K / 2 + 1) * n * n; break;
     default: return HOFEM_EINVAL;
   }
   if (len != count) return HOFEM_EINVAL;
@@ -746,6 +794,7 @@ int hofem_solver_create(int N, const hofem_plan1d* plans, const double* X, doubl
     const hofem_plan1d_s* P = plans[i];
     const Plan1DData& d = P->d;
     DevAxis& ax = S->ax[i];
+    ax.bc = d.bc;
     ax.n = d.n;
     ax.K = d.K;
     ax.m = d.m;
@@ -840,6 +889,7 @@ int hofem_solver_workspace_bytes(hofem_solver solver, int mode, int nrhs, size_t
 int hofem_solve(hofem_solver S, int mode, const void* f_dev, void* u_dev, int nrhs, void* ws_dev,
                 size_t ws_bytes, int max_iter, double tol, void* stream, hofem_info* info) {
   if (!S || !f_dev || !u_dev || nrhs < 1) return HOFEM_EINVAL;
+  if (mode != HOFEM_MODE_FP64 && !all_dirichlet(S)) return HOFEM_EUNSUPPORTED;
   hipStream_t st = static_cast<hipStream_t>(stream);
   // graph replay: solves without host synchronisation, on a stream that can
   // be captured
@@ -1011,6 +1061,7 @@ int hofem_solve(hofem_solver S, int mode, const void* f_dev, void* u_dev, int nr
 int hofem_forward(hofem_solver S, int mode, const void* in_dev, void* out_dev, int nrhs,
                   void* stream) {
   if (!S || !in_dev || !out_dev || nrhs < 1) return HOFEM_EINVAL;
+  if (mode != HOFEM_MODE_FP64 && !all_dirichlet(S)) return HOFEM_EUNSUPPORTED;
   if (mode != HOFEM_MODE_FP64 && mode != HOFEM_MODE_FP32) return HOFEM_EINVAL;
   const bool f64 = mode == HOFEM_MODE_FP64;
   const int dt = f64 ? 0 : 1;
@@ -1023,6 +1074,7 @@ int hofem_forward(hofem_solver S, int mode, const void* in_dev, void* out_dev, i
 int hofem_inverse(hofem_solver S, int mode, const void* in_dev, void* out_dev, int nrhs,
                   void* stream) {
   if (!S || !in_dev || !out_dev || nrhs < 1) return HOFEM_EINVAL;
+  if (mode != HOFEM_MODE_FP64 && !all_dirichlet(S)) return HOFEM_EUNSUPPORTED;
   if (mode != HOFEM_MODE_FP64 && mode != HOFEM_MODE_FP32) return HOFEM_EINVAL;
   const bool f64 = mode == HOFEM_MODE_FP64;
   const int dt = f64 ? 0 : 1;
@@ -1044,6 +1096,7 @@ int hofem_pcg(hofem_solver S, const hofem_coef* coef, const double* f_dev, doubl
   if (!S || !f_dev || !u_dev || nrhs < 1 || f_dev == u_dev || max_iter < 0 ||
       !std::isfinite(rtol) || !coef_ok(S, coef))
     return HOFEM_EINVAL;
+  if (!all_dirichlet(S)) return HOFEM_EUNSUPPORTED;
   if (!ws_dev || ws_bytes < pcg_bytes(S, coef)) return HOFEM_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const PcgWs w = pcg_carve(S, coef, ws_dev);
@@ -1070,6 +1123,7 @@ int hofem_apply_coef_operator(hofem_solver S, const hofem_coef* coef, const doub
                               void* stream) {
   if (!S || !u_dev || !out_dev || nrhs < 1 || u_dev == out_dev || !coef_ok(S, coef))
     return HOFEM_EINVAL;
+  if (!all_dirichlet(S)) return HOFEM_EUNSUPPORTED;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (!ws_dev || ws_bytes < pcg_bytes(S, coef)) return HOFEM_EINVAL;
   const PcgWs w = pcg_carve(S, coef, ws_dev);
@@ -1101,6 +1155,7 @@ namespace {
 int apply_op(hofem_solver S, const double* u_dev, double* out_dev, int nrhs, void* ws_dev,
              size_t ws_bytes, void* stream, bool mass_only) {
   if (!S || !u_dev || !out_dev || nrhs < 1 || u_dev == out_dev) return HOFEM_EINVAL;
+  if (!all_dirichlet(S)) return HOFEM_EUNSUPPORTED;
   const size_t need = op_elem_bytes(S);
   if (need && (!ws_dev || ws_bytes < need)) return HOFEM_EINVAL;
   OpArgs o;
@@ -1120,6 +1175,7 @@ int hofem_dirichlet_rhs(hofem_solver S, const double* b_ext_dev, const double* f
                         double* out_dev, int nrhs, void* stream) {
   if (!S || !b_ext_dev || !out_dev || nrhs < 1) return HOFEM_EINVAL;
   if (static_cast<const void*>(b_ext_dev) == static_cast<const void*>(out_dev)) return HOFEM_EINVAL;
+  if (!all_dirichlet(S)) return HOFEM_EUNSUPPORTED;
   OpArgs o = op_args(S, nullptr, nullptr, out_dev, 0, nrhs);
   HIPCHK(launch_dirichlet_lift(o, b_ext_dev, f_dev, out_dev, static_cast<hipStream_t>(stream)));
   return HOFEM_OK;
@@ -1214,6 +1270,7 @@ int hofem_solver_autotune(hofem_solver S, int mode, const void* f_dev, void* u_d
   if (mode != HOFEM_MODE_FP64 && mode != HOFEM_MODE_FP32 && mode != HOFEM_MODE_FP32_IR) return HOFEM_EINVAL;
   if (mode == HOFEM_MODE_FP32_IR && f_dev == u_dev) return HOFEM_EINVAL;
   if (max_entries > 0 && !out_host) return HOFEM_EINVAL;
+  if (!all_dirichlet(S)) return HOFEM_EUNSUPPORTED;   // periodic passes have one shape
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));

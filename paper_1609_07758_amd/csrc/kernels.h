@@ -148,6 +148,12 @@ struct BandArgs {
 };
 hipError_t launch_banded(const BandArgs& a, hipStream_t s);
 
+// Line passes along periodic axes (FP64; kind PASS_FWD, PASS_INV or
+// PASS_FUSED): tab.blk holds the Bloch eigenvectors w_{k,l,s} (complex FP64,
+// index (k n + l) n + s, k = 0..K/2), tab.tw the twiddles, tab.lam the
+// eigenvalues in the periodic coefficient order.
+hipError_t launch_periodic(int kind, const PassArgs& a, hipStream_t s);
+
 // u += delta over `count` elements with per-workgroup partial sums of
 // delta^2 and u^2 (nparts workgroups), reduced to out[0..1] by a second
 // launch (fixed order: deterministic).

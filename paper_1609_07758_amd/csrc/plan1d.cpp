@@ -397,4 +397,119 @@ int plan1d_build(int n, int K, Plan1DData* out) {
   return 0;
 }
 
+// Periodic axis (Section 2's pencil on a periodic mesh; the paper's
+// Bloch-type structure with phase 2 pi k / K).  A cell holds the n unknowns
+// node j and the interior points of element j+1; element j+1 couples cell j
+// with node j+1 of cell j+1, so the pencil is block circulant and its
+// eigenvectors are Bloch waves v_j = w e^{i phi j}, phi = 2 pi k / K, where
+// (lam, w) solve the n x n Hermitian pencil (T^H A T, T^H C T),
+// T = [[I_n], [e^{i phi} e_0^T]] (local nodes 0..n-1 are the cell, local node
+// n is node j+1).  The pencil is solved through its real 2n x 2n symmetric
+// embedding [[X, -Y], [Y, X]] (every eigenvalue doubled) by Cholesky and
+// Jacobi in binary128; w is normalised to w^H (T^H C T) w = 1 and rotated
+// so that its largest entry is real and positive (real at k = 0, K/2).
+int plan1d_build_periodic(int n, int K, Plan1DData* out) {
+  if (K < 2 || (K & (K - 1)) != 0) return -1;
+  if (plan1d_build(n, K, out) != 0) return -1;   // local matrices, Gauss tables, twiddles
+  const int nb = n + 1, d2 = 2 * n, m = n * K, nk = K / 2 + 1;
+  std::vector<q128> A, C, gx, gw, Bq, Dq;
+  local_matrices(n, A, C, gx, gw, Bq, Dq);
+  out->bc = 1;
+  out->m = m;
+  out->p.clear();
+  out->inorm.clear();
+  out->lam.assign(m, 0);
+  out->wr.assign((size_t)nk * n * n, 0);
+  out->wi.assign((size_t)nk * n * n, 0);
+  for (int k = 0; k < nk; ++k) {
+    const q128 ph = 2 * M_PIq * k / K;
+    const q128 cr = cosq(ph), ci = sinq(ph);
+    // T^H M T for M = A, C: real part X, imaginary part Y (n x n)
+    auto bloch = [&](const std::vector<q128>& M, std::vector<q128>& X, std::vector<q128>& Y) {
+      X.assign(n * n, 0);
+      Y.assign(n * n, 0);
+      for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) {
+          // sum_{r,c} conj(T[r][a]) M[r][c] T[c][b]; T[r][a] = [r == a] (r < n),
+          // T[n][a] = e^{i phi} [a == 0]
+          q128 xr = M[a * nb + b], xi = 0;
+          if (b == 0) {   // column c = n, T[n][0] = e^{i phi}
+            xr += M[a * nb + n] * cr;
+            xi += M[a * nb + n] * ci;
+          }
+          if (a == 0) {   // row r = n, conj(T[n][0]) = e^{-i phi}
+            xr += M[n * nb + b] * cr;
+            xi -= M[n * nb + b] * ci;
+          }
+          if (a == 0 && b == 0) xr += M[n * nb + n];
+          X[a * n + b] = xr;
+          Y[a * n + b] = xi;
+        }
+    };
+    std::vector<q128> XA, YA, XC, YC;
+    bloch(A, XA, YA);
+    bloch(C, XC, YC);
+    std::vector<q128> Ae(d2 * d2), Ce(d2 * d2);
+    for (int a = 0; a < n; ++a)
+      for (int b = 0; b < n; ++b) {
+        Ae[a * d2 + b] = XA[a * n + b];
+        Ae[(a + n) * d2 + (b + n)] = XA[a * n + b];
+        Ae[a * d2 + (b + n)] = -YA[a * n + b];
+        Ae[(a + n) * d2 + b] = YA[a * n + b];
+        Ce[a * d2 + b] = XC[a * n + b];
+        Ce[(a + n) * d2 + (b + n)] = XC[a * n + b];
+        Ce[a * d2 + (b + n)] = -YC[a * n + b];
+        Ce[(a + n) * d2 + b] = YC[a * n + b];
+      }
+    std::vector<q128> lam2, V2;
+    interior_eigen(d2, Ae, Ce, lam2, V2);   // ascending, pairs of equal eigenvalues
+    for (int l = 0; l < n; ++l) {
+      const int o = 2 * l;
+      std::vector<q128> wr(n), wi(n);
+      for (int s2 = 0; s2 < n; ++s2) {
+        wr[s2] = V2[s2 * d2 + o];
+        wi[s2] = V2[(s2 + n) * d2 + o];
+      }
+      // phase: largest entry real positive
+      int big = 0;
+      for (int s2 = 1; s2 < n; ++s2)
+        if (wr[s2] * wr[s2] + wi[s2] * wi[s2] > wr[big] * wr[big] + wi[big] * wi[big]) big = s2;
+      const q128 mag = sqrtq(wr[big] * wr[big] + wi[big] * wi[big]);
+      const q128 pr = wr[big] / mag, pi = -wi[big] / mag;   // multiply by conj(w_big)/|w_big|
+      for (int s2 = 0; s2 < n; ++s2) {
+        const q128 a = wr[s2] * pr - wi[s2] * pi, b = wr[s2] * pi + wi[s2] * pr;
+        wr[s2] = a;
+        wi[s2] = b;
+      }
+      if (k == 0 || 2 * k == K)
+        for (int s2 = 0; s2 < n; ++s2) wi[s2] = 0;
+      // w^H C w = 1 with C = X_C + i Y_C
+      q128 nrm = 0;
+      for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) {
+          // conj(w_a) (X + iY)_ab w_b, real part
+          const q128 mr = XC[a * n + b], mi = YC[a * n + b];
+          const q128 tr = mr * wr[b] - mi * wi[b], ti = mr * wi[b] + mi * wr[b];
+          nrm += wr[a] * tr + wi[a] * ti;
+        }
+      const q128 sc = 1 / sqrtq(nrm);
+      for (int s2 = 0; s2 < n; ++s2) {
+        out->wr[((size_t)k * n + l) * n + s2] = (double)(wr[s2] * sc);
+        out->wi[((size_t)k * n + l) * n + s2] = (double)(wi[s2] * sc);
+      }
+      // the constants span the kernel of A: lambda = 0 exactly for k = 0, l = 0
+      const double lv = k == 0 && l == 0 ? 0.0 : (double)lam2[o];
+      if (k == 0) {
+        out->lam[(size_t)l * K] = lv;
+      } else if (2 * k == K) {
+        out->lam[(size_t)l * K + K - 1] = lv;
+      } else {
+        out->lam[(size_t)l * K + 2 * k - 1] = lv;
+        out->lam[(size_t)l * K + 2 * k] = lv;
+      }
+    }
+  }
+  return 0;
+}
+
 }  // namespace hofem

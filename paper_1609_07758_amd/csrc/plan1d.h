@@ -10,6 +10,7 @@ namespace hofem {
 //   k = 0, l = 1..n-1      ->  q = l - 1
 //   k = 1..K-1, l = 1..n   ->  q = (n - 1) + (l - 1)(K - 1) + (k - 1)
 struct Plan1DData {
+  int bc = 0;                    // 0: Dirichlet, 1: periodic
   int n = 0, K = 0, m = 0;
   std::vector<double> A, C;      // local stiffness / mass on [-1,1], (n+1)^2 row major
   std::vector<double> lam;       // scaled eigenvalues in coefficient order (m)
@@ -25,9 +26,20 @@ struct Plan1DData {
   // differentiation on the Gauss nodes: Dh[q (n+1) + p] = g_p'(x_q) for the
   // Lagrange basis g_p of the Gauss nodes (Dh = D B^-1; rows sum to zero)
   std::vector<double> Dh;
+
+  // periodic axes: Bloch eigenvectors w_{k,l} (cell components s = 0..n-1:
+  // node j, interior points of element j+1) for k = 0..K/2, index
+  // (k n + l) n + s, real and imaginary parts; w^H C^(k) w = 1
+  std::vector<double> wr, wi;
 };
 
 // Returns 0 on success, -1 for unsupported (n, K).
 int plan1d_build(int n, int K, Plan1DData* out);
+// Periodic axis (m = nK unknowns: node j at q = n j, interior point s of
+// element j+1 at q = n j + s, j = 0..K-1): eigenvalues in the coefficient
+// order q = l K + t (t = 0: k = 0; t = 2k-1, 2k: real and imaginary parts of
+// wave number k = 1..K/2-1; t = K-1: k = K/2) and the Bloch eigenvectors.
+// Returns 0 on success, -1 for unsupported (n, K).
+int plan1d_build_periodic(int n, int K, Plan1DData* out);
 
 }  // namespace hofem

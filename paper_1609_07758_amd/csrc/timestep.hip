@@ -93,6 +93,7 @@ int hofem_stepper_create(hofem_solver solver, int scheme, hofem_stepper* out) {
   if (!solver || !out) return HOFEM_EINVAL;
   if (scheme != HOFEM_SCHEME_HEAT && scheme != HOFEM_SCHEME_WAVE) return HOFEM_EINVAL;
   if (!(solver_alpha(solver) > 0)) return HOFEM_EINVAL;   // alpha = 1/dt or 1/dt^2
+  if (!solver_all_dirichlet(solver)) return HOFEM_EUNSUPPORTED;
   hofem_stepper T = new (std::nothrow) hofem_stepper_s;
   if (!T) return HOFEM_ENOMEM;
   T->S = solver;

@@ -131,3 +131,45 @@ def test_one_hip_runtime_in_process():
     hsa = {l.split()[-1] for l in maps if "libhsa-runtime64" in l}
     assert len(hip) == 1, hip
     assert len(hsa) <= 1, hsa
+
+
+@pytest.mark.parametrize("n,K", [(1, 8), (2, 4), (3, 16), (5, 8), (9, 4), (4, 2)])
+def test_periodic_plan_tables(n, K):
+    # Bloch waves of the periodic plan are eigenvectors of the assembled
+    # periodic pencil (oracle.periodic), C-normalised to K, with the listed
+    # eigenvalues; the eigenvalues are the pencil's full spectrum.
+    import scipy.linalg as sla
+    from oracle import periodic
+    P = H.Plan1D(n, K, "periodic")
+    try:
+        assert P.m == n * K
+        lam = P.table("lam")
+        wr, wi = P.table("wr"), P.table("wi")
+        with pytest.raises(H.HofemError):
+            P.table("p")
+    finally:
+        P.close()
+    A, C = periodic.assemble_1d(n, K)
+    dense = np.sort(sla.eigh(A, C, eigvals_only=True))
+    assert np.max(np.abs(np.sort(lam) - dense)) < 1e-11 * max(1.0, dense[-1])
+    assert lam[0] == 0.0
+    w = (wr + 1j * wi).reshape(K // 2 + 1, n, n)
+    j = np.arange(K)
+    for k in range(K // 2 + 1):
+        ph = np.exp(2j * np.pi * k * j / K)
+        for l in range(n):
+            v = (ph[:, None] * w[k, l][None, :]).reshape(-1)
+            t = 0 if k == 0 else (K - 1 if 2 * k == K else 2 * k - 1)
+            lv = lam[l * K + t]
+            r = A @ v - lv * (C @ v)
+            assert np.linalg.norm(r) < 1e-11 * max(1.0, lv) * np.linalg.norm(C @ v)
+            assert abs(np.vdot(v, C @ v) - K) < 1e-12 * K
+            if 0 < k < K // 2:
+                assert lam[l * K + t + 1] == lv
+
+
+def test_periodic_plan_rejects_bad_bc():
+    h = ctypes.c_void_p()
+    lib = ctypes.CDLL(H.LIB_PATH)
+    assert lib.hofem_plan1d_create_bc(2, 8, 2, ctypes.byref(h)) == -1
+    assert lib.hofem_plan1d_create_bc(2, 6, 1, ctypes.byref(h)) == -2
