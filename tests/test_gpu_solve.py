@@ -358,3 +358,24 @@ def test_graph_replay_of_single_solves(mode):
     torch.cuda.synchronize()
     assert torch.equal(u, ref2)
     S.close()
+
+
+# Many long (tight-layout, two lines or one line per workgroup) lines: more
+# workgroups than the CUs hold at once, an uneven last round, two
+# right-hand sides.
+MANY_LONG = [
+    ((9, 2), (512, 512), (1.0, 1.0), 0.0, 1),     # fused pass along 1023 columns, two per group
+    ((3, 9), (256, 512), (1.0, 1.0), 1.0, 1),     # inverse pass along 767 rows, one per group
+    ((9, 3), (512, 256), (1.0, 2.0), 0.0, 2),     # both, two right-hand sides
+    ((2, 2, 9), (16, 16, 512), (1.0, 1.0, 1.0), 0.5, 1),
+]
+
+
+@pytest.mark.parametrize("orders,Ks,X,alpha,nrhs", MANY_LONG)
+def test_many_long_lines_match_oracle(orders, Ks, X, alpha, nrhs):
+    shp = workloads.shape(orders, Ks)
+    f = np.stack([workloads.uniform_rhs(shp, seed=20 + r) for r in range(nrhs)])
+    got, _ = run_case(orders, Ks, X, alpha, f.reshape(-1), nrhs=nrhs)
+    got = got.reshape(f.shape)
+    for r in range(nrhs):
+        assert rel(got[r], osolve.solve(f[r], orders, Ks, X, alpha)) < 1e-12
