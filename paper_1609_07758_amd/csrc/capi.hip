@@ -574,14 +574,20 @@ std::vector<unsigned char> pack_plan(const Plan1DData& d, PlanOff* off) {
   Packer pk;
   const int n = d.n, K = d.K;
   if (d.bc == 1) {
-    // periodic: eigenvalues, Bloch eigenvectors (complex, FP64), twiddles,
-    // local and Gauss tables; the FP32 and Dirichlet-only slots point at the
+    // periodic: eigenvalues, Bloch eigenvectors (complex FP64, blocked by
+    // 64 wave numbers: entry e = l n + s of wave number k at
+    // ((k / 64) n^2 + e) 64 + k % 64, so that a wavefront reads one entry
+    // of 64 consecutive k with one contiguous 1 KB access), twiddles, local
+    // and Gauss tables; the FP32 and Dirichlet-only slots point at the
     // twiddles (no pass reads them)
-    std::vector<double> w(2 * d.wr.size());
-    for (size_t i = 0; i < d.wr.size(); ++i) {
-      w[2 * i] = d.wr[i];
-      w[2 * i + 1] = d.wi[i];
-    }
+    const size_t nk = (size_t)K / 2 + 1, ne = (size_t)n * n, nblk = (nk + 63) / 64;
+    std::vector<double> w(2 * nblk * ne * 64, 0.0);
+    for (size_t k = 0; k < nk; ++k)
+      for (size_t e = 0; e < ne; ++e) {
+        const size_t at = ((k / 64) * ne + e) * 64 + k % 64;
+        w[2 * at] = d.wr[k * ne + e];
+        w[2 * at + 1] = d.wi[k * ne + e];
+      }
     off->lam = pk.add_f64(d.lam);
     off->blk64 = pk.add_f64(w);
     off->tw64 = pk.add_f64(d.tw);

@@ -14,7 +14,12 @@
 // for k = K/2.  Components are FFT-ed in pairs (s, s+1) as one complex
 // sequence y_s + i y_{s+1}, separated by conjugate symmetry; the K-point
 // FFT is the wavefront-level Stockham transform of the Dirichlet passes.
-// One line per 256-lane workgroup, in LDS.
+//
+// A workgroup owns cb lines in LDS.  After the transforms a lane owns one
+// wave number k of one line together with its mirror K - k (k = 0 also
+// takes K/2): every Bloch vector w_{k,l} is read once (64 consecutive k per
+// wavefront, one contiguous access per entry) and used both for the
+// coefficient and, in the fused and inverse passes, for the inverse sum.
 
 #include "linepass.h"
 
@@ -23,35 +28,84 @@ namespace {
 
 using lp::cx;
 
-constexpr int kPerThreads = 256;
+constexpr int kPerMaxThreads = 512;
+constexpr int kPerMaxCB = 32;
 
-template <int LOG2K, int MODE>
-__global__ __launch_bounds__(kPerThreads) void periodic_pass(PassArgs a) {
+struct PerShape {
+  int cb, threads;
+  size_t lds;
+};
+
+// Lines per workgroup: as many as 160 KB of LDS holds (a power of two, at
+// most kPerMaxCB and the line count); 512 lanes when there are two or more.
+// (The inverse pass reads its coefficients straight from global memory in
+// the block phase, each once, so every pass needs only the sequences.)
+inline PerShape per_shape(int n, int K, int mode, long long nlines) {
+  const int NP = (n + 1) / 2;
+  (void)mode;
+  const size_t per_line = (size_t)NP * K * sizeof(cx<double>);
+  long long cb = 1;
+  while (cb * 2 <= kPerMaxCB && (size_t)(cb * 2) * per_line <= 160 * 1024 && cb * 2 <= nlines) cb *= 2;
+  PerShape s;
+  s.cb = (int)cb;
+  s.threads = cb >= 2 ? 512 : 256;
+  s.lds = (size_t)cb * per_line;
+  return s;
+}
+
+template <int N, int LOG2K, int MODE>
+__global__ __launch_bounds__(kPerMaxThreads) void periodic_pass(PassArgs a) {
   using S = lp::FftShape<LOG2K, 4>;
   constexpr int K = S::K, R = S::R, G = S::G;
+  constexpr int H = K / 2;
   constexpr int TPW = 64 / G;
-  const int n = a.tab.n, m = a.tab.m;
-  const int NP = (n + 1) / 2;
+  constexpr int n = N, m = N * K;
+  constexpr int NP = (N + 1) / 2;
+  const int cb = a.cb, lcb = __builtin_ctz(cb);
   extern __shared__ __align__(16) unsigned char smem[];
-  cx<double>* slots = reinterpret_cast<cx<double>*>(smem);     // [NP][K]
-  double* flat = reinterpret_cast<double*>(slots + (size_t)NP * K);   // [m] (inverse pass)
+  cx<double>* slots = reinterpret_cast<cx<double>*>(smem);            // [cb][NP][K]
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int wave = tid >> 6, lane = tid & 63, nwaves = nthr >> 6;
-  const long long L = blockIdx.x;
+  // XCD-aware numbering, as in the Dirichlet passes: each XCD walks one
+  // contiguous range of lines
+  const unsigned nb = gridDim.x, xcd = blockIdx.x % lp::kXcds, per = nb / lp::kXcds,
+                 rem = nb % lp::kXcds;
+  const unsigned wg = xcd * per + min(xcd, rem) + blockIdx.x / lp::kXcds;
+  const long long L0 = (long long)wg * cb;
+  const int cv = (int)min((long long)cb, a.nlines - L0);
   const long long inner = a.inner;
-  const long long o = L / inner, tcol = L - o * inner;
-  const long long base = o * (long long)m * inner + tcol;
+  const bool cfast = inner != 1;   // strided axis: adjacent lanes take adjacent lines
   const double* __restrict__ src = static_cast<const double*>(a.in);
   double* __restrict__ dst = static_cast<double*>(a.out);
   const cx<double>* __restrict__ W = static_cast<const cx<double>*>(a.tab.blk);
   const cx<double>* __restrict__ TW = static_cast<const cx<double>*>(a.tab.tw);
-  auto slot = [&](int p, int i) -> cx<double>& { return slots[(size_t)p * K + lp::sw(i)]; };
+  auto lbase = [&](int c) -> long long {
+    const long long L = L0 + c, o = L / inner, t = L - o * inner;
+    return o * (long long)m * inner + t;
+  };
+  auto slot = [&](int c, int p, int i) -> cx<double>& {
+    return slots[((size_t)c * NP + p) * K + lp::sw(i)];
+  };
+  // item i of cv * count: (line, index), lines fastest on a strided axis
+  auto split = [&](int i, int count, int& c, int& q) {
+    if (cfast) {
+      c = i & (cb - 1);
+      q = i >> lcb;
+    } else {
+      c = i / count;
+      q = i - c * count;
+    }
+  };
+  const int items_m = cfast ? cb * m : cv * m;
 
   if (MODE == PASS_FWD || MODE == PASS_FUSED) {
-    for (int q = tid; q < m; q += nthr) {
+    for (int i = tid; i < items_m; i += nthr) {
+      int c, q;
+      split(i, m, c, q);
+      if (c >= cv) continue;
       const int j = q / n, s = q - j * n;
-      const double v = src[base + (long long)q * inner];
-      cx<double>& e = slot(s >> 1, j);
+      const double v = src[lbase(c) + (long long)q * inner];
+      cx<double>& e = slot(c, s >> 1, j);
       if (s & 1) {
         e.y = v;
       } else {
@@ -59,21 +113,22 @@ __global__ __launch_bounds__(kPerThreads) void periodic_pass(PassArgs a) {
         if (s == n - 1) e.y = 0.0;   // odd n: the last pair has one component
       }
     }
-  } else {
-    for (int q = tid; q < m; q += nthr) flat[q] = src[base + (long long)q * inner];
   }
   __syncthreads();
 
-  auto transforms = [&]() {   // K-point FFT of every pair, rounds of TPW per wave
-    for (int t0 = 0; t0 < NP; t0 += nwaves * TPW) {
+  auto transforms = [&]() {   // K-point FFT of every pair, rounds of TPW tasks per wave
+    const int ntask = cv * NP;
+    for (int t0 = 0; t0 < ntask; t0 += nwaves * TPW) {
       const int task = t0 + wave * TPW + lane / G;
-      if (task < NP) {
-        int j = lane & (G - 1);
+      if (task < ntask) {
+        const int c = task / NP, p = task - c * NP;
+        cx<double>* tb = slots + ((size_t)c * NP + p) * K;
+        const int j = lane & (G - 1);
         cx<double> v[R];
 #pragma unroll
-        for (int t = 0; t < R; ++t) v[t] = slot(task, j + G * t);
+        for (int t = 0; t < R; ++t) v[t] = tb[lp::sw(j + G * t)];
         lp::wave_sync();
-        lp::task_fft<double, LOG2K, 4>(v, slots + (size_t)task * K, j, TW);
+        lp::task_fft<double, LOG2K, 4>(v, tb, j, TW);
       }
     }
   };
@@ -82,89 +137,113 @@ __global__ __launch_bounds__(kPerThreads) void periodic_pass(PassArgs a) {
     __syncthreads();
   }
 
-  // per wave number k = 0..K/2: the n x n complex blocks (each k owns
-  // entries k and K-k of every pair: no other thread touches them)
   const double invK = 1.0 / K;
   const double sc = a.scale;
-  double dline = a.alpha;
-  if (MODE == PASS_FUSED) {
-    const long long t = tcol;   // position among the other axes
-    for (int i = 0; i < a.nother; ++i) dline += a.oscale[i] * a.olam[i][(t / a.odiv[i]) % a.omod[i]];
-  }
-  for (int k = tid; k <= K / 2; k += nthr) {
+  constexpr int ne = N * N;
+  // the n x n block of wave number k of line c
+  auto block = [&](int c, int k, double dline) {
     const int kk = (K - k) & (K - 1);
-    const int tre = k == 0 ? 0 : (2 * k == K ? K - 1 : 2 * k - 1);   // real part's t
+    const int tre = k == 0 ? 0 : (2 * k == K ? K - 1 : 2 * k - 1);   // the real part's t
     const bool cplx = k != 0 && 2 * k != K;
-    cx<double> c[9];
+    const cx<double>* __restrict__ wk = W + (size_t)(k >> 6) * ne * 64 + (k & 63);
+    cx<double> X[2 * NP], U[N];
     if (MODE == PASS_FWD || MODE == PASS_FUSED) {
-      cx<double> X[10];
+#pragma unroll
       for (int p = 0; p < NP; ++p) {
-        const cx<double> u = slot(p, k), w = slot(p, kk);
+        const cx<double> u = slot(c, p, k), w = slot(c, p, kk);
         X[2 * p] = {0.5 * (u.x + w.x), 0.5 * (u.y - w.y)};
         X[2 * p + 1] = {0.5 * (u.y + w.y), -0.5 * (u.x - w.x)};
       }
-      for (int l = 0; l < n; ++l) {
-        double cr = 0.0, ci = 0.0;
-        const cx<double>* wl = W + ((size_t)k * n + l) * n;
-        for (int s = 0; s < n; ++s) {
-          const cx<double> ws = wl[s];
-          cr += ws.x * X[s].x + ws.y * X[s].y;   // conj(w) X
-          ci += ws.x * X[s].y - ws.y * X[s].x;
+    }
+#pragma unroll
+    for (int s = 0; s < N; ++s) U[s] = {0.0, 0.0};
+    const long long ob = MODE != PASS_FUSED ? lbase(c) : 0;
+    // one eigenvector per iteration (n complex entries in registers)
+#pragma unroll 1
+    for (int l = 0; l < N; ++l) {
+      cx<double> wl[N];
+#pragma unroll
+      for (int s = 0; s < N; ++s) wl[s] = wk[(size_t)(l * N + s) * 64];
+      double cr, ci;
+      if (MODE == PASS_INV) {
+        // (in place is safe: a workgroup reads only its own lines, all of
+        // them before the barrier that precedes its stores)
+        cr = src[ob + ((long long)l * K + tre) * inner];
+        ci = cplx ? src[ob + ((long long)l * K + tre + 1) * inner] : 0.0;
+      } else {
+        cr = 0.0;
+        ci = 0.0;
+#pragma unroll
+        for (int s = 0; s < N; ++s) {
+          cr += wl[s].x * X[s].x + wl[s].y * X[s].y;   // conj(w) X
+          ci += wl[s].x * X[s].y - wl[s].y * X[s].x;
         }
-        c[l] = {cr * invK, cplx ? ci * invK : 0.0};
-      }
-      if (MODE == PASS_FWD) {
-        for (int l = 0; l < n; ++l) {
-          dst[base + ((long long)l * K + tre) * inner] = c[l].x;
-          if (cplx) dst[base + ((long long)l * K + tre + 1) * inner] = c[l].y;
+        cr *= invK;
+        ci = cplx ? ci * invK : 0.0;
+        if (MODE == PASS_FWD) {
+          dst[ob + ((long long)l * K + tre) * inner] = cr;
+          if (cplx) dst[ob + ((long long)l * K + tre + 1) * inner] = ci;
+          continue;
         }
-        continue;
-      }
-      for (int l = 0; l < n; ++l) {
         const double den = dline + sc * a.tab.lam[(size_t)l * K + tre];
-        c[l] = {c[l].x / den, c[l].y / den};
+        cr /= den;
+        ci /= den;
       }
-    } else {
-      for (int l = 0; l < n; ++l)
-        c[l] = {flat[(size_t)l * K + tre], cplx ? flat[(size_t)l * K + tre + 1] : 0.0};
+#pragma unroll
+      for (int s = 0; s < N; ++s) {
+        U[s].x += cr * wl[s].x - ci * wl[s].y;
+        U[s].y += cr * wl[s].y + ci * wl[s].x;
+      }
     }
-    // U_s = sum_l c_l w_{k,l,s}; inverse-FFT input as conj(Z), Z = U_s + i U_{s+1}
+    if (MODE == PASS_FWD) return;
+    // inverse-FFT input as conj(Z), Z = U_s + i U_{s+1}, at entries k and K - k
+#pragma unroll
     for (int p = 0; p < NP; ++p) {
-      cx<double> U0 = {0.0, 0.0}, U1 = {0.0, 0.0};
-      for (int l = 0; l < n; ++l) {
-        const cx<double>* wl = W + ((size_t)k * n + l) * n;
-        const cx<double> w0 = wl[2 * p];
-        U0.x += c[l].x * w0.x - c[l].y * w0.y;
-        U0.y += c[l].x * w0.y + c[l].y * w0.x;
-        if (2 * p + 1 < n) {
-          const cx<double> w1 = wl[2 * p + 1];
-          U1.x += c[l].x * w1.x - c[l].y * w1.y;
-          U1.y += c[l].x * w1.y + c[l].y * w1.x;
-        }
-      }
-      slot(p, k) = {U0.x - U1.y, -(U0.y + U1.x)};
-      if (kk != k) slot(p, kk) = {U0.x + U1.y, U0.y - U1.x};
+      const cx<double> U0 = U[2 * p];
+      const cx<double> U1 = 2 * p + 1 < N ? U[2 * p + 1] : cx<double>{0.0, 0.0};
+      slot(c, p, k) = {U0.x - U1.y, -(U0.y + U1.x)};
+      if (kk != k) slot(c, p, kk) = {U0.x + U1.y, U0.y - U1.x};
     }
+  };
+  // denominator part of line c from the other axes (fused pass)
+  auto line_den = [&](int c) -> double {
+    double d = a.alpha;
+    const long long t = (L0 + c) % inner;   // position among the other axes
+    for (int i = 0; i < a.nother; ++i) d += a.oscale[i] * a.olam[i][(t / a.odiv[i]) % a.omod[i]];
+    return d;
+  };
+  const int items_k = cfast ? cb * H : cv * H;
+  for (int i = tid; i < items_k; i += nthr) {
+    int c, k;
+    split(i, H, c, k);
+    if (c >= cv) continue;
+    const double dline = MODE == PASS_FUSED ? line_den(c) : 0.0;
+    block(c, k, dline);
+    if (k == 0) block(c, H, dline);   // the other self-conjugate wave number
   }
   if (MODE == PASS_FWD) return;
   __syncthreads();
   transforms();   // FFT of conj(Z) = conj of the inverse transform
   __syncthreads();
-  for (int q = tid; q < m; q += nthr) {
+  for (int i = tid; i < items_m; i += nthr) {
+    int c, q;
+    split(i, m, c, q);
+    if (c >= cv) continue;
     const int j = q / n, s = q - j * n;
-    const cx<double> e = slot(s >> 1, j);
-    dst[base + (long long)q * inner] = (s & 1) ? -e.y : e.x;
+    const cx<double> e = slot(c, s >> 1, j);
+    dst[lbase(c) + (long long)q * inner] = (s & 1) ? -e.y : e.x;
   }
 }
 
-template <int LOG2K, int MODE>
-hipError_t launch_per_k(const PassArgs& a, hipStream_t s) {
+template <int N, int LOG2K, int MODE>
+hipError_t launch_per_k(const PassArgs& a0, hipStream_t s) {
   constexpr int K = 1 << LOG2K;
-  const int NP = (a.tab.n + 1) / 2;
-  size_t lds = (size_t)NP * K * sizeof(cx<double>);
-  if (MODE == PASS_INV) lds += (size_t)a.tab.m * sizeof(double);
-  if (lds > 160 * 1024 || a.tab.n < 1 || a.tab.n > 9 || a.tab.K != K) return hipErrorInvalidValue;
-  auto fn = periodic_pass<LOG2K, MODE>;
+  if (a0.tab.n != N || a0.tab.K != K || a0.tab.m != N * K) return hipErrorInvalidValue;
+  const PerShape sh = per_shape(a0.tab.n, K, MODE, a0.nlines);
+  if (sh.lds > 160 * 1024) return hipErrorInvalidValue;
+  PassArgs a = a0;
+  a.cb = sh.cb;
+  auto fn = periodic_pass<N, LOG2K, MODE>;
   static bool raised = false;   // benign race: every caller sets the same value
   if (!raised) {
     const hipError_t e = hipFuncSetAttribute((const void*)fn,
@@ -172,24 +251,41 @@ hipError_t launch_per_k(const PassArgs& a, hipStream_t s) {
     if (e != hipSuccess) return e;
     raised = true;
   }
-  if (a.nlines > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(fn, dim3((unsigned)a.nlines), dim3(kPerThreads), lds, s, a);
+  const long long blocks = (a.nlines + a.cb - 1) / a.cb;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(sh.threads), sh.lds, s, a);
   return hipGetLastError();
+}
+
+template <int N, int MODE>
+hipError_t launch_per_nk(const PassArgs& a, hipStream_t s) {
+  switch (a.tab.K) {
+    case 2: return launch_per_k<N, 1, MODE>(a, s);
+    case 4: return launch_per_k<N, 2, MODE>(a, s);
+    case 8: return launch_per_k<N, 3, MODE>(a, s);
+    case 16: return launch_per_k<N, 4, MODE>(a, s);
+    case 32: return launch_per_k<N, 5, MODE>(a, s);
+    case 64: return launch_per_k<N, 6, MODE>(a, s);
+    case 128: return launch_per_k<N, 7, MODE>(a, s);
+    case 256: return launch_per_k<N, 8, MODE>(a, s);
+    case 512: return launch_per_k<N, 9, MODE>(a, s);
+    case 1024: return launch_per_k<N, 10, MODE>(a, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <int MODE>
 hipError_t launch_per_mode(const PassArgs& a, hipStream_t s) {
-  switch (a.tab.K) {
-    case 2: return launch_per_k<1, MODE>(a, s);
-    case 4: return launch_per_k<2, MODE>(a, s);
-    case 8: return launch_per_k<3, MODE>(a, s);
-    case 16: return launch_per_k<4, MODE>(a, s);
-    case 32: return launch_per_k<5, MODE>(a, s);
-    case 64: return launch_per_k<6, MODE>(a, s);
-    case 128: return launch_per_k<7, MODE>(a, s);
-    case 256: return launch_per_k<8, MODE>(a, s);
-    case 512: return launch_per_k<9, MODE>(a, s);
-    case 1024: return launch_per_k<10, MODE>(a, s);
+  switch (a.tab.n) {
+    case 1: return launch_per_nk<1, MODE>(a, s);
+    case 2: return launch_per_nk<2, MODE>(a, s);
+    case 3: return launch_per_nk<3, MODE>(a, s);
+    case 4: return launch_per_nk<4, MODE>(a, s);
+    case 5: return launch_per_nk<5, MODE>(a, s);
+    case 6: return launch_per_nk<6, MODE>(a, s);
+    case 7: return launch_per_nk<7, MODE>(a, s);
+    case 8: return launch_per_nk<8, MODE>(a, s);
+    case 9: return launch_per_nk<9, MODE>(a, s);
     default: return hipErrorInvalidValue;
   }
 }
