@@ -190,7 +190,7 @@ def bench_headline(args, torch, H, np, workloads, dev):
                          args.warmup)
     del bext, lift, uh
 
-    log("large_2d: periodic axes")
+    log("large_2d: periodic and Neumann axes")
     # the same orders and meshes with both axes periodic (alpha = 1): Bloch
     # waves, m = nK per axis
     Sp = H.Solver(cfg["orders"], cfg["Ks"], cfg["X"], 1.0, bcs=("periodic", "periodic"))
@@ -203,6 +203,16 @@ def bench_headline(args, torch, H, np, workloads, dev):
     M_per = Sp.size
     Sp.close()
     del fp, up
+    # Neumann axes, n = 9, K = 512 each (the passes run on the reflected
+    # periodic grid of 2K elements per axis)
+    Sn = H.Solver(cfg["orders"], (512, 512), cfg["X"], 1.0, bcs=("neumann", "neumann"))
+    fn_ = torch.rand(Sn.size, dtype=torch.float64, device=dev)
+    un_ = torch.empty_like(fn_)
+    wsn = Sn.workspace("fp64")
+    ms_neu = time_calls(torch, lambda: Sn.solve(fn_, un_, mode="fp64", ws=wsn), args.steps, args.warmup)
+    M_neu = Sn.size
+    Sn.close()
+    del fn_, un_, wsn
 
     log("large_2d: autotuned launch shapes (FP64)")
     tune = S.autotune("fp64", nrhs=1, reps=3, f=f64, u=u64)
@@ -259,6 +269,9 @@ def bench_headline(args, torch, H, np, workloads, dev):
                        "unknowns_per_s": M / (ms_heat * 1e-3),
                        "note": "backward Euler step: mass update + FP64 solve, HIP-graph replay"},
         "dirichlet_lift": {"ms": ms_lift, "unknowns_per_s": M / (ms_lift * 1e-3)},
+        "neumann_fp64": {"unknowns": M_neu, "orders": cfg["orders"], "K_per_axis": 512, "alpha": 1.0,
+                         "ms_per_step": ms_neu, "unknowns_per_s": M_neu / (ms_neu * 1e-3),
+                         "note": "even reflection onto the periodic grid of 2K elements per axis"},
         "periodic_fp64": {"unknowns": M_per, "alpha": 1.0, "ms_per_step": ms_per,
                           "unknowns_per_s": M_per / (ms_per * 1e-3),
                           "passes": [dict(p, avg_ms=p["ms"] / p["launches"],

@@ -123,7 +123,22 @@ int hofem_plan1d_create(int n, int K, hofem_plan1d* out);
  * every other entry point returns HOFEM_EUNSUPPORTED for a solver with a
  * periodic axis.  An all-periodic solver needs alpha > 0 (the constants have
  * lambda = 0): otherwise hofem_solver_create returns HOFEM_ENOTPOSDEF. */
-enum hofem_bc { HOFEM_BC_DIRICHLET = 0, HOFEM_BC_PERIODIC = 1 };
+enum hofem_bc { HOFEM_BC_DIRICHLET = 0, HOFEM_BC_PERIODIC = 1, HOFEM_BC_NEUMANN = 2 };
+
+/* A Neumann axis (natural boundary conditions at x = 0 and x = X) holds the
+ * m = nK + 1 values at the points g h / n, g = 0..nK, boundary nodes
+ * included, in physical order.  Its pencil is the even half of the periodic
+ * pencil of 2K elements on [-X, X) (the reflection maps Bloch waves of wave
+ * number k to -k), so a solve reflects f^h into that periodic grid (the two
+ * boundary rows doubled, as the reflected pencil counts them twice), runs
+ * the periodic FP64 passes there and keeps the caller's half: K <= 512
+ * (HOFEM_EUNSUPPORTED otherwise), and an FP64 solve of a solver with a
+ * Neumann axis takes a workspace of the reflected grid
+ * (hofem_solver_workspace_bytes; HOFEM_EINVAL without it).  The plan's
+ * tables (hofem_plan1d_table) are those of the periodic axis of 2K elements
+ * (table 0 has 2nK eigenvalues); hofem_plan1d_dim reports nK + 1.
+ * hofem_forward and hofem_inverse return HOFEM_EUNSUPPORTED for a solver
+ * with a Neumann axis; the other restrictions are those of periodic axes. */
 
 /* hofem_plan1d_create with a boundary condition (enum hofem_bc; else
  * HOFEM_EINVAL).  hofem_plan1d_create(n, K, out) is
@@ -131,7 +146,8 @@ enum hofem_bc { HOFEM_BC_DIRICHLET = 0, HOFEM_BC_PERIODIC = 1 };
 int hofem_plan1d_create_bc(int n, int K, int bc, hofem_plan1d* out);
 void hofem_plan1d_destroy(hofem_plan1d plan);
 
-/* Number of unknowns of the plan's axis: m = nK - 1 (Dirichlet), nK (periodic). */
+/* Number of unknowns of the plan's axis: m = nK - 1 (Dirichlet), nK (periodic),
+ * nK + 1 (Neumann). */
 int hofem_plan1d_dim(hofem_plan1d plan, int* m);
 
 /* Host copies of the plan's tables, for inspection and tests.  `which`:

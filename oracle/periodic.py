@@ -1,4 +1,4 @@
-"""Periodic axes (oracle).  TEST INFRASTRUCTURE ONLY.
+"""Periodic and Neumann axes (oracle).  TEST INFRASTRUCTURE ONLY.
 
 The Introduction notes that boundary conditions other than Dirichlet fit the
 method.  On a periodic axis the points x = 0 and x = X are one point, so the
@@ -7,7 +7,11 @@ q = g): the mesh node j at q = n j and the interior points l = 1..n-1 of
 element j + 1 at q = n j + l.  Element j = 1..K couples the positions
 n (j-1) .. n j, the last one taken modulo nK (element K ends at node 0).
 
-The oracle is the plain definition: the periodic pencil assembled from the
+A Neumann axis (natural boundary conditions at both ends) holds the values
+at every point g h / n, g = 0..nK, boundary nodes included: element j
+couples the positions n (j-1) .. n j and nothing is removed.
+
+The oracle is the plain definition: the periodic (or Neumann) pencil assembled from the
 exact local matrices of Section 2, paragraph 1 (every entry rounded once),
 the N-D operator of eq. (bvp glob 2) with the periodic matrices on the
 periodic axes, and a sparse direct solve of it, corrected with residuals
@@ -60,16 +64,42 @@ def assemble_1d(n, K):
     return As.toarray(), Cs.toarray()
 
 
+def assemble_1d_neumann_sparse(n, K):
+    """Scaled Neumann stiffness and mass (all nK + 1 points), CSR, every entry
+    the exact assembled rational rounded once."""
+    A, C = local_matrices(n)
+    m = n * K + 1
+    ea, ec = {}, {}
+    for j in range(1, K + 1):
+        for r in range(n + 1):
+            qr = n * (j - 1) + r
+            for s in range(n + 1):
+                qs = n * (j - 1) + s
+                ea[(qr, qs)] = ea.get((qr, qs), Fraction(0)) + A[r][s]
+                ec[(qr, qs)] = ec.get((qr, qs), Fraction(0)) + C[r][s]
+    keys = sorted(ea)
+    rows = np.array([k[0] for k in keys])
+    cols = np.array([k[1] for k in keys])
+    Av = np.array([float(ea[k]) for k in keys])
+    Cv = np.array([float(ec[k]) for k in keys])
+    return (sp.csr_matrix((Av, (rows, cols)), shape=(m, m)),
+            sp.csr_matrix((Cv, (rows, cols)), shape=(m, m)))
+
+
 def axis_matrices(n, K, bc):
-    """(A, C) of one axis, bc "dirichlet" or "periodic" (CSR)."""
+    """(A, C) of one axis, bc "dirichlet", "periodic" or "neumann" (CSR)."""
     if bc == "periodic":
         return assemble_1d_sparse(n, K)
+    if bc == "neumann":
+        return assemble_1d_neumann_sparse(n, K)
     if bc == "dirichlet":
         return assembly.assemble_1d_sparse(n, K)
     raise ValueError(f"unknown boundary condition {bc!r}")
 
 
 def axis_dim(n, K, bc):
+    if bc == "neumann":
+        return n * K + 1
     return dim(n, K) if bc == "periodic" else assembly.dim(n, K)
 
 
@@ -129,17 +159,23 @@ def _exact_rows(n, K, bc):
     m = axis_dim(n, K, bc)
     ra = [dict() for _ in range(m)]
     rc = [dict() for _ in range(m)]
+
+    def index(g):   # array index of position g, None if not an unknown
+        if bc == "periodic":
+            return g % m
+        if bc == "neumann":
+            return g
+        return None if g in (0, n * K) else g - 1
+
     for j in range(1, K + 1):
         for r in range(n + 1):
-            gr = n * (j - 1) + r
-            if bc != "periodic" and gr in (0, n * K):
+            qr = index(n * (j - 1) + r)
+            if qr is None:
                 continue
-            qr = gr % m if bc == "periodic" else gr - 1
             for t in range(n + 1):
-                gt = n * (j - 1) + t
-                if bc != "periodic" and gt in (0, n * K):
+                qt = index(n * (j - 1) + t)
+                if qt is None:
                     continue
-                qt = gt % m if bc == "periodic" else gt - 1
                 ra[qr][qt] = ra[qr].get(qt, Fraction(0)) + A[r][t]
                 rc[qr][qt] = rc[qr].get(qt, Fraction(0)) + C[r][t]
 
@@ -217,10 +253,11 @@ def solve(fh, ns, Ks, Xs, alpha, bcs, steps=6):
     The rounded matrix alone would carry an error of about cond(L) 2^-53
     (its stiffness no longer annihilates the constants exactly); the
     corrected v is the solution of the exact FEM system rounded to FP64.
-    L is SPD unless every axis is periodic and alpha = 0."""
+    L is SPD unless no axis is Dirichlet and alpha = 0 (constants in the
+    kernel)."""
     fh = np.asarray(fh, dtype=np.float64)
-    if all(b == "periodic" for b in bcs) and not alpha > 0:
-        raise ValueError("an all-periodic operator needs alpha > 0")
+    if all(b != "dirichlet" for b in bcs) and not alpha > 0:
+        raise ValueError("without a Dirichlet axis the operator needs alpha > 0")
     lu = spla.splu(operator_sparse(ns, Ks, Xs, alpha, bcs))
     v = lu.solve(fh.reshape(-1)).reshape(fh.shape)
     for _ in range(steps):

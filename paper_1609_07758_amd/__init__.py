@@ -35,7 +35,7 @@ HOFEM_ETOOBIG = -7
 MODES = {"fp64": 0, "fp32": 1, "fp32_ir": 2, "fp32_pcg": 3, "fp64_b": 4}
 TABLES = {"lam": 0, "p": 1, "inorm": 2, "E": 3, "A": 4, "C": 5, "gx": 6, "gw": 7, "B": 8, "D": 9,
           "wr": 10, "wi": 11}
-BCS = {"dirichlet": 0, "periodic": 1}
+BCS = {"dirichlet": 0, "periodic": 1, "neumann": 2}
 
 # Names and signatures of every entry point of include/hofem.h.
 _c_int, _c_double, _c_size, _vp = ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p
@@ -562,10 +562,13 @@ class Plan1D:
 
     def table(self, which):
         n, K = self.n, self.K
-        counts = {"lam": self.m, "p": (K - 1) * n * (n - 1), "inorm": (K - 1) * n,
+        # a Neumann plan carries the tables of the periodic axis of 2K elements
+        Kt = 2 * K if self.bc == "neumann" else K
+        nlam = n * Kt if self.bc != "dirichlet" else self.m
+        counts = {"lam": nlam, "p": (K - 1) * n * (n - 1), "inorm": (K - 1) * n,
                   "E": (n - 1) ** 2, "A": (n + 1) ** 2, "C": (n + 1) ** 2,
                   "gx": n + 1, "gw": n + 1, "B": (n + 1) ** 2, "D": (n + 1) ** 2,
-                  "wr": (K // 2 + 1) * n * n, "wi": (K // 2 + 1) * n * n}
+                  "wr": (Kt // 2 + 1) * n * n, "wi": (Kt // 2 + 1) * n * n}
         return hofem_plan1d_table(self.handle, which, counts[which])
 
     def close(self):
@@ -656,7 +659,7 @@ class Solver:
         if u is None:
             u = torch.empty_like(f)
         self._check_grid(u, dt, nrhs, "u")
-        if mode in ("fp32_ir", "fp32_pcg") and ws is None:
+        if ws is None:   # (FP64 needs one only with a Neumann axis)
             ws = self.workspace(mode, nrhs, f.device)
         info, st = hofem_solve(self.handle, mode, f, u, nrhs, ws, max_iter, tol, stream, want_info,
                                raise_noconv)

@@ -66,8 +66,11 @@ namespace {
   } while (0)
 
 struct DevAxis {
-  int bc = 0;                   // 0: Dirichlet, 1: periodic
-  int n = 0, K = 0, m = 0;
+  int bc = 0;                   // 0: Dirichlet, 1: periodic, 2: Neumann
+  // n, K, m of the passes (a Neumann axis runs as the periodic axis of 2K
+  // elements on its even reflection: K = 2 K_own, m = 2 n K_own); mu: the
+  // axis's unknowns in the caller's grid (n K_own + 1 for Neumann, else m)
+  int n = 0, K = 0, m = 0, mu = 0;
   double X = 0, scale = 0;
   AxisTab t64{}, t32{};
   const double* A = nullptr;
@@ -111,7 +114,8 @@ struct hofem_solver_s {
   double alpha = 0;
   int device = 0;
   DevAxis ax[3];
-  size_t per_rhs = 0;
+  size_t per_rhs = 0;   // unknowns of one right-hand side (the caller's grid)
+  size_t per_ext = 0;   // the grid the passes run on (Neumann axes reflected)
   // per-pass timing
   bool timing = false;
   std::vector<hipEvent_t> event_pool;
@@ -226,11 +230,11 @@ int run_list(hofem_solver_s* S, const std::vector<PassSpec>& list, bool f64, con
       if (list[i].il_out) a.ilv_out = rows;
     }
     static const int in_bytes[6] = {8, 4, 8, 4, 4, 8}, out_bytes[6] = {8, 4, 4, 8, 16, 8};
-    const double bytes = (double)S->per_rhs * nrhs * (in_bytes[dt] + out_bytes[dt]);
+    const double bytes = (double)S->per_ext * nrhs * (in_bytes[dt] + out_bytes[dt]);
     LaunchTimer tm(S, st, list[i].kind == PASS_INV_ACC ? PASS_INV : list[i].kind, list[i].axis,
                    f64 ? 1 : 0, bytes);
-    if (S->ax[list[i].axis].bc == 1) {
-      if (dt != 0) return HOFEM_EUNSUPPORTED;   // periodic axes: FP64 passes only
+    if (S->ax[list[i].axis].bc != 0) {
+      if (dt != 0) return HOFEM_EUNSUPPORTED;   // periodic / Neumann axes: FP64 passes only
       HIPCHK(launch_periodic(list[i].kind, a, st));
     } else {
       HIPCHK(launch_pass(list[i].kind, dt, a, st));
@@ -324,6 +328,29 @@ bool all_dirichlet(const hofem_solver_s* S) {
   for (int i = 0; i < S->N; ++i)
     if (S->ax[i].bc != 0) return false;
   return true;
+}
+
+bool has_neumann(const hofem_solver_s* S) {
+  for (int i = 0; i < S->N; ++i)
+    if (S->ax[i].bc == 2) return true;
+  return false;
+}
+
+// Workspace of an FP64 solve with Neumann axes: the reflected grid.
+size_t neumann_bytes(const hofem_solver_s* S, int nrhs) {
+  return (S->per_ext * (size_t)nrhs * sizeof(double) + 255) & ~size_t(255);
+}
+
+EvenArgs even_args(const hofem_solver_s* S, int nrhs) {
+  EvenArgs e{};
+  e.N = S->N;
+  for (int i = 0; i < S->N; ++i) {
+    e.me[i] = S->ax[i].m;
+    e.mu[i] = S->ax[i].mu;
+    e.neu[i] = S->ax[i].bc == 2 ? 1 : 0;
+  }
+  e.nrhs = nrhs;
+  return e;
 }
 
 size_t ir_workspace(const hofem_solver_s* S, int nrhs) {
@@ -573,8 +600,8 @@ namespace {
 std::vector<unsigned char> pack_plan(const Plan1DData& d, PlanOff* off) {
   Packer pk;
   const int n = d.n, K = d.K;
-  if (d.bc == 1) {
-    // periodic: eigenvalues, Bloch eigenvectors (complex FP64, blocked by
+  if (d.bc != 0) {
+    // periodic (and Neumann: the periodic axis of 2K elements): eigenvalues, Bloch eigenvectors (complex FP64, blocked by
     // 64 wave numbers: entry e = l n + s of wave number k at
     // ((k / 64) n^2 + e) 64 + k % 64, so that a wavefront reads one entry
     // of 64 consecutive k with one contiguous 1 KB access), twiddles, local
@@ -693,12 +720,13 @@ int hofem_plan1d_create(int n, int K, hofem_plan1d* out) {
 
 int hofem_plan1d_create_bc(int n, int K, int bc, hofem_plan1d* out) {
   if (!out) return HOFEM_EINVAL;
-  if (bc != HOFEM_BC_DIRICHLET && bc != HOFEM_BC_PERIODIC) return HOFEM_EINVAL;
+  if (bc != HOFEM_BC_DIRICHLET && bc != HOFEM_BC_PERIODIC && bc != HOFEM_BC_NEUMANN) return HOFEM_EINVAL;
   if (n < 1 || n > 9 || K < 2 || K > 1024 || (K & (K - 1)) != 0) return HOFEM_EUNSUPPORTED;
   hofem_plan1d p = new (std::nothrow) hofem_plan1d_s;
   if (!p) return HOFEM_ENOMEM;
-  const int rc = bc == HOFEM_BC_PERIODIC ? plan1d_build_periodic(n, K, &p->d)
-                                         : plan1d_build(n, K, &p->d);
+  const int rc = bc == HOFEM_BC_PERIODIC  ? plan1d_build_periodic(n, K, &p->d)
+                 : bc == HOFEM_BC_NEUMANN ? plan1d_build_neumann(n, K, &p->d)
+                                          : plan1d_build(n, K, &p->d);
   if (rc != 0) {
     delete p;
     return HOFEM_EUNSUPPORTED;
@@ -731,7 +759,7 @@ void hofem_plan1d_destroy(hofem_plan1d plan) { delete plan; }
 
 int hofem_plan1d_dim(hofem_plan1d plan, int* m) {
   if (!plan || !m) return HOFEM_EINVAL;
-  *m = plan->d.m;
+  *m = plan->d.mu;
   return HOFEM_OK;
 }
 
@@ -742,7 +770,7 @@ int hofem_plan1d_table(hofem_plan1d plan, int which, double* out_host, size_t le
   const std::vector<double>* v = nullptr;
   size_t count = 0;
   const bool dirichlet_only = which == 1 || which == 2, periodic_only = which == 10 || which == 11;
-  if ((dirichlet_only && d.bc != 0) || (periodic_only && d.bc != 1)) return HOFEM_EINVAL;
+  if ((dirichlet_only && d.bc != 0) || (periodic_only && d.bc == 0)) return HOFEM_EINVAL;
   switch (which) {
     case 0: v = &d.lam; count = d.m; break;
     case 1: v = &d.p; count = (size_t)(K - 1) * n * (n - 1); break;
@@ -777,7 +805,7 @@ int hofem_solver_create(int N, const hofem_plan1d* plans, const double* X, doubl
   double dmin = alpha;
   for (int i = 0; i < N; ++i) {
     const Plan1DData& d = plans[i]->d;
-    const double h = X[i] / d.K;
+    const double h = X[i] / d.kn;
     dmin += 4.0 / (h * h) * *std::min_element(d.lam.begin(), d.lam.end());
   }
   if (!(dmin > 0)) return HOFEM_ENOTPOSDEF;
@@ -795,6 +823,7 @@ int hofem_solver_create(int N, const hofem_plan1d* plans, const double* X, doubl
   S->N = N;
   S->alpha = alpha;
   S->per_rhs = 1;
+  S->per_ext = 1;
   S->device = cur;
   for (int i = 0; i < N; ++i) {
     const hofem_plan1d_s* P = plans[i];
@@ -804,10 +833,12 @@ int hofem_solver_create(int N, const hofem_plan1d* plans, const double* X, doubl
     ax.n = d.n;
     ax.K = d.K;
     ax.m = d.m;
+    ax.mu = d.mu;
     ax.X = X[i];
-    const double h = X[i] / d.K;
+    const double h = X[i] / d.kn;
     ax.scale = 4.0 / (h * h);
-    S->per_rhs *= (size_t)d.m;
+    S->per_rhs *= (size_t)d.mu;
+    S->per_ext *= (size_t)d.m;
     ax.hA = d.A;
     ax.hC = d.C;
     const unsigned char* b = P->dev;
@@ -883,7 +914,7 @@ int hofem_solver_size(hofem_solver solver, size_t* unknowns) {
 int hofem_solver_workspace_bytes(hofem_solver solver, int mode, int nrhs, size_t* bytes) {
   if (!solver || !bytes || nrhs < 1) return HOFEM_EINVAL;
   switch (mode) {
-    case HOFEM_MODE_FP64:
+    case HOFEM_MODE_FP64: *bytes = has_neumann(solver) ? neumann_bytes(solver, nrhs) : 0; return HOFEM_OK;
     case HOFEM_MODE_FP32:
     case HOFEM_MODE_FP64_B: *bytes = 0; return HOFEM_OK;
     case HOFEM_MODE_FP32_IR: *bytes = ir_workspace(solver, nrhs); return HOFEM_OK;
@@ -896,6 +927,8 @@ int hofem_solve(hofem_solver S, int mode, const void* f_dev, void* u_dev, int nr
                 size_t ws_bytes, int max_iter, double tol, void* stream, hofem_info* info) {
   if (!S || !f_dev || !u_dev || nrhs < 1) return HOFEM_EINVAL;
   if (mode != HOFEM_MODE_FP64 && !all_dirichlet(S)) return HOFEM_EUNSUPPORTED;
+  if (mode == HOFEM_MODE_FP64 && has_neumann(S) && (!ws_dev || ws_bytes < neumann_bytes(S, nrhs)))
+    return HOFEM_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   // graph replay: solves without host synchronisation, on a stream that can
   // be captured
@@ -954,6 +987,18 @@ int hofem_solve(hofem_solver S, int mode, const void* f_dev, void* u_dev, int nr
     return HOFEM_OK;
   }
   const std::vector<PassSpec> list = solve_list(S, mode == HOFEM_MODE_FP64, nrhs);
+  if (mode == HOFEM_MODE_FP64 && has_neumann(S)) {
+    // Neumann axes: reflect f^h (boundary rows doubled) into the workspace,
+    // solve the periodic problem there in place, keep the caller's half
+    double* e = static_cast<double*>(ws_dev);
+    const EvenArgs ea = even_args(S, nrhs);
+    HIPCHK(launch_even_extend(ea, static_cast<const double*>(f_dev), e, st));
+    const int rc = run_list(S, list, true, e, e, e, 0, 0, 0, 0, nrhs, st);
+    if (rc != HOFEM_OK) return rc;
+    HIPCHK(launch_even_restrict(ea, e, static_cast<double*>(u_dev), st));
+    if (info) *info = hofem_info{0, 0.0, 0.0};
+    return HOFEM_OK;
+  }
   if (mode == HOFEM_MODE_FP64 || mode == HOFEM_MODE_FP32) {
     const bool f64 = mode == HOFEM_MODE_FP64;
     const int dt = f64 ? 0 : 1;
@@ -1069,6 +1114,7 @@ int hofem_forward(hofem_solver S, int mode, const void* in_dev, void* out_dev, i
   if (!S || !in_dev || !out_dev || nrhs < 1) return HOFEM_EINVAL;
   if (mode != HOFEM_MODE_FP64 && !all_dirichlet(S)) return HOFEM_EUNSUPPORTED;
   if (mode != HOFEM_MODE_FP64 && mode != HOFEM_MODE_FP32) return HOFEM_EINVAL;
+  if (has_neumann(S)) return HOFEM_EUNSUPPORTED;   // coefficients of the reflected grid
   const bool f64 = mode == HOFEM_MODE_FP64;
   const int dt = f64 ? 0 : 1;
   std::vector<PassSpec> l;
@@ -1082,6 +1128,7 @@ int hofem_inverse(hofem_solver S, int mode, const void* in_dev, void* out_dev, i
   if (!S || !in_dev || !out_dev || nrhs < 1) return HOFEM_EINVAL;
   if (mode != HOFEM_MODE_FP64 && !all_dirichlet(S)) return HOFEM_EUNSUPPORTED;
   if (mode != HOFEM_MODE_FP64 && mode != HOFEM_MODE_FP32) return HOFEM_EINVAL;
+  if (has_neumann(S)) return HOFEM_EUNSUPPORTED;   // coefficients of the reflected grid
   const bool f64 = mode == HOFEM_MODE_FP64;
   const int dt = f64 ? 0 : 1;
   std::vector<PassSpec> l;

@@ -154,6 +154,22 @@ hipError_t launch_banded(const BandArgs& a, hipStream_t s);
 // eigenvalues in the periodic coefficient order.
 hipError_t launch_periodic(int kind, const PassArgs& a, hipStream_t s);
 
+// Neumann axes by even reflection.  Axis i of the caller's grid has mu[i]
+// points (n K + 1 on a Neumann axis: g = 0..nK), of the reflected grid me[i]
+// (2 n K: g' = 0..2nK-1, point g' = 2nK - g' of the mirror half).  extend:
+// e(g') = prod_i d_i f(g), g = g' or its mirror, d_i = 2 at the boundary
+// nodes g = 0, nK of a Neumann axis (the reflected pencil counts their rows
+// twice), else 1.  restrict: u(g) = e(g) on the caller's grid.  C order,
+// nrhs grids in sequence.
+struct EvenArgs {
+  int N;
+  long long me[3], mu[3];
+  int neu[3];
+  int nrhs;
+};
+hipError_t launch_even_extend(const EvenArgs& a, const double* f, double* e, hipStream_t s);
+hipError_t launch_even_restrict(const EvenArgs& a, const double* e, double* u, hipStream_t s);
+
 // u += delta over `count` elements with per-workgroup partial sums of
 // delta^2 and u^2 (nparts workgroups), reduced to out[0..1] by a second
 // launch (fixed order: deterministic).

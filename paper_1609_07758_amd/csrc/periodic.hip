@@ -290,7 +290,69 @@ hipError_t launch_per_mode(const PassArgs& a, hipStream_t s) {
   }
 }
 
+// One thread per point of the reflected grid: its point in the caller's grid
+// and the boundary weights of the Neumann axes.
+__global__ __launch_bounds__(256) void even_extend_kernel(EvenArgs a, const double* __restrict__ f,
+                                                          double* __restrict__ e, long long total) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  long long r = i, src = 0, mul = 1;
+  double w = 1.0;
+  for (int d = a.N - 1; d >= 0; --d) {
+    long long g = r % a.me[d];
+    r /= a.me[d];
+    if (a.neu[d]) {
+      const long long half = a.me[d] / 2;   // nK: the far boundary node
+      if (g > half) g = a.me[d] - g;
+      if (g == 0 || g == half) w *= 2.0;
+    }
+    src += g * mul;
+    mul *= a.mu[d];
+  }
+  src += r * mul;   // right-hand side
+  e[i] = w * f[src];
+}
+
+__global__ __launch_bounds__(256) void even_restrict_kernel(EvenArgs a, const double* __restrict__ e,
+                                                            double* __restrict__ u, long long total) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  long long r = i, src = 0, mul = 1;
+  for (int d = a.N - 1; d >= 0; --d) {
+    const long long g = r % a.mu[d];
+    r /= a.mu[d];
+    src += g * mul;
+    mul *= a.me[d];
+  }
+  src += r * mul;
+  u[i] = e[src];
+}
+
+long long grid_points(const long long* m, int N, int nrhs) {
+  long long t = nrhs;
+  for (int d = 0; d < N; ++d) t *= m[d];
+  return t;
+}
+
 }  // namespace
+
+hipError_t launch_even_extend(const EvenArgs& a, const double* f, double* e, hipStream_t s) {
+  if (a.N < 1 || a.N > 3 || a.nrhs < 1) return hipErrorInvalidValue;
+  const long long total = grid_points(a.me, a.N, a.nrhs);
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(even_extend_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a, f,
+                     e, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_even_restrict(const EvenArgs& a, const double* e, double* u, hipStream_t s) {
+  if (a.N < 1 || a.N > 3 || a.nrhs < 1) return hipErrorInvalidValue;
+  const long long total = grid_points(a.mu, a.N, a.nrhs);
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(even_restrict_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a, e,
+                     u, total);
+  return hipGetLastError();
+}
 
 hipError_t launch_periodic(int kind, const PassArgs& a, hipStream_t s) {
   if (a.nlines == 0) return hipSuccess;

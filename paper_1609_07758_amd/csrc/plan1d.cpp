@@ -295,6 +295,8 @@ int plan1d_build(int n, int K, Plan1DData* out) {
   out->n = n;
   out->K = K;
   out->m = m;
+  out->kn = K;
+  out->mu = m;
   out->A.assign(nb * nb, 0);
   out->C.assign(nb * nb, 0);
   for (int i = 0; i < nb * nb; ++i) {
@@ -509,6 +511,17 @@ int plan1d_build_periodic(int n, int K, Plan1DData* out) {
       }
     }
   }
+  out->kn = K;
+  out->mu = m;
+  return 0;
+}
+
+int plan1d_build_neumann(int n, int K, Plan1DData* out) {
+  if (K < 2 || K > 512 || (K & (K - 1)) != 0) return -1;
+  if (plan1d_build_periodic(n, 2 * K, out) != 0) return -1;
+  out->bc = 2;
+  out->kn = K;
+  out->mu = n * K + 1;
   return 0;
 }
 

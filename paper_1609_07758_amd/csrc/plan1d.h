@@ -10,8 +10,12 @@ namespace hofem {
 //   k = 0, l = 1..n-1      ->  q = l - 1
 //   k = 1..K-1, l = 1..n   ->  q = (n - 1) + (l - 1)(K - 1) + (k - 1)
 struct Plan1DData {
-  int bc = 0;                    // 0: Dirichlet, 1: periodic
+  int bc = 0;                    // 0: Dirichlet, 1: periodic, 2: Neumann
   int n = 0, K = 0, m = 0;
+  // Neumann axes carry the tables of the periodic axis of 2K elements (K, m
+  // above are 2K, 2nK): kn is the axis's own element count, mu its number of
+  // unknowns nK + 1.  Otherwise kn = K and mu = m.
+  int kn = 0, mu = 0;
   std::vector<double> A, C;      // local stiffness / mass on [-1,1], (n+1)^2 row major
   std::vector<double> lam;       // scaled eigenvalues in coefficient order (m)
   std::vector<double> p;         // p_k^(l): [(k-1) n + (l-1)] * (n-1) + i, i = 0..n-2
@@ -41,5 +45,9 @@ int plan1d_build(int n, int K, Plan1DData* out);
 // wave number k = 1..K/2-1; t = K-1: k = K/2) and the Bloch eigenvectors.
 // Returns 0 on success, -1 for unsupported (n, K).
 int plan1d_build_periodic(int n, int K, Plan1DData* out);
+// Neumann axis of K elements (m = nK + 1 unknowns, the points g h / n,
+// g = 0..nK, boundary nodes included): its even reflection is the periodic
+// axis of 2K elements on [-X, X), whose tables it carries (K <= 512).
+int plan1d_build_neumann(int n, int K, Plan1DData* out);
 
 }  // namespace hofem

@@ -171,5 +171,28 @@ def test_periodic_plan_tables(n, K):
 def test_periodic_plan_rejects_bad_bc():
     h = ctypes.c_void_p()
     lib = ctypes.CDLL(H.LIB_PATH)
-    assert lib.hofem_plan1d_create_bc(2, 8, 2, ctypes.byref(h)) == -1
+    assert lib.hofem_plan1d_create_bc(2, 8, 3, ctypes.byref(h)) == -1
     assert lib.hofem_plan1d_create_bc(2, 6, 1, ctypes.byref(h)) == -2
+
+
+def test_neumann_plan_dims_and_tables():
+    # a Neumann plan has nK + 1 unknowns and carries the periodic tables of
+    # 2K elements (its even reflection); K above 512 is refused
+    P = H.Plan1D(3, 8, "neumann")
+    try:
+        assert P.m == 3 * 8 + 1
+        lam = P.table("lam")
+        assert lam.size == 3 * 16 and lam[0] == 0.0
+        Q = H.Plan1D(3, 16, "periodic")
+        try:
+            assert np.array_equal(lam, Q.table("lam"))
+            assert np.array_equal(P.table("wr"), Q.table("wr"))
+        finally:
+            Q.close()
+    finally:
+        P.close()
+    h = ctypes.c_void_p()
+    lib = ctypes.CDLL(H.LIB_PATH)
+    assert lib.hofem_plan1d_create_bc(2, 1024, 2, ctypes.byref(h)) == -2
+    assert lib.hofem_plan1d_create_bc(2, 512, 2, ctypes.byref(h)) == 0
+    lib.hofem_plan1d_destroy(h)

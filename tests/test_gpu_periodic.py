@@ -1,4 +1,5 @@
-"""GPU parity of periodic axes (Bloch-wave line passes, FP64) against the oracle.
+"""GPU parity of periodic and Neumann axes (Bloch-wave line passes, FP64)
+against the oracle.
 
 Small grids: the sparse direct solve of the assembled operator
 (oracle.periodic), relative l2 <= 1e-12, in 1D, 2D and 3D with every mix of
@@ -27,7 +28,7 @@ if not torch.cuda.is_available():
 H = pytest.importorskip("paper_1609_07758_amd")
 
 DEV = "cuda:0"
-P, D = "periodic", "dirichlet"
+P, D, NM = "periodic", "dirichlet", "neumann"
 
 
 def rel(a, b):
@@ -177,4 +178,78 @@ def test_periodic_full_size_backward_error():
             + alpha * inf(mats[0][1]) * inf(mats[1][1]))
     eta = np.linalg.norm(r) / (Linf * np.linalg.norm(u) + np.linalg.norm(f))
     print(f"backward error, full size: {eta:.3e}")
+    assert eta < 1e-15
+
+
+# Neumann axes (even reflection onto the periodic axis of 2K elements)
+NEUMANN = [
+    ((1,), (4,), (1.0,), 0.5, (NM,)),
+    ((2,), (8,), (1.0,), 2.0, (NM,)),
+    ((3,), (16,), (2.0,), 1.0, (NM,)),
+    ((9,), (512,), (1.0,), 1.0, (NM,)),
+    ((5,), (2,), (1.0,), 0.25, (NM,)),
+    ((3, 2), (8, 16), (1.0, 1.0), 0.0, (NM, D)),
+    ((2, 4), (16, 8), (1.0, 0.5), 0.0, (D, NM)),
+    ((4, 3), (8, 8), (1.0, 1.0), 1.0, (NM, NM)),
+    ((2, 3), (16, 8), (1.0, 1.0), 0.5, (NM, P)),
+    ((2, 3, 2), (8, 4, 8), (1.0, 1.0, 1.0), 0.0, (NM, D, P)),
+    ((3, 2, 2), (4, 8, 4), (1.0, 1.0, 1.0), 1.0, (NM, NM, NM)),
+]
+
+
+@pytest.mark.parametrize("orders,Ks,X,alpha,bcs", NEUMANN)
+def test_neumann_solve_matches_oracle(orders, Ks, X, alpha, bcs):
+    shp = grid(orders, Ks, bcs)
+    f = workloads.uniform_rhs(shp, seed=3)
+    S = H.Solver(orders, Ks, X, alpha, bcs=bcs)
+    try:
+        assert S.shape == shp
+        u = S.solve(torch.from_numpy(f).to(DEV)).cpu().numpy()
+    finally:
+        S.close()
+    want = periodic.solve(f, orders, Ks, X, alpha, bcs)
+    assert rel(u, want) < 1e-12
+
+
+def test_neumann_several_rhs_and_workspace():
+    orders, Ks, X, alpha, bcs = (3, 2), (8, 16), (1.0, 1.0), 0.0, (NM, D)
+    shp = grid(orders, Ks, bcs)
+    f = workloads.uniform_rhs((2,) + shp, seed=4)
+    S = H.Solver(orders, Ks, X, alpha, bcs=bcs)
+    try:
+        fd = torch.from_numpy(f).to(DEV).reshape(-1)
+        u = torch.empty_like(fd)
+        with pytest.raises(H.HofemError) as e:   # the reflected grid is required
+            H.hofem_solve(S.handle, "fp64", fd, u, 2, None, 0, 0.0, None, False, True)
+        assert e.value.status == -1
+        u = S.solve(fd, nrhs=2).cpu().numpy().reshape(f.shape)
+        with pytest.raises(H.HofemError) as e:
+            S.forward(fd)
+        assert e.value.status == -2
+    finally:
+        S.close()
+    for r in range(2):
+        assert rel(u[r], periodic.solve(f[r], orders, Ks, X, alpha, bcs)) < 1e-12
+
+
+@pytest.mark.slow
+def test_neumann_full_size_backward_error():
+    # n = 9, K = 512 on both Neumann axes (21,242,881 unknowns; the passes run
+    # on the reflected 9216 x 9216 grid)
+    orders, Ks, X, alpha, bcs = (9, 9), (512, 512), (1.0, 1.0), 1.0, (NM, NM)
+    shp = grid(orders, Ks, bcs)
+    f = workloads.uniform_rhs(shp, seed=9)
+    S = H.Solver(orders, Ks, X, alpha, bcs=bcs)
+    try:
+        u = S.solve(torch.from_numpy(f).to(DEV)).cpu().numpy()
+    finally:
+        S.close()
+    r = f - periodic.apply_operator(u, orders, Ks, X, alpha, bcs)
+    mats = [periodic.axis_matrices(n, K, b) for n, K, b in zip(orders, Ks, bcs)]
+    inf = lambda M: float(abs(M).sum(axis=1).max())
+    s = [4.0 * K ** 2 / x ** 2 for K, x in zip(Ks, X)]
+    Linf = (s[0] * inf(mats[0][0]) * inf(mats[1][1]) + s[1] * inf(mats[0][1]) * inf(mats[1][0])
+            + alpha * inf(mats[0][1]) * inf(mats[1][1]))
+    eta = np.linalg.norm(r) / (Linf * np.linalg.norm(u) + np.linalg.norm(f))
+    print(f"Neumann backward error, full size: {eta:.3e}")
     assert eta < 1e-15

@@ -1,4 +1,5 @@
-"""Pins of the periodic-axis oracle (oracle.periodic) to facts outside it.
+"""Pins of the periodic- and Neumann-axis oracle (oracle.periodic) to facts
+outside it.
 
 * the stiffness annihilates the constants; the mass integrates 1 to the
   length (2K on reference elements);
@@ -11,7 +12,13 @@
   also along one axis of a 2D problem with the other axis Dirichlet;
 * convergence: a smooth periodic solution is reproduced at order >= n + 1;
 * brute force: on tiny, badly conditioned systems the corrected solve equals
-  exact rational elimination of the exact FEM system to 4 ulps.
+  exact rational elimination of the exact FEM system to 4 ulps;
+* Neumann axes: constants in the stiffness kernel, total mass 2K, the n = 1
+  closed form 3(1 - cos t)/(2(2 + cos t)), t = pi k / K, k = 0..K, even
+  reflection (the periodic problem of 2K elements with the reflected
+  right-hand side, boundary rows doubled, restricts to the Neumann
+  solution), convergence at order >= n + 1 for a smooth solution with zero
+  end slopes, and exact elimination.
 """
 import numpy as np
 import pytest
@@ -123,7 +130,7 @@ def _exact_dense_1d(n, K, bc):
     from fractions import Fraction
     from oracle.element import local_matrices
     A, C = local_matrices(n)
-    m = n * K if bc == "periodic" else n * K - 1
+    m = {"periodic": n * K, "neumann": n * K + 1}.get(bc, n * K - 1)
     Ag = [[Fraction(0)] * m for _ in range(m)]
     Cg = [[Fraction(0)] * m for _ in range(m)]
     for j in range(K):
@@ -132,6 +139,8 @@ def _exact_dense_1d(n, K, bc):
                 gr, gs = n * j + r, n * j + s
                 if bc == "periodic":
                     qr, qs = gr % m, gs % m
+                elif bc == "neumann":
+                    qr, qs = gr, gs
                 elif 0 < gr < n * K and 0 < gs < n * K:
                     qr, qs = gr - 1, gs - 1
                 else:
@@ -166,6 +175,8 @@ def _exact_solve(L, f):
     ((3,), (4,), (1.0,), 1e-3, ("periodic",)),
     ((2, 2), (3, 2), (1.0, 0.5), 0.0, ("periodic", "dirichlet")),
     ((4,), (2,), (2.0,), 1e-4, ("periodic",)),
+    ((3,), (4,), (1.0,), 1e-3, ("neumann",)),
+    ((2, 2), (2, 3), (1.0, 0.5), 0.0, ("neumann", "dirichlet")),
 ])
 def test_corrected_solve_is_the_exact_solution(ns, Ks, Xs, alpha, bcs):
     # brute force: exact rational elimination of the exact FEM system
@@ -190,3 +201,71 @@ def test_corrected_solve_is_the_exact_solution(ns, Ks, Xs, alpha, bcs):
     want = np.array([float(x) for x in _exact_solve(L, f.ravel().tolist())]).reshape(shp)
     got = periodic.solve(f, ns, Ks, Xs, alpha, bcs)
     assert np.max(np.abs(got - want)) <= 4 * np.finfo(float).eps * np.max(np.abs(want))
+
+
+@pytest.mark.parametrize("n,K", [(1, 4), (2, 5), (4, 3), (9, 4)])
+def test_neumann_constants_and_total_mass(n, K):
+    A, C = [M.toarray() for M in periodic.axis_matrices(n, K, "neumann")]
+    one = np.ones(n * K + 1)
+    assert np.max(np.abs(A @ one)) < 1e-13 * np.max(np.abs(A))
+    assert abs(one @ C @ one - 2.0 * K) < 1e-12 * K
+
+
+@pytest.mark.parametrize("K", [3, 8, 16])
+def test_neumann_linear_spectrum_closed_form(K):
+    import scipy.linalg as sla
+    A, C = [M.toarray() for M in periodic.axis_matrices(1, K, "neumann")]
+    got = np.sort(sla.eigh(A, C, eigvals_only=True))
+    t = np.pi * np.arange(K + 1) / K
+    want = np.sort(3.0 * (1.0 - np.cos(t)) / (2.0 * (2.0 + np.cos(t))))
+    assert np.max(np.abs(got - want)) < 1e-13
+
+
+def even_extension(fn, n, K, axis):
+    """Right-hand side on the periodic axis of 2K elements, even about x = 0:
+    position g' holds fn at g' (g' <= nK) or 2nK - g', the boundary values
+    (g = 0, nK) doubled."""
+    fn = np.moveaxis(np.asarray(fn, dtype=np.float64), axis, 0)
+    m = n * K
+    w = fn.copy()
+    w[0] *= 2.0
+    w[m] *= 2.0
+    out = np.concatenate([w[:m + 1], w[1:m][::-1]], axis=0)
+    return np.moveaxis(out, 0, axis)
+
+
+@pytest.mark.parametrize("n,K,alpha", [(1, 8, 0.5), (2, 4, 0.7), (3, 8, 2.0), (5, 4, 0.1)])
+def test_neumann_even_extension_1d(n, K, alpha):
+    X = 1.3
+    fn = workloads.uniform_rhs((n * K + 1,), seed=13)
+    want = periodic.solve(fn, (n,), (K,), (X,), alpha, ("neumann",))
+    got = periodic.solve(even_extension(fn, n, K, 0), (n,), (2 * K,), (2 * X,), alpha, ("periodic",))
+    assert np.max(np.abs(got[:n * K + 1] - want)) < 1e-12 * np.max(np.abs(want))
+    assert np.max(np.abs(got[n * K + 1:] - want[1:n * K][::-1])) < 1e-12 * np.max(np.abs(want))
+
+
+def test_neumann_even_extension_2d_mixed():
+    ns, Ks, Xs, alpha = (2, 3), (4, 4), (1.0, 0.7), 0.0
+    fn = workloads.uniform_rhs((ns[0] * Ks[0] + 1, ns[1] * Ks[1] - 1), seed=14)
+    want = periodic.solve(fn, ns, Ks, Xs, alpha, ("neumann", "dirichlet"))
+    got = periodic.solve(even_extension(fn, ns[0], Ks[0], 0), ns, (2 * Ks[0], Ks[1]),
+                         (2 * Xs[0], Xs[1]), alpha, ("periodic", "dirichlet"))
+    assert np.max(np.abs(got[:ns[0] * Ks[0] + 1] - want)) < 1e-12 * np.max(np.abs(want))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_neumann_smooth_solution_converges(n):
+    # -u'' + alpha u = f on [0, X] with u = cos(pi x / X) + 0.5 cos(3 pi x / X)
+    # (zero slope at both ends); right-hand side C I f as in the periodic test
+    X, alpha = 1.0, 2.0
+    errs = []
+    for K in (8, 16, 32):
+        x = np.arange(n * K + 1) * X / (n * K)
+        w1, w3 = np.pi / X, 3 * np.pi / X
+        u = np.cos(w1 * x) + 0.5 * np.cos(w3 * x)
+        f = (w1 ** 2 + alpha) * np.cos(w1 * x) + 0.5 * (w3 ** 2 + alpha) * np.cos(w3 * x)
+        C = periodic.axis_matrices(n, K, "neumann")[1].toarray()
+        v = periodic.solve(C @ f, (n,), (K,), (X,), alpha, ("neumann",))
+        errs.append(np.max(np.abs(v - u)))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > n + 1 - 0.3), (errs, rates)
