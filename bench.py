@@ -190,7 +190,7 @@ def bench_headline(args, torch, H, np, workloads, dev):
                          args.warmup)
     del bext, lift, uh
 
-    log("large_2d: periodic and Neumann axes")
+    log("large_2d: periodic, Neumann and non-power-of-two axes")
     # the same orders and meshes with both axes periodic (alpha = 1): Bloch
     # waves, m = nK per axis
     Sp = H.Solver(cfg["orders"], cfg["Ks"], cfg["X"], 1.0, bcs=("periodic", "periodic"))
@@ -213,6 +213,17 @@ def bench_headline(args, torch, H, np, workloads, dev):
     M_neu = Sn.size
     Sn.close()
     del fn_, un_, wsn
+    # K not a power of two (n = 9, K = 384 per axis): dense eigenvector
+    # transforms on the FP64 matrix cores, four m^3 products per solve
+    Sd = H.Solver(cfg["orders"], (384, 384), cfg["X"], cfg["alpha"])
+    fd_ = torch.rand(Sd.size, dtype=torch.float64, device=dev)
+    ud_ = torch.empty_like(fd_)
+    wsd = Sd.workspace("fp64")
+    ms_dense = time_calls(torch, lambda: Sd.solve(fd_, ud_, mode="fp64", ws=wsd), args.steps, args.warmup)
+    m_d = Sd.shape[0]
+    M_dense = Sd.size
+    Sd.close()
+    del fd_, ud_, wsd
 
     log("large_2d: autotuned launch shapes (FP64)")
     tune = S.autotune("fp64", nrhs=1, reps=3, f=f64, u=u64)
@@ -269,6 +280,11 @@ def bench_headline(args, torch, H, np, workloads, dev):
                        "unknowns_per_s": M / (ms_heat * 1e-3),
                        "note": "backward Euler step: mass update + FP64 solve, HIP-graph replay"},
         "dirichlet_lift": {"ms": ms_lift, "unknowns_per_s": M / (ms_lift * 1e-3)},
+        "dense_fp64": {"unknowns": M_dense, "orders": cfg["orders"], "K_per_axis": 384,
+                       "ms_per_step": ms_dense, "unknowns_per_s": M_dense / (ms_dense * 1e-3),
+                       "tflops": 8.0 * m_d ** 3 / (ms_dense * 1e-3) / 1e12,
+                       "tflops_frac_of_fp64_mfma": 8.0 * m_d ** 3 / (ms_dense * 1e-3) / 1e12 / 78.6,
+                       "note": "K not a power of two: four dense m x m products per solve (FP64 MFMA)"},
         "neumann_fp64": {"unknowns": M_neu, "orders": cfg["orders"], "K_per_axis": 512, "alpha": 1.0,
                          "ms_per_step": ms_neu, "unknowns_per_s": M_neu / (ms_neu * 1e-3),
                          "note": "even reflection onto the periodic grid of 2K elements per axis"},

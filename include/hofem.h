@@ -104,8 +104,8 @@ typedef struct {
  * norms ||s_k^(l)||_C^2 of the transform theorem, and the interior-node
  * eigenpairs of eq. (eig_elem).  Computed on the host in binary128 and
  * rounded once.  1 <= n <= 9 (simple element spectra are verified up to 9),
- * K a power of two with 2 <= K <= 1024.  Returns HOFEM_EUNSUPPORTED
- * otherwise.  A plan changes only in hofem_plan1d_upload; otherwise it is
+ * 2 <= K <= 1024, and nK - 1 <= 4095 when K is not a power of two.
+ * Returns HOFEM_EUNSUPPORTED otherwise.  A plan changes only in hofem_plan1d_upload; otherwise it is
  * read-only and may be shared between threads. */
 int hofem_plan1d_create(int n, int K, hofem_plan1d* out);
 
@@ -163,9 +163,22 @@ int hofem_plan1d_dim(hofem_plan1d plan, int* m);
  *   9  basis derivatives e_r'(x_q) at index q (n+1) + r   ((n+1)^2 values)
  *  10  periodic plans: Re w_{k,l,s} at index (k n + l) n + s, k = 0..K/2 ((K/2+1) n^2)
  *  11  periodic plans: Im w_{k,l,s}, the same layout
+ *  12  plans with K not a power of two: S, the unnormalised eigenvectors of
+ *      Theorem 1 as columns in coefficient order, row major (m^2 values)
+ *  13  the same plans: S diag(1 / ||s||_C^2) (1/K for the k = 0 columns)
  * Tables 1 and 2 exist for Dirichlet plans only, 10 and 11 for periodic
- * plans only (HOFEM_EINVAL otherwise); table 0 of a periodic plan holds its
- * m = nK eigenvalues in the periodic coefficient order.
+ * plans only, 12 and 13 for dense ones (HOFEM_EINVAL otherwise); table 0 of
+ * a periodic plan holds its m = nK eigenvalues in the periodic coefficient
+ * order.
+ *
+ * K need not be a power of two for a Dirichlet axis: with m = nK - 1 <= 4095
+ * the plan then also holds S and its scaled form, and the solver applies
+ * them along that axis as dense products on the FP64 matrix cores (there is
+ * no power-of-two FFT); an FP64 solve of such a solver takes a workspace of
+ * one grid (hofem_solver_workspace_bytes), and only the FP64 solve, the
+ * operators, the mass product and the Dirichlet lift accept it
+ * (HOFEM_EUNSUPPORTED elsewhere).  Periodic and Neumann axes need K a
+ * power of two.
  * The coefficient index of a line is q = l-1 for k = 0 (l = 1..n-1) and
  * q = (n-1) + (l-1)(K-1) + (k-1) for k = 1..K-1 (l = 1..n): for each l the
  * wave numbers are consecutive.  `len` must equal the count; otherwise

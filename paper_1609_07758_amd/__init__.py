@@ -34,7 +34,7 @@ HOFEM_ETOOBIG = -7
 
 MODES = {"fp64": 0, "fp32": 1, "fp32_ir": 2, "fp32_pcg": 3, "fp64_b": 4}
 TABLES = {"lam": 0, "p": 1, "inorm": 2, "E": 3, "A": 4, "C": 5, "gx": 6, "gw": 7, "B": 8, "D": 9,
-          "wr": 10, "wi": 11}
+          "wr": 10, "wi": 11, "S": 12, "St": 13}
 BCS = {"dirichlet": 0, "periodic": 1, "neumann": 2}
 
 # Names and signatures of every entry point of include/hofem.h.
@@ -568,7 +568,8 @@ class Plan1D:
         counts = {"lam": nlam, "p": (K - 1) * n * (n - 1), "inorm": (K - 1) * n,
                   "E": (n - 1) ** 2, "A": (n + 1) ** 2, "C": (n + 1) ** 2,
                   "gx": n + 1, "gw": n + 1, "B": (n + 1) ** 2, "D": (n + 1) ** 2,
-                  "wr": (Kt // 2 + 1) * n * n, "wi": (Kt // 2 + 1) * n * n}
+                  "wr": (Kt // 2 + 1) * n * n, "wi": (Kt // 2 + 1) * n * n,
+                  "S": self.m * self.m, "St": self.m * self.m}
         return hofem_plan1d_table(self.handle, which, counts[which])
 
     def close(self):

@@ -32,6 +32,7 @@ using namespace hofem;
 // Byte offsets of one plan's tables in its device image (256-byte aligned).
 struct PlanOff {
   size_t lam, blk64, E64, tw64, sn64, blk32, E32, tw32, sn32, A, C, B, D, Dh, gw;
+  size_t S = 0, St = 0;   // dense axes (K not a power of two)
 };
 
 struct hofem_plan1d_s {
@@ -71,6 +72,11 @@ struct DevAxis {
   // elements on its even reflection: K = 2 K_own, m = 2 n K_own); mu: the
   // axis's unknowns in the caller's grid (n K_own + 1 for Neumann, else m)
   int n = 0, K = 0, m = 0, mu = 0;
+  // K not a power of two: transforms by the dense matrices S (inverse) and
+  // St = S diag(1 / ||s||^2) (forward: St^T y)
+  int dense = 0;
+  const double* S = nullptr;
+  const double* St = nullptr;
   double X = 0, scale = 0;
   AxisTab t64{}, t32{};
   const double* A = nullptr;
@@ -116,6 +122,7 @@ struct hofem_solver_s {
   DevAxis ax[3];
   size_t per_rhs = 0;   // unknowns of one right-hand side (the caller's grid)
   size_t per_ext = 0;   // the grid the passes run on (Neumann axes reflected)
+  double* dense_tmp = nullptr;   // scratch grid of the dense passes (set per solve)
   // per-pass timing
   bool timing = false;
   std::vector<hipEvent_t> event_pool;
@@ -202,6 +209,60 @@ PassArgs make_args(const hofem_solver_s* S, int axis, int kind, bool f64, const 
   return a;
 }
 
+// A pass along an axis whose K is not a power of two: the transforms are the
+// dense products with St^T (forward) and S (inverse) on the matrix cores;
+// the fused pass divides in between.  In place through the solver's dense
+// scratch grid.
+int dense_pass(hofem_solver_s* S, int axis, int kind, const PassArgs& a, const void* in, void* out,
+               hipStream_t st) {
+  const DevAxis& X = S->ax[axis];
+  const int m = X.m;
+  const long long inner = a.inner, outer = a.nlines / inner;
+  double* tmp = S->dense_tmp;
+  if (!tmp) return HOFEM_EINVAL;
+  auto apply = [&](const double* src, double* dst, bool fwd) -> hipError_t {
+    GemmArgs g{};
+    g.K = m;
+    if (inner == 1) {
+      // rows: dst (outer x m) = src St (forward) or src S^T (inverse)
+      g.A = src;
+      g.B = fwd ? X.St : X.S;
+      g.C = dst;
+      g.M = (int)outer;
+      g.N = m;
+      g.lda = g.ldb = g.ldc = m;
+      g.batch = 1;
+      return launch_dgemm(g, false, !fwd, st);
+    }
+    // strided: per block o of the outer axes, dst_o (m x inner) = St^T src_o or S src_o
+    g.A = fwd ? X.St : X.S;
+    g.B = src;
+    g.C = dst;
+    g.M = m;
+    g.N = (int)inner;
+    g.lda = m;
+    g.ldb = g.ldc = inner;
+    g.sb = g.sc = (long long)m * inner;
+    g.batch = outer;
+    return launch_dgemm(g, fwd, false, st);
+  };
+  if (outer > 0x7fffffffLL || inner > 0x7fffffffLL) return HOFEM_EUNSUPPORTED;
+  const double* src = static_cast<const double*>(in);
+  double* dst = static_cast<double*>(out);
+  const size_t bytes = (size_t)outer * m * inner * sizeof(double);
+  if (kind == PASS_FUSED) {
+    HIPCHK(apply(src, tmp, true));
+    HIPCHK(launch_dense_divide(tmp, outer, m, inner, a, st));
+    HIPCHK(apply(tmp, dst, false));
+  } else if (src != dst) {
+    HIPCHK(apply(src, dst, kind == PASS_FWD));
+  } else {
+    HIPCHK(apply(src, tmp, kind == PASS_FWD));
+    HIPCHK(hipMemcpyAsync(dst, tmp, bytes, hipMemcpyDeviceToDevice, st));
+  }
+  return HOFEM_OK;
+}
+
 // Runs a list of passes: the first reads in0, the last writes outl, the
 // others work in place on buf.  dt codes as in launch_pass.
 int run_list(hofem_solver_s* S, const std::vector<PassSpec>& list, bool f64, const void* in0,
@@ -233,7 +294,11 @@ int run_list(hofem_solver_s* S, const std::vector<PassSpec>& list, bool f64, con
     const double bytes = (double)S->per_ext * nrhs * (in_bytes[dt] + out_bytes[dt]);
     LaunchTimer tm(S, st, list[i].kind == PASS_INV_ACC ? PASS_INV : list[i].kind, list[i].axis,
                    f64 ? 1 : 0, bytes);
-    if (S->ax[list[i].axis].bc != 0) {
+    if (S->ax[list[i].axis].dense) {
+      if (dt != 0) return HOFEM_EUNSUPPORTED;   // dense axes: FP64 passes only
+      const int rc = dense_pass(S, list[i].axis, list[i].kind, a, in, out, st);
+      if (rc != HOFEM_OK) return rc;
+    } else if (S->ax[list[i].axis].bc != 0) {
       if (dt != 0) return HOFEM_EUNSUPPORTED;   // periodic / Neumann axes: FP64 passes only
       HIPCHK(launch_periodic(list[i].kind, a, st));
     } else {
@@ -256,7 +321,7 @@ std::vector<PassSpec> solve_list(const hofem_solver_s* S, bool f64, int nrhs) {
   for (int a = N - 1; a >= 1; --a) l.push_back({a, PASS_FWD});
   l.push_back({0, PASS_FUSED});
   for (int a = 1; a < N; ++a) l.push_back({a, PASS_INV});
-  if (N == 2 && S->ax[0].bc == 0 && S->ax[1].bc == 0 &&
+  if (N == 2 && S->ax[0].bc == 0 && S->ax[1].bc == 0 && !S->ax[0].dense && !S->ax[1].dense &&
       pass_lines_per_workgroup(S->ax[1].n, S->ax[1].K, f64, (long long)S->ax[0].m * nrhs) == 2) {
     l[0].il_out = true;
     l[1].il_in = l[1].il_out = true;
@@ -328,6 +393,17 @@ bool all_dirichlet(const hofem_solver_s* S) {
   for (int i = 0; i < S->N; ++i)
     if (S->ax[i].bc != 0) return false;
   return true;
+}
+
+bool has_dense(const hofem_solver_s* S) {
+  for (int i = 0; i < S->N; ++i)
+    if (S->ax[i].dense) return true;
+  return false;
+}
+
+// Scratch grid of the dense passes (the grid the passes run on).
+size_t dense_bytes(const hofem_solver_s* S, int nrhs) {
+  return has_dense(S) ? (S->per_ext * (size_t)nrhs * sizeof(double) + 255) & ~size_t(255) : 0;
 }
 
 bool has_neumann(const hofem_solver_s* S) {
@@ -660,6 +736,10 @@ std::vector<unsigned char> pack_plan(const Plan1DData& d, PlanOff* off) {
   off->D = pk.add_f64(d.D);
   off->Dh = pk.add_f64(d.Dh);
   off->gw = pk.add_f64(d.gw);
+  if (d.dense) {
+    off->S = pk.add_f64(d.S);
+    off->St = pk.add_f64(d.St);
+  }
   pk.bytes.resize((pk.bytes.size() + 255) & ~size_t(255), 0);
   return pk.bytes;
 }
@@ -669,7 +749,7 @@ std::vector<unsigned char> pack_plan(const Plan1DData& d, PlanOff* off) {
 namespace hofem {
 
 size_t solver_unknowns(const hofem_solver_s* S) { return S->per_rhs; }
-bool solver_all_dirichlet(const hofem_solver_s* S) { return all_dirichlet(S); }
+bool solver_all_dirichlet(const hofem_solver_s* S) { return all_dirichlet(S) && !has_dense(S); }
 double solver_alpha(const hofem_solver_s* S) { return S->alpha; }
 int solver_device(const hofem_solver_s* S) { return S->device; }
 size_t solver_op_elem_bytes(const hofem_solver_s* S) { return op_elem_bytes(S); }
@@ -721,12 +801,16 @@ int hofem_plan1d_create(int n, int K, hofem_plan1d* out) {
 int hofem_plan1d_create_bc(int n, int K, int bc, hofem_plan1d* out) {
   if (!out) return HOFEM_EINVAL;
   if (bc != HOFEM_BC_DIRICHLET && bc != HOFEM_BC_PERIODIC && bc != HOFEM_BC_NEUMANN) return HOFEM_EINVAL;
-  if (n < 1 || n > 9 || K < 2 || K > 1024 || (K & (K - 1)) != 0) return HOFEM_EUNSUPPORTED;
+  const bool pow2 = (K & (K - 1)) == 0;
+  if (n < 1 || n > 9 || K < 2 || K > 1024) return HOFEM_EUNSUPPORTED;
+  // K not a power of two: Dirichlet axes only, by dense transforms (m <= 4095)
+  if (!pow2 && (bc != HOFEM_BC_DIRICHLET || n * K - 1 > kDenseMax)) return HOFEM_EUNSUPPORTED;
   hofem_plan1d p = new (std::nothrow) hofem_plan1d_s;
   if (!p) return HOFEM_ENOMEM;
-  const int rc = bc == HOFEM_BC_PERIODIC  ? plan1d_build_periodic(n, K, &p->d)
-                 : bc == HOFEM_BC_NEUMANN ? plan1d_build_neumann(n, K, &p->d)
-                                          : plan1d_build(n, K, &p->d);
+  int rc = bc == HOFEM_BC_PERIODIC  ? plan1d_build_periodic(n, K, &p->d)
+           : bc == HOFEM_BC_NEUMANN ? plan1d_build_neumann(n, K, &p->d)
+                                    : plan1d_build(n, K, &p->d);
+  if (rc == 0 && !pow2) rc = plan1d_build_dense(&p->d);
   if (rc != 0) {
     delete p;
     return HOFEM_EUNSUPPORTED;
@@ -784,8 +868,11 @@ int hofem_plan1d_table(hofem_plan1d plan, int which, double* out_host, size_t le
     case 9: v = &d.D; count = (size_t)(n + 1) * (n + 1); break;
     case 10: v = &d.wr; count = (size_t)(K / 2 + 1) * n * n; break;
     case 11: v = &d.wi; count = (size_t)(K / 2 + 1) * n * n; break;
+    case 12: v = &d.S; count = d.dense ? (size_t)d.m * d.m : 0; break;
+    case 13: v = &d.St; count = d.dense ? (size_t)d.m * d.m : 0; break;
     default: return HOFEM_EINVAL;
   }
+  if ((which == 12 || which == 13) && !d.dense) return HOFEM_EINVAL;
   if (len != count) return HOFEM_EINVAL;
   if (count) std::memcpy(out_host, v->data(), count * sizeof(double));
   return HOFEM_OK;
@@ -852,6 +939,11 @@ int hofem_solver_create(int N, const hofem_plan1d* plans, const double* X, doubl
     ax.D = reinterpret_cast<const double*>(b + o.D);
     ax.Dh = reinterpret_cast<const double*>(b + o.Dh);
     ax.gw = reinterpret_cast<const double*>(b + o.gw);
+    ax.dense = d.dense;
+    if (d.dense) {
+      ax.S = reinterpret_cast<const double*>(b + o.S);
+      ax.St = reinterpret_cast<const double*>(b + o.St);
+    }
   }
   *out = S;
   return HOFEM_OK;
@@ -914,7 +1006,9 @@ int hofem_solver_size(hofem_solver solver, size_t* unknowns) {
 int hofem_solver_workspace_bytes(hofem_solver solver, int mode, int nrhs, size_t* bytes) {
   if (!solver || !bytes || nrhs < 1) return HOFEM_EINVAL;
   switch (mode) {
-    case HOFEM_MODE_FP64: *bytes = has_neumann(solver) ? neumann_bytes(solver, nrhs) : 0; return HOFEM_OK;
+    case HOFEM_MODE_FP64:
+      *bytes = (has_neumann(solver) ? neumann_bytes(solver, nrhs) : 0) + dense_bytes(solver, nrhs);
+      return HOFEM_OK;
     case HOFEM_MODE_FP32:
     case HOFEM_MODE_FP64_B: *bytes = 0; return HOFEM_OK;
     case HOFEM_MODE_FP32_IR: *bytes = ir_workspace(solver, nrhs); return HOFEM_OK;
@@ -926,9 +1020,13 @@ int hofem_solver_workspace_bytes(hofem_solver solver, int mode, int nrhs, size_t
 int hofem_solve(hofem_solver S, int mode, const void* f_dev, void* u_dev, int nrhs, void* ws_dev,
                 size_t ws_bytes, int max_iter, double tol, void* stream, hofem_info* info) {
   if (!S || !f_dev || !u_dev || nrhs < 1) return HOFEM_EINVAL;
-  if (mode != HOFEM_MODE_FP64 && !all_dirichlet(S)) return HOFEM_EUNSUPPORTED;
-  if (mode == HOFEM_MODE_FP64 && has_neumann(S) && (!ws_dev || ws_bytes < neumann_bytes(S, nrhs)))
-    return HOFEM_EINVAL;
+  if (mode != HOFEM_MODE_FP64 && (!all_dirichlet(S) || has_dense(S))) return HOFEM_EUNSUPPORTED;
+  const size_t ext_b = has_neumann(S) ? neumann_bytes(S, nrhs) : 0;
+  if (mode == HOFEM_MODE_FP64 && (ext_b || has_dense(S))) {
+    if (!ws_dev || ws_bytes < ext_b + dense_bytes(S, nrhs)) return HOFEM_EINVAL;
+    S->dense_tmp = has_dense(S) ? reinterpret_cast<double*>(static_cast<unsigned char*>(ws_dev) + ext_b)
+                                : nullptr;
+  }
   hipStream_t st = static_cast<hipStream_t>(stream);
   // graph replay: solves without host synchronisation, on a stream that can
   // be captured
@@ -1114,7 +1212,7 @@ int hofem_forward(hofem_solver S, int mode, const void* in_dev, void* out_dev, i
   if (!S || !in_dev || !out_dev || nrhs < 1) return HOFEM_EINVAL;
   if (mode != HOFEM_MODE_FP64 && !all_dirichlet(S)) return HOFEM_EUNSUPPORTED;
   if (mode != HOFEM_MODE_FP64 && mode != HOFEM_MODE_FP32) return HOFEM_EINVAL;
-  if (has_neumann(S)) return HOFEM_EUNSUPPORTED;   // coefficients of the reflected grid
+  if (has_neumann(S) || has_dense(S)) return HOFEM_EUNSUPPORTED;   // no workspace argument
   const bool f64 = mode == HOFEM_MODE_FP64;
   const int dt = f64 ? 0 : 1;
   std::vector<PassSpec> l;
@@ -1128,7 +1226,7 @@ int hofem_inverse(hofem_solver S, int mode, const void* in_dev, void* out_dev, i
   if (!S || !in_dev || !out_dev || nrhs < 1) return HOFEM_EINVAL;
   if (mode != HOFEM_MODE_FP64 && !all_dirichlet(S)) return HOFEM_EUNSUPPORTED;
   if (mode != HOFEM_MODE_FP64 && mode != HOFEM_MODE_FP32) return HOFEM_EINVAL;
-  if (has_neumann(S)) return HOFEM_EUNSUPPORTED;   // coefficients of the reflected grid
+  if (has_neumann(S) || has_dense(S)) return HOFEM_EUNSUPPORTED;   // no workspace argument
   const bool f64 = mode == HOFEM_MODE_FP64;
   const int dt = f64 ? 0 : 1;
   std::vector<PassSpec> l;
@@ -1149,7 +1247,7 @@ int hofem_pcg(hofem_solver S, const hofem_coef* coef, const double* f_dev, doubl
   if (!S || !f_dev || !u_dev || nrhs < 1 || f_dev == u_dev || max_iter < 0 ||
       !std::isfinite(rtol) || !coef_ok(S, coef))
     return HOFEM_EINVAL;
-  if (!all_dirichlet(S)) return HOFEM_EUNSUPPORTED;
+  if (!all_dirichlet(S) || has_dense(S)) return HOFEM_EUNSUPPORTED;
   if (!ws_dev || ws_bytes < pcg_bytes(S, coef)) return HOFEM_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const PcgWs w = pcg_carve(S, coef, ws_dev);
@@ -1323,7 +1421,7 @@ int hofem_solver_autotune(hofem_solver S, int mode, const void* f_dev, void* u_d
   if (mode != HOFEM_MODE_FP64 && mode != HOFEM_MODE_FP32 && mode != HOFEM_MODE_FP32_IR) return HOFEM_EINVAL;
   if (mode == HOFEM_MODE_FP32_IR && f_dev == u_dev) return HOFEM_EINVAL;
   if (max_entries > 0 && !out_host) return HOFEM_EINVAL;
-  if (!all_dirichlet(S)) return HOFEM_EUNSUPPORTED;   // periodic passes have one shape
+  if (!all_dirichlet(S) || has_dense(S)) return HOFEM_EUNSUPPORTED;   // FFT line passes only
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));

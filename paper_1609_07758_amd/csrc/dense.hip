@@ -1,0 +1,139 @@
+// Dense eigenvector transforms of axes whose K is not a power of two: the
+// solve v = (x)V diag(1 / (alpha + sum_i 4 h_i^-2 lambda_i)) (x)V^T f^h of
+// eq. (decomp v 2) with V applied along the axis as a matrix product (there
+// is no power-of-two FFT for it), on the FP64 matrix cores.
+//
+// dgemm: C_b = op(A_b) op(B_b), FP64, row-major operands with leading
+// dimensions and batch strides, op = transpose when TA / TB.  A workgroup of
+// four wavefronts owns a 64 x 64 tile of C; each wavefront a 32 x 32
+// quarter as 2 x 2 blocks of v_mfma_f64_16x16x4 (A operand: lane l holds
+// A[l % 16][l / 16] of the 16 x 4 slice, B operand: B[l / 16][l % 16] of the
+// 4 x 16 slice, result: lane l holds D[l / 16 + 4 r][l % 16], r = 0..3).
+// K advances in slices of 16 staged through LDS, zero-filled outside the
+// matrices, so any M, N, K work.
+#include "kernels.h"
+
+namespace hofem {
+namespace {
+
+constexpr int kBM = 64, kBN = 64, kBK = 16;
+constexpr int kPadM = kBM + 2, kPadN = kBN + 2;   // LDS row pitch (doubles)
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void dgemm_kernel(GemmArgs g) {
+  __shared__ double As[kBK][kPadM];   // As[k][i] = op(A)[i][k]
+  __shared__ double Bs[kBK][kPadN];   // Bs[k][j] = op(B)[k][j]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wy = wave >> 1, wx = wave & 1;
+  const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
+  for (long long b = blockIdx.z; b < g.batch; b += gridDim.z) {
+    const double* __restrict__ A = g.A + b * g.sa;
+    const double* __restrict__ B = g.B + b * g.sb;
+    double* __restrict__ C = g.C + b * g.sc;
+    double4_t acc[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = double4_t{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < g.K; k0 += kBK) {
+      // stage op(A)[m0 .. m0+63][k0 .. k0+15] and op(B)[k0 .. k0+15][n0 .. n0+63]:
+      // four values per lane, consecutive in memory
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        int i, k;
+        if (TA) {   // A[k][i]: i contiguous
+          k = tid >> 4;
+          i = 4 * (tid & 15) + u;
+        } else {    // A[i][k]: k contiguous
+          i = tid >> 2;
+          k = 4 * (tid & 3) + u;
+        }
+        const int gi = m0 + i, gk = k0 + k;
+        double v = 0.0;
+        if (gi < g.M && gk < g.K) v = TA ? A[(long long)gk * g.lda + gi] : A[(long long)gi * g.lda + gk];
+        As[k][i] = v;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        int k, j;
+        if (TB) {   // B[j][k]: k contiguous
+          j = tid >> 2;
+          k = 4 * (tid & 3) + u;
+        } else {    // B[k][j]: j contiguous
+          k = tid >> 4;
+          j = 4 * (tid & 15) + u;
+        }
+        const int gk = k0 + k, gj = n0 + j;
+        double v = 0.0;
+        if (gk < g.K && gj < g.N) v = TB ? B[(long long)gj * g.ldb + gk] : B[(long long)gk * g.ldb + gj];
+        Bs[k][j] = v;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < kBK; kk += 4) {
+        const int kr = kk + (lane >> 4), c = lane & 15;
+        double a[2], bv[2];
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi) a[bi] = As[kr][32 * wy + 16 * bi + c];
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) bv[bj] = Bs[kr][32 * wx + 16 * bj + c];
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj)
+            acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], bv[bj], acc[bi][bj], 0, 0, 0);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gi = m0 + 32 * wy + 16 * bi + (lane >> 4) + 4 * r;
+          const int gj = n0 + 32 * wx + 16 * bj + (lane & 15);
+          if (gi < g.M && gj < g.N) C[(long long)gi * g.ldc + gj] = acc[bi][bj][r];
+        }
+  }
+}
+
+// x[o][q][t] /= alpha + scale lam[q] + sum_i oscale[i] olam[i][(t / odiv[i]) % omod[i]]
+// over a grid [outer][m][inner] (outer = right-hand sides: the fused pass runs
+// along axis 0).
+__global__ __launch_bounds__(256) void dense_divide_kernel(double* __restrict__ x, long long total,
+                                                           int m, long long inner, PassArgs a) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const long long t = i % inner;
+  const int q = (int)((i / inner) % m);
+  double d = a.alpha + a.scale * a.tab.lam[q];
+  for (int k = 0; k < a.nother; ++k) d += a.oscale[k] * a.olam[k][(t / a.odiv[k]) % a.omod[k]];
+  x[i] /= d;
+}
+
+}  // namespace
+
+hipError_t launch_dgemm(const GemmArgs& g, bool ta, bool tb, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+  if (g.K <= 0) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((g.N + kBN - 1) / kBN), (unsigned)((g.M + kBM - 1) / kBM),
+                  (unsigned)(g.batch < 65535 ? g.batch : 65535));
+  auto fn = ta ? (tb ? dgemm_kernel<true, true> : dgemm_kernel<true, false>)
+              : (tb ? dgemm_kernel<false, true> : dgemm_kernel<false, false>);
+  hipLaunchKernelGGL(fn, grid, dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_divide(double* x, long long outer, int m, long long inner, const PassArgs& a,
+                               hipStream_t s) {
+  const long long total = outer * m * inner;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(dense_divide_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, x, total,
+                     m, inner, a);
+  return hipGetLastError();
+}
+
+}  // namespace hofem

@@ -170,6 +170,24 @@ struct EvenArgs {
 hipError_t launch_even_extend(const EvenArgs& a, const double* f, double* e, hipStream_t s);
 hipError_t launch_even_restrict(const EvenArgs& a, const double* e, double* u, hipStream_t s);
 
+// C_b = op(A_b) op(B_b) in FP64 on the matrix cores (dense transforms of
+// axes whose K is not a power of two): row-major M x K, K x N, M x N after
+// op, op = transpose when ta / tb; b = 0..batch-1 with element strides
+// sa, sb, sc.
+struct GemmArgs {
+  const double* A;
+  const double* B;
+  double* C;
+  int M, N, K;
+  long long lda, ldb, ldc;
+  long long sa, sb, sc, batch;
+};
+hipError_t launch_dgemm(const GemmArgs& g, bool ta, bool tb, hipStream_t s);
+// x[o][q][t] /= a.alpha + a.scale a.tab.lam[q] + the other axes' terms (as
+// in the fused pass), x of shape [outer][m][inner].
+hipError_t launch_dense_divide(double* x, long long outer, int m, long long inner, const PassArgs& a,
+                               hipStream_t s);
+
 // u += delta over `count` elements with per-workgroup partial sums of
 // delta^2 and u^2 (nparts workgroups), reduced to out[0..1] by a second
 // launch (fixed order: deterministic).

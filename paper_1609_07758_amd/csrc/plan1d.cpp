@@ -263,7 +263,7 @@ q128 root_in(const Secular& S, q128 th, q128 lo, q128 hi) {
 }  // namespace
 
 int plan1d_build(int n, int K, Plan1DData* out) {
-  if (n < 1 || n > 9 || K < 2 || (K & (K - 1)) != 0 || K > 65536) return -1;
+  if (n < 1 || n > 9 || K < 2 || K > 65536) return -1;
   const int nb = n + 1, d = n - 1, m = n * K - 1;
   std::vector<q128> A, C, gx, gw, Bq, Dq;
   local_matrices(n, A, C, gx, gw, Bq, Dq);
@@ -513,6 +513,49 @@ int plan1d_build_periodic(int n, int K, Plan1DData* out) {
   }
   out->kn = K;
   out->mu = m;
+  return 0;
+}
+
+int plan1d_build_dense(Plan1DData* d) {
+  const int n = d->n, K = d->K, m = d->m;
+  if (d->bc != 0 || m < 1 || m > kDenseMax) return -1;
+  d->dense = 1;
+  d->S.assign((size_t)m * m, 0.0);
+  d->St.assign((size_t)m * m, 0.0);
+  // sin(pi x / K) for an integer x, reduced modulo 2K first
+  auto sine = [&](long long x) -> long double {
+    const long long r = ((x % (2LL * K)) + 2LL * K) % (2LL * K);
+    return sinl(3.14159265358979323846264338327950288L * (long double)r / (long double)K);
+  };
+  auto put = [&](int q, int c, long double v, double norm) {
+    d->S[(size_t)q * m + c] = (double)v;
+    d->St[(size_t)q * m + c] = (double)(v * norm);
+  };
+  // k = 0, l = 1..n-1: zero at the nodes, ((-P)^(e-1) e^(l))_s in element e
+  for (int l = 1; l < n; ++l) {
+    const int c = l - 1;
+    for (int e = 1; e <= K; ++e)
+      for (int s = 1; s < n; ++s) {
+        const int si = (e & 1) ? s : n - s;
+        const long double v = (long double)d->E[(size_t)(si - 1) * (n - 1) + (l - 1)];
+        put(n * (e - 1) + s - 1, c, (e & 1) ? v : -v, 1.0 / K);
+      }
+  }
+  // k = 1..K-1, l = 1..n: sin(pi k j / K) at node j, and
+  // sin(pi k (e-1) / K) p_s + sin(pi k e / K) p_(n-s) in element e
+  for (int k = 1; k < K; ++k)
+    for (int l = 1; l <= n; ++l) {
+      const int c = (n - 1) + (l - 1) * (K - 1) + (k - 1);
+      const double norm = d->inorm[(size_t)(k - 1) * n + (l - 1)];
+      const double* p = d->p.data() + ((size_t)(k - 1) * n + (l - 1)) * (n - 1);
+      for (int j = 1; j < K; ++j) put(n * j - 1, c, sine((long long)k * j), norm);
+      for (int e = 1; e <= K; ++e)
+        for (int s = 1; s < n; ++s) {
+          const long double v = sine((long long)k * (e - 1)) * (long double)p[s - 1] +
+                                sine((long long)k * e) * (long double)p[n - s - 1];
+          put(n * (e - 1) + s - 1, c, v, norm);
+        }
+    }
   return 0;
 }
 

@@ -31,14 +31,27 @@ struct Plan1DData {
   // Lagrange basis g_p of the Gauss nodes (Dh = D B^-1; rows sum to zero)
   std::vector<double> Dh;
 
+  // Dirichlet axes whose K is not a power of two (no FFT): the unnormalised
+  // eigenvectors s_k^(l) of Theorem 1 as the columns of S (m x m, row q =
+  // unknown, column c = coefficient index) and St = S diag(1 / ||s_c||_C^2)
+  // (1/K for the k = 0 columns), so that the coefficients are St^T y and the
+  // inverse transform S c
+  int dense = 0;
+  std::vector<double> S, St;
+
   // periodic axes: Bloch eigenvectors w_{k,l} (cell components s = 0..n-1:
   // node j, interior points of element j+1) for k = 0..K/2, index
   // (k n + l) n + s, real and imaginary parts; w^H C^(k) w = 1
   std::vector<double> wr, wi;
 };
 
+// Largest m of a dense (non-power-of-two K) axis: S and St take 2 m^2 doubles.
+constexpr int kDenseMax = 4095;
+
 // Returns 0 on success, -1 for unsupported (n, K).
 int plan1d_build(int n, int K, Plan1DData* out);
+// Fills S and St of a Dirichlet plan (m <= kDenseMax); 0 on success.
+int plan1d_build_dense(Plan1DData* d);
 // Periodic axis (m = nK unknowns: node j at q = n j, interior point s of
 // element j+1 at q = n j + s, j = 0..K-1): eigenvalues in the coefficient
 // order q = l K + t (t = 0: k = 0; t = 2k-1, 2k: real and imaginary parts of

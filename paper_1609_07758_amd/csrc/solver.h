@@ -14,7 +14,8 @@ namespace hofem {
 size_t solver_unknowns(const hofem_solver_s* S);
 double solver_alpha(const hofem_solver_s* S);
 int solver_device(const hofem_solver_s* S);
-// Every axis has Dirichlet data (time stepping needs the Dirichlet operator).
+// Every axis has Dirichlet data and K a power of two (time stepping needs the
+// Dirichlet operator and the FFT passes).
 bool solver_all_dirichlet(const hofem_solver_s* S);
 // Bytes of the operator's element buffer (0 where it needs none; a multiple of 256).
 size_t solver_op_elem_bytes(const hofem_solver_s* S);

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(H.SIGNATURES)
 
 
-@pytest.mark.parametrize("n,K", [(0, 16), (10, 16), (2, 3), (2, 1), (2, 2048), (-1, 8)])
+@pytest.mark.parametrize("n,K", [(0, 16), (10, 16), (2, 1), (2, 2048), (-1, 8), (9, 1000)])
 def test_plan_rejects_unsupported(n, K):
     h = ctypes.c_void_p()
     assert H._lib.hofem_plan1d_create(n, K, ctypes.byref(h)) == H.HOFEM_EUNSUPPORTED
@@ -81,7 +81,8 @@ def test_plan_table_image_size_and_upload_errors():
     assert H._lib.hofem_status_string(H.HOFEM_ENOCONV) == b"refinement did not converge"
 
 
-@pytest.mark.parametrize("n,K", [(1, 16), (2, 16), (3, 8), (4, 32), (6, 16), (9, 8), (9, 64)])
+@pytest.mark.parametrize("n,K", [(1, 16), (2, 16), (3, 8), (4, 32), (6, 16), (9, 8), (9, 64),
+                                 (3, 12), (5, 6), (2, 3), (9, 10)])
 def test_plan_tables_match_oracle(n, K):
     p = H.Plan1D(n, K)
     o = spectral.eigen_structured(n, K)
@@ -196,3 +197,45 @@ def test_neumann_plan_dims_and_tables():
     assert lib.hofem_plan1d_create_bc(2, 1024, 2, ctypes.byref(h)) == -2
     assert lib.hofem_plan1d_create_bc(2, 512, 2, ctypes.byref(h)) == 0
     lib.hofem_plan1d_destroy(h)
+
+
+
+def test_non_power_of_two_plans():
+    # Dirichlet axes whose K is not a power of two take dense transforms
+    # (m = nK - 1 <= 4095); other conditions need the FFT (powers of two)
+    P = H.Plan1D(3, 12)
+    try:
+        assert P.m == 35
+    finally:
+        P.close()
+    h = ctypes.c_void_p()
+    lib = ctypes.CDLL(H.LIB_PATH)
+    assert lib.hofem_plan1d_create_bc(9, 455, 0, ctypes.byref(h)) == 0   # m = 4094
+    lib.hofem_plan1d_destroy(h)
+    assert lib.hofem_plan1d_create_bc(9, 456, 0, ctypes.byref(h)) == -2   # m = 4103
+    assert lib.hofem_plan1d_create_bc(2, 12, 1, ctypes.byref(h)) == -2
+    assert lib.hofem_plan1d_create_bc(2, 12, 2, ctypes.byref(h)) == -2
+
+
+@pytest.mark.parametrize("n,K", [(3, 12), (2, 3), (5, 6)])
+def test_dense_eigenvectors_match_oracle(n, K):
+    # the dense transform matrices of a non-power-of-two plan: the columns of
+    # S are Theorem 1's eigenvectors (the oracle's structured route), St
+    # scales them by 1 / ||s||_C^2
+    P = H.Plan1D(n, K)
+    try:
+        m = P.m
+        S = P.table("S").reshape(m, m)
+        St = P.table("St").reshape(m, m)
+    finally:
+        P.close()
+    o = spectral.eigen_structured(n, K)
+    So, _ = spectral.eigenvectors_structured(n, K, o)
+    # the oracle lists the k >= 1 columns k-major, the library l-major
+    perm = list(range(n - 1)) + [(n - 1) + (k - 1) * n + (l - 1)
+                                 for l in range(1, n + 1) for k in range(1, K)]
+    So = So[:, perm]
+    assert np.allclose(S, So, rtol=0, atol=1e-14 * np.abs(So).max())
+    A, C = assembly.assemble_1d(n, K)
+    G = St.T @ C @ S   # = identity: St^T is the inverse of S
+    assert np.allclose(G, np.eye(m), rtol=0, atol=1e-12)
