@@ -361,6 +361,21 @@ __global__ __launch_bounds__(kOpSfThreads) __attribute__((amdgpu_waves_per_eu(4)
   const double* C1 = mt.C1;
   const double s0 = a.scale[0], s1 = a.scale[1], al = a.alpha;
   const double* __restrict__ u = a.u + roff;
+  const double* __restrict__ f = a.f ? a.f + roff : nullptr;
+
+  // f of this lane's first phase-2 task, loaded now: its latency overlaps
+  // phase 1 instead of following the barrier
+  double fpre[NO];
+  {
+    const int e = tid / W, cl = tid - e * W;
+    const int g1 = NO * E1 + cl + 1, E = E0 + e + 1;
+    const bool ok = f && tid < W * TE0 && g1 <= m1 && E <= K0;
+#pragma unroll
+    for (int r = 1; r <= NO; ++r) {
+      const int g0 = NO * (E - 1) + r;
+      fpre[r - 1] = (ok && g0 <= m0) ? f[(long long)(g0 - 1) * m1 + (g1 - 1)] : 0.0;
+    }
+  }
 
   // 1. axis 1: P = C1_g u, D = s1 A1_g u + alpha P on rows NO E0 + i
   for (int t0 = 0; t0 < R * TE1; t0 += kOpSfThreads) {
@@ -411,7 +426,6 @@ __global__ __launch_bounds__(kOpSfThreads) __attribute__((amdgpu_waves_per_eu(4)
   __syncthreads();
 
   // 2. axis 0: r = f - s0 A0_g P - C0_g D at rows NO (E - 1) + r, E = E0 + e + 1
-  const double* __restrict__ f = a.f ? a.f + roff : nullptr;
   for (int t0 = 0; t0 < W * TE0; t0 += kOpSfThreads) {
     const int task = t0 + tid;
     const int e = task / W, cl = task - e * W;
@@ -446,7 +460,8 @@ __global__ __launch_bounds__(kOpSfThreads) __attribute__((amdgpu_waves_per_eu(4)
       const double lu = s0 * ap + cd;
       if (ok && g0 <= m0) {
         const long long idx = (long long)(g0 - 1) * m1 + (g1 - 1);
-        const double res = f ? f[idx] - lu : lu;
+        const double fv = t0 == 0 ? fpre[r - 1] : (f ? f[idx] : 0.0);
+        const double res = f ? fv - lu : lu;
         if (a.out_f32) static_cast<float*>(a.out)[roff + idx] = (float)res;
         else static_cast<double*>(a.out)[roff + idx] = res;
       }
