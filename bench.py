@@ -18,7 +18,7 @@ pass that takes most time.
 Further workloads (one entry each under other_workloads):
   batch_2d    256 independent 2D problems (K in {32..256}, n in {2..6}, 4 RHS
               each), one batched call replayed from a HIP graph;
-  cube_3d     3D n = 4, K = 128 (511^3 unknowns), manufactured f plus noise;
+  cube_3d     3D n = 4, K = 128 (511^3 unknowns), Gauss load of a manufactured f plus noise;
   varcoef_3d  -div(a grad u) = f, 3D n = 3, K = 64, PCG to 1e-10.
 
 `cpu_baseline` times the CPU oracle (dense eigenvector products along both
@@ -403,11 +403,36 @@ def bench_batch(args, torch, H, np, workloads, dev):
     return rec
 
 
+def gauss_load_1d(H, np, n, K, X, g):
+    """1D scaled load vector of g by the (n+1)-point Gauss rule per element
+    (Section 2, paragraph 5), from the plan's Gauss nodes, weights and basis
+    values: sum over elements of sum_q w_q g(x_q) e_r(xi_q), interior points."""
+    P = H.Plan1D(n, K)
+    try:
+        gx, gw = P.table("gx"), P.table("gw")
+        B = P.table("B").reshape(n + 1, n + 1)   # B[q, r] = e_r(xi_q)
+    finally:
+        P.close()
+    h = X / K
+    x = np.arange(K)[:, None] * h + (gx[None, :] + 1.0) * (h / 2.0)
+    contrib = (gw[None, :] * g(x)) @ B            # [element, r]
+    b = np.zeros(n * K + 1)
+    for r in range(n + 1):
+        np.add.at(b, n * np.arange(K) + r, contrib[:, r])
+    return b[1:-1]
+
+
 def bench_cube(args, torch, H, np, workloads, dev):
     cfg = workloads.CONFIGS["cube_3d"]
     shp = workloads.shape(cfg["orders"], cfg["Ks"])
     M = int(np.prod(shp))
-    f64 = torch.from_numpy(workloads.manufactured_3d(cfg, seed=0)).to(dev)
+    # f^h: Gauss load of f = 11 pi^2 sin(pi x) sin(pi y) sin(3 pi z) (= -Lap of
+    # sin(pi x) sin(pi y) sin(3 pi z)) plus N(0, 1e-3^2) noise on every entry
+    ls = [gauss_load_1d(H, np, n, K, X, (lambda x, c=c: np.sin(c * np.pi * x)))
+          for n, K, X, c in zip(cfg["orders"], cfg["Ks"], cfg["X"], (1, 1, 3))]
+    fh = (11 * np.pi ** 2) * np.multiply.outer(np.multiply.outer(ls[0], ls[1]), ls[2])
+    fh += workloads.normal_noise(fh.shape, 1e-3, seed=0)
+    f64 = torch.from_numpy(fh).to(dev)
     S = H.Solver(cfg["orders"], cfg["Ks"], cfg["X"], cfg["alpha"])
     u64 = torch.empty_like(f64)
     uir = torch.empty_like(f64)

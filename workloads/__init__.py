@@ -77,15 +77,3 @@ def grid_points(n, K, X):
     """Coordinates q X / (n K), q = 1..nK-1, of the unknowns along one axis."""
     return np.arange(1, n * K) * (X / (n * K))
 
-
-def manufactured_3d(cfg, seed=0, sigma=1e-3):
-    """Nodal values of f = 11 pi^2 sin(pi x) sin(pi y) sin(3 pi z) (= -Lap of
-    u = sin(pi x) sin(pi y) sin(3 pi z)) on the grid of a 3D configuration,
-    plus i.i.d. N(0, sigma^2) noise (sigma is the standard deviation)."""
-    (n0, n1, n2), (K0, K1, K2), (X0, X1, X2) = cfg["orders"], cfg["Ks"], cfg["X"]
-    a = np.sin(np.pi * grid_points(n0, K0, X0))
-    b = np.sin(np.pi * grid_points(n1, K1, X1))
-    c = np.sin(3 * np.pi * grid_points(n2, K2, X2))
-    f = (11 * np.pi ** 2) * a[:, None, None] * b[None, :, None] * c[None, None, :]
-    f += np.random.default_rng(seed).normal(0.0, sigma, f.shape)
-    return f
