@@ -9,15 +9,17 @@
 // quarter as 2 x 2 blocks of v_mfma_f64_16x16x4 (A operand: lane l holds
 // A[l % 16][l / 16] of the 16 x 4 slice, B operand: B[l / 16][l % 16] of the
 // 4 x 16 slice, result: lane l holds D[l / 16 + 4 r][l % 16], r = 0..3).
-// K advances in slices of 16 staged through LDS, zero-filled outside the
-// matrices, so any M, N, K work.
+// K advances in slices of 32 staged through LDS, zero-filled outside the
+// matrices, so any M, N, K work; each lane fetches the next slice into
+// registers while the matrix cores work on the current one.
 #include "kernels.h"
 
 namespace hofem {
 namespace {
 
-constexpr int kBM = 64, kBN = 64, kBK = 16;
+constexpr int kBM = 64, kBN = 64, kBK = 32;
 constexpr int kPadM = kBM + 2, kPadN = kBN + 2;   // LDS row pitch (doubles)
+constexpr int kLoad = kBM * kBK / 256;            // values of each operand a lane stages per slice
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
@@ -28,6 +30,27 @@ __global__ __launch_bounds__(256) void dgemm_kernel(GemmArgs g) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wy = wave >> 1, wx = wave & 1;
   const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
+  // this lane's staging positions: kLoad values of each operand per slice,
+  // consecutive in memory (i or k contiguous for A, k or j for B)
+  int ai[kLoad], ak[kLoad], bk[kLoad], bj[kLoad];
+#pragma unroll
+  for (int u = 0; u < kLoad; ++u) {
+    if (TA) {   // A[k][i]: i contiguous
+      ak[u] = tid >> 4;
+      ai[u] = 4 * (tid & 15) + (u & 3);
+      ak[u] += 16 * (u >> 2);
+    } else {    // A[i][k]: k contiguous
+      ai[u] = tid >> 2;
+      ak[u] = 4 * (tid & 3) + (u & 3) + 16 * (u >> 2);
+    }
+    if (TB) {   // B[j][k]: k contiguous
+      bj[u] = tid >> 2;
+      bk[u] = 4 * (tid & 3) + (u & 3) + 16 * (u >> 2);
+    } else {    // B[k][j]: j contiguous
+      bk[u] = (tid >> 4) + 16 * (u >> 2);
+      bj[u] = 4 * (tid & 15) + (u & 3);
+    }
+  }
   for (long long b = blockIdx.z; b < g.batch; b += gridDim.z) {
     const double* __restrict__ A = g.A + b * g.sa;
     const double* __restrict__ B = g.B + b * g.sb;
@@ -36,41 +59,29 @@ __global__ __launch_bounds__(256) void dgemm_kernel(GemmArgs g) {
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-      for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = double4_t{0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < g.K; k0 += kBK) {
-      // stage op(A)[m0 .. m0+63][k0 .. k0+15] and op(B)[k0 .. k0+15][n0 .. n0+63]:
-      // four values per lane, consecutive in memory
+      for (int bj2 = 0; bj2 < 2; ++bj2) acc[bi][bj2] = double4_t{0.0, 0.0, 0.0, 0.0};
+    // slice k0 of op(A) and op(B) into registers (zero outside the matrices)
+    double ra[kLoad], rb[kLoad];
+    auto fetch = [&](int k0) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        int i, k;
-        if (TA) {   // A[k][i]: i contiguous
-          k = tid >> 4;
-          i = 4 * (tid & 15) + u;
-        } else {    // A[i][k]: k contiguous
-          i = tid >> 2;
-          k = 4 * (tid & 3) + u;
-        }
-        const int gi = m0 + i, gk = k0 + k;
-        double v = 0.0;
-        if (gi < g.M && gk < g.K) v = TA ? A[(long long)gk * g.lda + gi] : A[(long long)gi * g.lda + gk];
-        As[k][i] = v;
+      for (int u = 0; u < kLoad; ++u) {
+        const int gi = m0 + ai[u], gk = k0 + ak[u];
+        ra[u] = (gi < g.M && gk < g.K) ? (TA ? A[(long long)gk * g.lda + gi] : A[(long long)gi * g.lda + gk])
+                                       : 0.0;
+        const int gk2 = k0 + bk[u], gj = n0 + bj[u];
+        rb[u] = (gk2 < g.K && gj < g.N) ? (TB ? B[(long long)gj * g.ldb + gk2] : B[(long long)gk2 * g.ldb + gj])
+                                        : 0.0;
       }
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < g.K; k0 += kBK) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        int k, j;
-        if (TB) {   // B[j][k]: k contiguous
-          j = tid >> 2;
-          k = 4 * (tid & 3) + u;
-        } else {    // B[k][j]: j contiguous
-          k = tid >> 4;
-          j = 4 * (tid & 15) + u;
-        }
-        const int gk = k0 + k, gj = n0 + j;
-        double v = 0.0;
-        if (gk < g.K && gj < g.N) v = TB ? B[(long long)gj * g.ldb + gk] : B[(long long)gk * g.ldb + gj];
-        Bs[k][j] = v;
+      for (int u = 0; u < kLoad; ++u) {
+        As[ak[u]][ai[u]] = ra[u];
+        Bs[bk[u]][bj[u]] = rb[u];
       }
       __syncthreads();
+      if (k0 + kBK < g.K) fetch(k0 + kBK);   // the next slice's loads overlap this slice's products
 #pragma unroll
       for (int kk = 0; kk < kBK; kk += 4) {
         const int kr = kk + (lane >> 4), c = lane & 15;
@@ -78,24 +89,24 @@ __global__ __launch_bounds__(256) void dgemm_kernel(GemmArgs g) {
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi) a[bi] = As[kr][32 * wy + 16 * bi + c];
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj) bv[bj] = Bs[kr][32 * wx + 16 * bj + c];
+        for (int bj2 = 0; bj2 < 2; ++bj2) bv[bj2] = Bs[kr][32 * wx + 16 * bj2 + c];
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-          for (int bj = 0; bj < 2; ++bj)
-            acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], bv[bj], acc[bi][bj], 0, 0, 0);
+          for (int bj2 = 0; bj2 < 2; ++bj2)
+            acc[bi][bj2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], bv[bj2], acc[bi][bj2], 0, 0, 0);
       }
       __syncthreads();
     }
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
+      for (int bj2 = 0; bj2 < 2; ++bj2)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int gi = m0 + 32 * wy + 16 * bi + (lane >> 4) + 4 * r;
-          const int gj = n0 + 32 * wx + 16 * bj + (lane & 15);
-          if (gi < g.M && gj < g.N) C[(long long)gi * g.ldc + gj] = acc[bi][bj][r];
+          const int gj = n0 + 32 * wx + 16 * bj2 + (lane & 15);
+          if (gi < g.M && gj < g.N) C[(long long)gi * g.ldc + gj] = acc[bi][bj2][r];
         }
   }
 }
