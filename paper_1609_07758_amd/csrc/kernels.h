@@ -114,8 +114,8 @@ struct OpArgs {
   const double* hA[3]; // the same, host copies (passed by value to kernels)
   const double* hC[3];
   int nrhs;
-  // 3D with equal orders: per-element outputs of one right-hand side,
-  // prod K_i (n+1)^3 doubles (op3_elem_doubles), device
+  // 3D with equal orders: two grids of one right-hand side (the planes' 2D
+  // mass products and operators; op3_elem_doubles), device
   double* elem;
 };
 hipError_t launch_operator(const OpArgs& a, hipStream_t s);

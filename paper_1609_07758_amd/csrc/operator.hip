@@ -339,7 +339,9 @@ struct OpSfShape {
   static constexpr int LDS = 2 * R * W * 8;
 };
 
-template <int NO>
+// MASS: also writes (C0_g (x) C1_g) u, the plain mass product, to a.elem
+// (double; the planes of the 3D operator need both).
+template <int NO, bool MASS = false>
 __global__ __launch_bounds__(kOpSfThreads) __attribute__((amdgpu_waves_per_eu(4))) void op2_sf_kernel(
     OpArgs a, OpMats mt, int nt1) {
   using SH = OpSfShape<NO>;
@@ -433,6 +435,7 @@ __global__ __launch_bounds__(kOpSfThreads) __attribute__((amdgpu_waves_per_eu(4)
     const int E = E0 + e + 1;
     const bool ok = task < W * TE0 && g1 <= m1 && E <= K0;
     double p[B], d[B], pn[B], dn[B];
+    // (the plain mass product needs C1_g u without alpha: P holds it)
     const int l0 = ok ? NO * e : 0;              // local row of the element's first point
     const int lc = ok ? cl : 0;
 #pragma unroll
@@ -458,8 +461,18 @@ __global__ __launch_bounds__(kOpSfThreads) __attribute__((amdgpu_waves_per_eu(4)
         for (int q = 0; q < B; ++q) cd += C0[q] * dn[q];
       }
       const double lu = s0 * ap + cd;
+      double cm = 0.0;   // C0_g P: the mass product (MASS)
+      if constexpr (MASS) {
+#pragma unroll
+        for (int q = 0; q < B; ++q) cm += C0[r * B + q] * p[q];
+        if (r == NO) {
+#pragma unroll
+          for (int q = 0; q < B; ++q) cm += C0[q] * pn[q];
+        }
+      }
       if (ok && g0 <= m0) {
         const long long idx = (long long)(g0 - 1) * m1 + (g1 - 1);
+        if constexpr (MASS) a.elem[roff + idx] = cm;
         const double fv = t0 == 0 ? fpre[r - 1] : (f ? f[idx] : 0.0);
         const double res = f ? fv - lu : lu;
         if (a.out_f32) static_cast<float*>(a.out)[roff + idx] = (float)res;
@@ -469,12 +482,12 @@ __global__ __launch_bounds__(kOpSfThreads) __attribute__((amdgpu_waves_per_eu(4)
   }
 }
 
-template <int NO>
+template <int NO, bool MASS = false>
 hipError_t launch_op2_sf(const OpArgs& a, hipStream_t s) {
   using SH = OpSfShape<NO>;
   static bool raised = false;   // benign race: every caller sets the same value
   if (!raised) {
-    hipError_t e = hipFuncSetAttribute((const void*)op2_sf_kernel<NO>,
+    hipError_t e = hipFuncSetAttribute((const void*)op2_sf_kernel<NO, MASS>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, SH::LDS);
     if (e != hipSuccess) return e;
     raised = true;
@@ -488,186 +501,122 @@ hipError_t launch_op2_sf(const OpArgs& a, hipStream_t s) {
     mt.C1[i] = a.hC[1][i];
   }
   const int nt0 = (a.K[0] + SH::TE0 - 1) / SH::TE0, nt1 = (a.K[1] + SH::TE1 - 1) / SH::TE1;
-  hipLaunchKernelGGL(op2_sf_kernel<NO>, dim3((unsigned)(nt0 * nt1), (unsigned)a.nrhs),
+  if (MASS && !a.elem) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((op2_sf_kernel<NO, MASS>), dim3((unsigned)(nt0 * nt1), (unsigned)a.nrhs),
                      dim3(kOpSfThreads), SH::LDS, s, a, mt, nt1);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// 3D operator for equal orders NO (compile time): per element, sum-factorised
-// with the stiffness factor applied to u first in difference form,
-//   E = C_2 [ s0 C_1 (A_0 U) + s1 C_0 (A_1 U) ] + C_1 C_0 [ (s2 A_2 + alpha C_2) U ]
-// (X_a: factor X along axis a), EPW elements per workgroup, one line of b
-// outputs per lane and contraction; the elements' outputs go to a buffer and
-// a second kernel sums, for every point, the 1..8 elements holding it in a
-// fixed order (deterministic).
+// 3D operator for equal orders NO, by planes and lines:
+//   L u = s0 A0 (x) C1 (x) C2 u + C0 (x) [ s1 A1 (x) C2 + C1 (x) (s2 A2 + alpha C2) ] u
+//       = s0 A0_g Z1 + C0_g Z2,   Z1 = (C1 (x) C2) u,   Z2 = L12 u
+// along axis 0, where Z1 and Z2 are the 2D mass product and the 2D operator
+// (with alpha) of every plane of constant axis-0 index: one run of the tiled
+// 2D kernel computes both (its planes as right-hand sides), and op3_axis0_kernel
+// applies the axis-0 factors element by element (stiffness in difference
+// form) and subtracts from f.  Z1, Z2: the operator's element buffer
+// (2 grids of one right-hand side); every output has one writer.
 // ---------------------------------------------------------------------------
 
+// One lane per (point of the axis-1/2 plane, element e along axis 0): the
+// element's outputs at positions n(e-1)+r, r = 1..n (the node n e also takes
+// the first row of element e+1).
 template <int NO>
-struct Op3Shape {
-  static constexpr int B = NO + 1, BBB = B * B * B;
-  static constexpr int EPW0 = 40960 / (6 * BBB * 8);
-  static constexpr int EPW = EPW0 < 1 ? 1 : (EPW0 > 32 ? 32 : EPW0);
-  static constexpr int LDS = 6 * BBB * EPW * 8;
-};
-
-// dst[line, q] (+)= sum_r M[q][r] src[line, r] along axis ax of b^3 blocks;
-// mode 0: plain, 1: difference form sum_{r != q} M[q][r] (src_r - src_q),
-// 2: sd * (difference form of M) + sp * (plain with M2).
-template <int B, int MODE, bool ACC>
-__device__ __forceinline__ void op3_contract(const double* src, double* dst, int ax,
-                                             const double* __restrict__ M,
-                                             const double* __restrict__ M2, double sd, double sp,
-                                             int nel, int tid, int nthr) {
-  constexpr int BB = B * B, BBB = B * B * B;
-  for (int task = tid; task < nel * BB; task += nthr) {
-    const int el = task / BB, line = task - el * BB;
-    const int i = line / B, j = line - i * B;
-    // stride of the contracted axis and base of the line inside the block
-    const int st = ax == 0 ? BB : (ax == 1 ? B : 1);
-    const int base = ax == 0 ? (i * B + j) : (ax == 1 ? (i * BB + j) : (i * BB + j * B));
-    const double* s = src + el * BBB + base;
-    double* d = dst + el * BBB + base;
-    double v[B];
+__global__ __launch_bounds__(256) void op3_axis0_kernel(const double* __restrict__ Z1,
+                                                        const double* __restrict__ Z2,
+                                                        const double* __restrict__ f, void* out,
+                                                        int out_f32, int K0, int m0, long long plane,
+                                                        double s0, OpMats mt) {
+  constexpr int B = NO + 1;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= plane * K0) return;
+  const long long pt = t % plane;
+  const int e = (int)(t / plane) + 1;
+  auto zat = [&](const double* Z, int g) -> double {   // position g = 0..nK0 (0 and nK0: boundary)
+    return (g >= 1 && g <= m0) ? Z[(long long)(g - 1) * plane + pt] : 0.0;
+  };
+  double z1[B], z2[B], z1n[B], z2n[B];
 #pragma unroll
-    for (int r = 0; r < B; ++r) v[r] = s[r * st];
+  for (int q = 0; q < B; ++q) {
+    const int g = NO * (e - 1) + q;
+    z1[q] = zat(Z1, g);
+    z2[q] = zat(Z2, g);
+    z1n[q] = e < K0 ? zat(Z1, g + NO) : 0.0;
+    z2n[q] = e < K0 ? zat(Z2, g + NO) : 0.0;
+  }
+  const double* A0 = mt.A0;
+  const double* C0 = mt.C0;
+#pragma unroll
+  for (int r = 1; r <= NO; ++r) {
+    const int g = NO * (e - 1) + r;
+    if (g > m0) break;
+    double ap = 0.0, cd = 0.0;
 #pragma unroll
     for (int q = 0; q < B; ++q) {
-      double t = 0.0;
-      if (MODE == 0) {
-#pragma unroll
-        for (int r = 0; r < B; ++r) t += M[q * B + r] * v[r];
-      } else {
-        double dd = 0.0;
-#pragma unroll
-        for (int r = 0; r < B; ++r)
-          if (r != q) dd += M[q * B + r] * (v[r] - v[q]);
-        if (MODE == 1) {
-          t = dd;
-        } else {
-          double pp = 0.0;
-#pragma unroll
-          for (int r = 0; r < B; ++r) pp += M2[q * B + r] * v[r];
-          t = sd * dd + sp * pp;
-        }
-      }
-      if (ACC) d[q * st] += t; else d[q * st] = t;
+      if (q != r) ap += A0[r * B + q] * (z1[q] - z1[r]);
+      cd += C0[r * B + q] * z2[q];
     }
-  }
-}
-
-template <int NO>
-__global__ __launch_bounds__(256) void op3_element_kernel(OpArgs a, const double* u,
-                                                          long long nel) {
-  using SH = Op3Shape<NO>;
-  constexpr int B = SH::B, BBB = SH::BBB, EPW = SH::EPW;
-  extern __shared__ __align__(16) unsigned char smem[];
-  double* U = reinterpret_cast<double*>(smem);
-  double* X = U + EPW * BBB;
-  double* Y = X + EPW * BBB;
-  double* Z = Y + EPW * BBB;
-  double* P = Z + EPW * BBB;
-  double* W = P + EPW * BBB;
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const long long e0 = (long long)blockIdx.x * EPW;
-  const int ne = (int)min((long long)EPW, nel - e0);
-  const int K1 = a.K[1], K2 = a.K[2], m1 = a.m[1], m2 = a.m[2];
-  for (int t = tid; t < ne * BBB; t += nthr) {
-    const int el = t / BBB, loc = t - el * BBB;
-    const long long eg = e0 + el;
-    const int k0 = (int)(eg / ((long long)K1 * K2)), rem = (int)(eg - (long long)k0 * K1 * K2);
-    const int k1 = rem / K2, k2 = rem - k1 * K2;
-    const int r0 = loc / (B * B), r1 = (loc / B) % B, r2 = loc % B;
-    const int g0 = NO * k0 + r0, g1 = NO * k1 + r1, g2 = NO * k2 + r2;
-    double v = 0.0;
-    if (g0 >= 1 && g0 <= a.m[0] && g1 >= 1 && g1 <= m1 && g2 >= 1 && g2 <= m2)
-      v = u[((long long)(g0 - 1) * m1 + (g1 - 1)) * m2 + (g2 - 1)];
-    U[t] = v;
-  }
-  __syncthreads();
-  const double s0 = a.scale[0], s1 = a.scale[1], s2 = a.scale[2], al = a.alpha;
-  op3_contract<B, 1, false>(U, X, 0, a.A[0], nullptr, 1.0, 0.0, ne, tid, nthr);
-  op3_contract<B, 1, false>(U, Y, 1, a.A[1], nullptr, 1.0, 0.0, ne, tid, nthr);
-  op3_contract<B, 2, false>(U, Z, 2, a.A[2], a.C[2], s2, al, ne, tid, nthr);
-  __syncthreads();
-  op3_contract<B, 0, false>(X, P, 1, a.C[1], nullptr, 0.0, 0.0, ne, tid, nthr);
-  op3_contract<B, 0, false>(Z, W, 0, a.C[0], nullptr, 0.0, 0.0, ne, tid, nthr);
-  __syncthreads();
-  // P = s0 P + s1 C_0 Y
-  for (int t = tid; t < ne * BBB; t += nthr) P[t] *= s0;
-  __syncthreads();
-  op3_contract<B, 0, false>(Y, X, 0, a.C[0], nullptr, 0.0, 0.0, ne, tid, nthr);
-  __syncthreads();
-  for (int t = tid; t < ne * BBB; t += nthr) P[t] += s1 * X[t];
-  __syncthreads();
-  op3_contract<B, 0, false>(P, U, 2, a.C[2], nullptr, 0.0, 0.0, ne, tid, nthr);
-  __syncthreads();
-  op3_contract<B, 0, true>(W, U, 1, a.C[1], nullptr, 0.0, 0.0, ne, tid, nthr);
-  __syncthreads();
-  double* out = a.elem + e0 * BBB;
-  for (int t = tid; t < ne * BBB; t += nthr) out[t] = U[t];
-}
-
-// Per point: the sum of the element outputs holding it, then f - sum (or sum).
-template <int NO>
-__global__ __launch_bounds__(256) void op3_gather_kernel(OpArgs a, const double* f, void* out,
-                                                         long long total) {
-  constexpr int B = NO + 1, BBB = B * B * B;
-  const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= total) return;
-  const int m1 = a.m[1], m2 = a.m[2], K1 = a.K[1], K2 = a.K[2];
-  const int q0 = (int)(idx / ((long long)m1 * m2)), rem = (int)(idx - (long long)q0 * m1 * m2);
-  const int q1 = rem / m2, q2 = rem - q1 * m2;
-  int ne[3], el[3][2], rl[3][2];
-  const int qs[3] = {q0, q1, q2};
+    if (r == NO) {   // the node also takes row 0 of element e+1
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const int g = qs[i] + 1;
-    if (g % NO == 0) {
-      ne[i] = 2;
-      el[i][0] = g / NO - 1; rl[i][0] = NO;
-      el[i][1] = g / NO;     rl[i][1] = 0;
-    } else {
-      ne[i] = 1;
-      el[i][0] = g / NO; rl[i][0] = g % NO;
+      for (int q = 1; q < B; ++q) ap += A0[q] * (z1n[q] - z1n[0]);
+#pragma unroll
+      for (int q = 0; q < B; ++q) cd += C0[q] * z2n[q];
     }
+    const long long idx = (long long)(g - 1) * plane + pt;
+    const double lu = s0 * ap + cd;
+    const double res = f ? f[idx] - lu : lu;
+    if (out_f32) static_cast<float*>(out)[idx] = (float)res;
+    else static_cast<double*>(out)[idx] = res;
   }
-  double acc = 0.0;
-  for (int c0 = 0; c0 < ne[0]; ++c0)
-    for (int c1 = 0; c1 < ne[1]; ++c1)
-      for (int c2 = 0; c2 < ne[2]; ++c2) {
-        const long long e = ((long long)el[0][c0] * K1 + el[1][c1]) * K2 + el[2][c2];
-        const int loc = (rl[0][c0] * B + rl[1][c1]) * B + rl[2][c2];
-        acc += a.elem[e * BBB + loc];
-      }
-  const double res = f ? f[idx] - acc : acc;
-  if (a.out_f32) static_cast<float*>(out)[idx] = (float)res;
-  else static_cast<double*>(out)[idx] = res;
 }
 
 template <int NO>
 hipError_t launch_op3_order(const OpArgs& a, hipStream_t s) {
-  using SH = Op3Shape<NO>;
-  const long long nel = (long long)a.K[0] * a.K[1] * a.K[2];
-  const long long per = (long long)a.m[0] * a.m[1] * a.m[2];
-  const unsigned blocks = (unsigned)((nel + SH::EPW - 1) / SH::EPW);
-  static bool raised = false;
-  if (!raised) {
-    hipError_t e = hipFuncSetAttribute((const void*)op3_element_kernel<NO>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    raised = true;
+  const long long plane = (long long)a.m[1] * a.m[2];
+  const long long per = (long long)a.m[0] * plane;
+  if (!a.hA[0] || !a.hC[0] || a.m[0] > 65535) return hipErrorInvalidValue;
+  double* Z1 = a.elem;
+  double* Z2 = a.elem + per;
+  OpMats mt{};
+  for (int i = 0; i < (NO + 1) * (NO + 1); ++i) {
+    mt.A0[i] = a.hA[0][i];
+    mt.C0[i] = a.hC[0][i];
   }
+  // the planes of constant axis-0 index as the 2D kernel's right-hand sides
+  OpArgs b{};
+  b.N = 2;
+  b.f = nullptr;
+  b.out_f32 = 0;
+  b.nrhs = a.m[0];
+  for (int i = 0; i < 2; ++i) {
+    b.n[i] = a.n[i + 1];
+    b.K[i] = a.K[i + 1];
+    b.m[i] = a.m[i + 1];
+    b.A[i] = a.A[i + 1];
+    b.C[i] = a.C[i + 1];
+    b.hA[i] = a.hA[i + 1];
+    b.hC[i] = a.hC[i + 1];
+  }
+  const unsigned blocks = (unsigned)((plane * a.K[0] + 255) / 256);
+  b.scale[0] = a.scale[1];
+  b.scale[1] = a.scale[2];
+  b.alpha = a.alpha;
+  b.out = Z2;
+  b.elem = Z1;   // the mass product C1 (x) C2 u, from the same tiles
   for (int r = 0; r < a.nrhs; ++r) {
-    const double* u = a.u + r * per;
+    b.u = a.u + r * per;
+    hipError_t e = launch_op2_sf<NO, true>(b, s);
+    if (e != hipSuccess) return e;
     const double* f = a.f ? a.f + r * per : nullptr;
     void* out = a.out_f32 ? (void*)(static_cast<float*>(a.out) + r * per)
                           : (void*)(static_cast<double*>(a.out) + r * per);
-    hipLaunchKernelGGL(op3_element_kernel<NO>, dim3(blocks), dim3(256), SH::LDS, s, a, u, nel);
-    hipLaunchKernelGGL(op3_gather_kernel<NO>, dim3((unsigned)((per + 255) / 256)), dim3(256), 0,
-                       s, a, f, out, per);
+    hipLaunchKernelGGL(op3_axis0_kernel<NO>, dim3(blocks), dim3(256), 0, s, Z1, Z2, f, out, a.out_f32,
+                       a.K[0], a.m[0], plane, a.scale[0], mt);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 // LDS bytes of a 2D tile of TE0 x TE1 owned elements.
@@ -921,8 +870,7 @@ hipError_t launch_dirichlet_lift(const OpArgs& a, const double* bext, const doub
 
 size_t op3_elem_doubles(const OpArgs& a) {
   if (a.N != 3 || a.n[0] != a.n[1] || a.n[1] != a.n[2]) return 0;
-  const size_t b = (size_t)a.n[0] + 1;
-  return (size_t)a.K[0] * a.K[1] * a.K[2] * b * b * b;
+  return 2 * (size_t)a.m[0] * a.m[1] * a.m[2];   // Z1, Z2 of one right-hand side
 }
 
 }  // namespace hofem
