@@ -299,8 +299,9 @@ int hofem_apply_coef_operator(hofem_solver solver, const hofem_coef* coef, const
                               void* stream);
 
 /* Workspace bytes of hofem_apply_operator and hofem_apply_mass: for N = 3
- * with equal orders the element outputs of one right-hand side,
- * prod K_i (n+1)^3 doubles (rounded up to 256 bytes); 0 otherwise. */
+ * with equal orders two grids of one right-hand side (the planes' stiffness
+ * and mass products), 2 prod m_i doubles (rounded up to 256 bytes); 0
+ * otherwise. */
 int hofem_operator_workspace_bytes(hofem_solver solver, size_t* bytes);
 
 /* out = L u with L the operator of eq. (bvp glob 2), FP64, matrix-free
@@ -360,7 +361,7 @@ int hofem_stepper_create(hofem_solver solver, int scheme, hofem_stepper* out);
 void hofem_stepper_destroy(hofem_stepper stepper);
 
 /* Workspace of hofem_stepper_run for nrhs right-hand sides: one FP64 grid
- * (two for the wave scheme) and the operator's element buffer. */
+ * (two for the wave scheme) and the operator's workspace. */
 int hofem_stepper_workspace_bytes(hofem_stepper stepper, int nrhs, size_t* bytes);
 
 /* Advances u_dev (in: u^n, out: u^{n+nsteps}) by nsteps steps.  f_dev: the
@@ -384,7 +385,7 @@ int hofem_stepper_run(hofem_stepper stepper, const double* f_dev, double* u_dev,
  * library's load until the process ends.  The problem must fit it:
  * hofem_solver_workspace_bytes(solver, HOFEM_MODE_FP32_IR, nrhs) <= 64 MiB
  * (the FP32 residual grid of nrhs right-hand sides, 16 KB of norm partials
- * and, in 3D with equal orders, the operator's element outputs; about 16
+ * and, in 3D with equal orders, the operator's two plane-product grids; about 16
  * million unknowns in all), else HOFEM_ETOOBIG before any work.  Allocates
  * nothing and records no timing events.  Every call on a device shares that
  * device's scratch: calls that overlap on one device (other streams, other

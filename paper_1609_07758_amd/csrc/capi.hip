@@ -1628,7 +1628,7 @@ int hofem_solve_ir_noalloc(hofem_solver S, const double* f_dev, double* u_dev, i
   if (rc != HOFEM_OK) return rc;
   // every byte the refinement reads from the scratch is written first in
   // the same call (the residual grid by the operator, the norm partials by
-  // the norm kernels, the 3D element outputs by the operator), so nothing
+  // the norm kernels, the 3D plane-product grids by the operator), so nothing
   // needs clearing
   g_no_events = true;
   const int st = hofem_solve(S, HOFEM_MODE_FP32_IR, f_dev, u_dev, nrhs, ws, kScratchBytes,

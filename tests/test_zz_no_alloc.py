@@ -4,7 +4,7 @@ scratch) against the entry point that takes a caller workspace
 (hofem_solve, mode FP32_IR): the same kernels in the same order, so equal
 bit for bit, and within 1e-12 of the oracle.  Two calls in a row on the
 shared scratch, the second with a smaller problem; a 3D problem whose
-operator keeps its element outputs in the scratch; a problem too large for
+operator keeps its plane-product grids in the scratch; a problem too large for
 the scratch is refused before any work."""
 import ctypes
 
