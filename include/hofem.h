@@ -127,18 +127,23 @@ enum hofem_bc { HOFEM_BC_DIRICHLET = 0, HOFEM_BC_PERIODIC = 1, HOFEM_BC_NEUMANN 
 
 /* A Neumann axis (natural boundary conditions at x = 0 and x = X) holds the
  * m = nK + 1 values at the points g h / n, g = 0..nK, boundary nodes
- * included, in physical order.  Its pencil is the even half of the periodic
- * pencil of 2K elements on [-X, X) (the reflection maps Bloch waves of wave
- * number k to -k), so a solve reflects f^h into that periodic grid (the two
- * boundary rows doubled, as the reflected pencil counts them twice), runs
- * the periodic FP64 passes there and keeps the caller's half: K <= 512
- * (HOFEM_EUNSUPPORTED otherwise), and an FP64 solve of a solver with a
- * Neumann axis takes a workspace of the reflected grid
- * (hofem_solver_workspace_bytes; HOFEM_EINVAL without it).  The plan's
- * tables (hofem_plan1d_table) are those of the periodic axis of 2K elements
- * (table 0 has 2nK eigenvalues); hofem_plan1d_dim reports nK + 1.
- * hofem_forward and hofem_inverse return HOFEM_EUNSUPPORTED for a solver
- * with a Neumann axis; the other restrictions are those of periodic axes. */
+ * included, in physical order.  Its eigenvectors follow Theorem 1 with
+ * cosines for sines: for k = 1..K-1 and l = 1..n, node j: cos(pi k j / K),
+ * point s of element e: cos(pi k (e-1)/K) p_s + cos(pi k e/K) p_{n-s}, with
+ * the eigenvalue, p_k^(l) and norm ||s_k^(l)||_C^2 of the Dirichlet wave
+ * number k (they satisfy the boundary rows because a boundary node belongs
+ * to one element: its condensed diagonal is half the interior one).  The
+ * other n + 1 are band-edge vectors: a cell (node a, interior values
+ * w_1..w_{n-1}) repeated with the factor 1 (theta = 0; w_s = w_{n-s}) or
+ * (-1)^j (theta = pi; w_s = -w_{n-s}), the eigenvectors of the cell pencil
+ * restricted to those even cells, w^T C_cell w = 1 (so ||v||_C^2 = K).
+ * The passes take DCT-I transforms of length K + 1 by K-point FFTs.
+ * Coefficient order: q = (l-1)(K-1) + (k-1) for k = 1..K-1, then n(K-1) + b
+ * for the band-edge vectors (b < n/2 + 1 at theta = 0, the rest at pi).
+ * Neumann axes run in HOFEM_MODE_FP64 only (hofem_solve, hofem_forward,
+ * hofem_inverse) and need K a power of two; the other restrictions are
+ * those of periodic axes (a solver without a Dirichlet axis needs
+ * alpha > 0). */
 
 /* hofem_plan1d_create with a boundary condition (enum hofem_bc; else
  * HOFEM_EINVAL).  hofem_plan1d_create(n, K, out) is
@@ -166,10 +171,12 @@ int hofem_plan1d_dim(hofem_plan1d plan, int* m);
  *  12  plans with K not a power of two: S, the unnormalised eigenvectors of
  *      Theorem 1 as columns in coefficient order, row major (m^2 values)
  *  13  the same plans: S diag(1 / ||s||_C^2) (1/K for the k = 0 columns)
- * Tables 1 and 2 exist for Dirichlet plans only, 10 and 11 for periodic
- * plans only, 12 and 13 for dense ones (HOFEM_EINVAL otherwise); table 0 of
- * a periodic plan holds its m = nK eigenvalues in the periodic coefficient
- * order.
+ *  14  Neumann plans: the n + 1 band-edge cells (a, w_1..w_{n-1}) at index
+ *      b n + s, theta = 0 first ((n+1) n values)
+ * Tables 1 and 2 exist for Dirichlet and Neumann plans, 10 and 11 for
+ * periodic plans only, 12 and 13 for dense ones, 14 for Neumann ones
+ * (HOFEM_EINVAL otherwise); table 0 holds the m eigenvalues in the axis's
+ * own coefficient order (periodic and Neumann orders above).
  *
  * K need not be a power of two for a Dirichlet axis: with m = nK - 1 <= 4095
  * the plan then also holds S and its scaled form, and the solver applies

@@ -34,7 +34,7 @@ HOFEM_ETOOBIG = -7
 
 MODES = {"fp64": 0, "fp32": 1, "fp32_ir": 2, "fp32_pcg": 3, "fp64_b": 4}
 TABLES = {"lam": 0, "p": 1, "inorm": 2, "E": 3, "A": 4, "C": 5, "gx": 6, "gw": 7, "B": 8, "D": 9,
-          "wr": 10, "wi": 11, "S": 12, "St": 13}
+          "wr": 10, "wi": 11, "S": 12, "St": 13, "band": 14}
 BCS = {"dirichlet": 0, "periodic": 1, "neumann": 2}
 
 # Names and signatures of every entry point of include/hofem.h.
@@ -546,7 +546,7 @@ def hofem_kernel_hash():
 
 class Plan1D:
     """1D eigen data for order n and K elements (host, binary128 precompute);
-    bc "dirichlet" or "periodic"."""
+    bc "dirichlet", "periodic" or "neumann"."""
 
     def __init__(self, n, K, bc="dirichlet"):
         self.n, self.K, self.bc = int(n), int(K), bc
@@ -562,14 +562,11 @@ class Plan1D:
 
     def table(self, which):
         n, K = self.n, self.K
-        # a Neumann plan carries the tables of the periodic axis of 2K elements
-        Kt = 2 * K if self.bc == "neumann" else K
-        nlam = n * Kt if self.bc != "dirichlet" else self.m
-        counts = {"lam": nlam, "p": (K - 1) * n * (n - 1), "inorm": (K - 1) * n,
+        counts = {"lam": self.m, "p": (K - 1) * n * (n - 1), "inorm": (K - 1) * n,
                   "E": (n - 1) ** 2, "A": (n + 1) ** 2, "C": (n + 1) ** 2,
                   "gx": n + 1, "gw": n + 1, "B": (n + 1) ** 2, "D": (n + 1) ** 2,
-                  "wr": (Kt // 2 + 1) * n * n, "wi": (Kt // 2 + 1) * n * n,
-                  "S": self.m * self.m, "St": self.m * self.m}
+                  "wr": (K // 2 + 1) * n * n, "wi": (K // 2 + 1) * n * n,
+                  "S": self.m * self.m, "St": self.m * self.m, "band": (n + 1) * n}
         return hofem_plan1d_table(self.handle, which, counts[which])
 
     def close(self):
@@ -660,7 +657,7 @@ class Solver:
         if u is None:
             u = torch.empty_like(f)
         self._check_grid(u, dt, nrhs, "u")
-        if ws is None:   # (FP64 needs one only with a Neumann axis)
+        if ws is None:   # (FP64 needs one only with a dense axis)
             ws = self.workspace(mode, nrhs, f.device)
         info, st = hofem_solve(self.handle, mode, f, u, nrhs, ws, max_iter, tol, stream, want_info,
                                raise_noconv)

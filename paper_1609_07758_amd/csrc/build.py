@@ -51,7 +51,7 @@ def _jobs():
         jobs.append(([HIPCC] + HIP_FLAGS + [f"-DHOFEM_ORDER={n}", "-c",
                                             os.path.join(CSRC, "linepass.hip"), "-o", o], o))
     for src in ("linepass_dispatch.hip", "operator.hip", "pcg.hip", "capi.hip", "batch.hip",
-                "timestep.hip", "banded.hip", "periodic.hip", "dense.hip"):
+                "timestep.hip", "banded.hip", "periodic.hip", "neumann.hip", "dense.hip"):
         o = os.path.join(OUT_DIR, src.replace(".hip", ".o"))
         extra = [f'-DHOFEM_KERNEL_HASH="{kernel_hash()}"'] if src == "capi.hip" else []
         jobs.append(([HIPCC] + HIP_FLAGS + extra + ["-c", os.path.join(CSRC, src), "-o", o], o))

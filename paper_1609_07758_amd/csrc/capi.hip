@@ -33,6 +33,7 @@ using namespace hofem;
 struct PlanOff {
   size_t lam, blk64, E64, tw64, sn64, blk32, E32, tw32, sn32, A, C, B, D, Dh, gw;
   size_t S = 0, St = 0;   // dense axes (K not a power of two)
+  size_t band = 0;        // Neumann axes: band-edge vectors
 };
 
 struct hofem_plan1d_s {
@@ -68,10 +69,8 @@ namespace {
 
 struct DevAxis {
   int bc = 0;                   // 0: Dirichlet, 1: periodic, 2: Neumann
-  // n, K, m of the passes (a Neumann axis runs as the periodic axis of 2K
-  // elements on its even reflection: K = 2 K_own, m = 2 n K_own); mu: the
-  // axis's unknowns in the caller's grid (n K_own + 1 for Neumann, else m)
-  int n = 0, K = 0, m = 0, mu = 0;
+  // order, elements and unknowns of the axis (nK - 1, nK, nK + 1)
+  int n = 0, K = 0, m = 0;
   // K not a power of two: transforms by the dense matrices S (inverse) and
   // St = S diag(1 / ||s||^2) (forward: St^T y)
   int dense = 0;
@@ -120,8 +119,7 @@ struct hofem_solver_s {
   double alpha = 0;
   int device = 0;
   DevAxis ax[3];
-  size_t per_rhs = 0;   // unknowns of one right-hand side (the caller's grid)
-  size_t per_ext = 0;   // the grid the passes run on (Neumann axes reflected)
+  size_t per_rhs = 0;   // unknowns of one right-hand side
   double* dense_tmp = nullptr;   // scratch grid of the dense passes (set per solve)
   // per-pass timing
   bool timing = false;
@@ -291,7 +289,7 @@ int run_list(hofem_solver_s* S, const std::vector<PassSpec>& list, bool f64, con
       if (list[i].il_out) a.ilv_out = rows;
     }
     static const int in_bytes[6] = {8, 4, 8, 4, 4, 8}, out_bytes[6] = {8, 4, 4, 8, 16, 8};
-    const double bytes = (double)S->per_ext * nrhs * (in_bytes[dt] + out_bytes[dt]);
+    const double bytes = (double)S->per_rhs * nrhs * (in_bytes[dt] + out_bytes[dt]);
     LaunchTimer tm(S, st, list[i].kind == PASS_INV_ACC ? PASS_INV : list[i].kind, list[i].axis,
                    f64 ? 1 : 0, bytes);
     if (S->ax[list[i].axis].dense) {
@@ -300,7 +298,8 @@ int run_list(hofem_solver_s* S, const std::vector<PassSpec>& list, bool f64, con
       if (rc != HOFEM_OK) return rc;
     } else if (S->ax[list[i].axis].bc != 0) {
       if (dt != 0) return HOFEM_EUNSUPPORTED;   // periodic / Neumann axes: FP64 passes only
-      HIPCHK(launch_periodic(list[i].kind, a, st));
+      if (S->ax[list[i].axis].bc == 1) HIPCHK(launch_periodic(list[i].kind, a, st));
+      else HIPCHK(launch_neumann(list[i].kind, a, st));
     } else {
       HIPCHK(launch_pass(list[i].kind, dt, a, st));
     }
@@ -401,32 +400,9 @@ bool has_dense(const hofem_solver_s* S) {
   return false;
 }
 
-// Scratch grid of the dense passes (the grid the passes run on).
+// Scratch grid of the dense passes.
 size_t dense_bytes(const hofem_solver_s* S, int nrhs) {
-  return has_dense(S) ? (S->per_ext * (size_t)nrhs * sizeof(double) + 255) & ~size_t(255) : 0;
-}
-
-bool has_neumann(const hofem_solver_s* S) {
-  for (int i = 0; i < S->N; ++i)
-    if (S->ax[i].bc == 2) return true;
-  return false;
-}
-
-// Workspace of an FP64 solve with Neumann axes: the reflected grid.
-size_t neumann_bytes(const hofem_solver_s* S, int nrhs) {
-  return (S->per_ext * (size_t)nrhs * sizeof(double) + 255) & ~size_t(255);
-}
-
-EvenArgs even_args(const hofem_solver_s* S, int nrhs) {
-  EvenArgs e{};
-  e.N = S->N;
-  for (int i = 0; i < S->N; ++i) {
-    e.me[i] = S->ax[i].m;
-    e.mu[i] = S->ax[i].mu;
-    e.neu[i] = S->ax[i].bc == 2 ? 1 : 0;
-  }
-  e.nrhs = nrhs;
-  return e;
+  return has_dense(S) ? (S->per_rhs * (size_t)nrhs * sizeof(double) + 255) & ~size_t(255) : 0;
 }
 
 size_t ir_workspace(const hofem_solver_s* S, int nrhs) {
@@ -676,8 +652,8 @@ namespace {
 std::vector<unsigned char> pack_plan(const Plan1DData& d, PlanOff* off) {
   Packer pk;
   const int n = d.n, K = d.K;
-  if (d.bc != 0) {
-    // periodic (and Neumann: the periodic axis of 2K elements): eigenvalues, Bloch eigenvectors (complex FP64, blocked by
+  if (d.bc == 1) {
+    // periodic: eigenvalues, Bloch eigenvectors (complex FP64, blocked by
     // 64 wave numbers: entry e = l n + s of wave number k at
     // ((k / 64) n^2 + e) 64 + k % 64, so that a wavefront reads one entry
     // of 64 consecutive k with one contiguous 1 KB access), twiddles, local
@@ -740,6 +716,7 @@ std::vector<unsigned char> pack_plan(const Plan1DData& d, PlanOff* off) {
     off->S = pk.add_f64(d.S);
     off->St = pk.add_f64(d.St);
   }
+  if (d.bc == 2) off->band = pk.add_f64(d.band);
   pk.bytes.resize((pk.bytes.size() + 255) & ~size_t(255), 0);
   return pk.bytes;
 }
@@ -843,7 +820,7 @@ void hofem_plan1d_destroy(hofem_plan1d plan) { delete plan; }
 
 int hofem_plan1d_dim(hofem_plan1d plan, int* m) {
   if (!plan || !m) return HOFEM_EINVAL;
-  *m = plan->d.mu;
+  *m = plan->d.m;
   return HOFEM_OK;
 }
 
@@ -853,8 +830,11 @@ int hofem_plan1d_table(hofem_plan1d plan, int which, double* out_host, size_t le
   const int n = d.n, K = d.K;
   const std::vector<double>* v = nullptr;
   size_t count = 0;
-  const bool dirichlet_only = which == 1 || which == 2, periodic_only = which == 10 || which == 11;
-  if ((dirichlet_only && d.bc != 0) || (periodic_only && d.bc == 0)) return HOFEM_EINVAL;
+  // p and 1/||s||^2 of the Dirichlet and Neumann axes, Bloch vectors of the
+  // periodic ones, band-edge vectors of the Neumann ones
+  const bool sine_tabs = which == 1 || which == 2, periodic_only = which == 10 || which == 11;
+  if ((sine_tabs && d.bc == 1) || (periodic_only && d.bc != 1) || (which == 14 && d.bc != 2))
+    return HOFEM_EINVAL;
   switch (which) {
     case 0: v = &d.lam; count = d.m; break;
     case 1: v = &d.p; count = (size_t)(K - 1) * n * (n - 1); break;
@@ -870,6 +850,7 @@ int hofem_plan1d_table(hofem_plan1d plan, int which, double* out_host, size_t le
     case 11: v = &d.wi; count = (size_t)(K / 2 + 1) * n * n; break;
     case 12: v = &d.S; count = d.dense ? (size_t)d.m * d.m : 0; break;
     case 13: v = &d.St; count = d.dense ? (size_t)d.m * d.m : 0; break;
+    case 14: v = &d.band; count = (size_t)(n + 1) * n; break;
     default: return HOFEM_EINVAL;
   }
   if ((which == 12 || which == 13) && !d.dense) return HOFEM_EINVAL;
@@ -892,7 +873,7 @@ int hofem_solver_create(int N, const hofem_plan1d* plans, const double* X, doubl
   double dmin = alpha;
   for (int i = 0; i < N; ++i) {
     const Plan1DData& d = plans[i]->d;
-    const double h = X[i] / d.kn;
+    const double h = X[i] / d.K;
     dmin += 4.0 / (h * h) * *std::min_element(d.lam.begin(), d.lam.end());
   }
   if (!(dmin > 0)) return HOFEM_ENOTPOSDEF;
@@ -910,7 +891,6 @@ int hofem_solver_create(int N, const hofem_plan1d* plans, const double* X, doubl
   S->N = N;
   S->alpha = alpha;
   S->per_rhs = 1;
-  S->per_ext = 1;
   S->device = cur;
   for (int i = 0; i < N; ++i) {
     const hofem_plan1d_s* P = plans[i];
@@ -920,19 +900,18 @@ int hofem_solver_create(int N, const hofem_plan1d* plans, const double* X, doubl
     ax.n = d.n;
     ax.K = d.K;
     ax.m = d.m;
-    ax.mu = d.mu;
     ax.X = X[i];
-    const double h = X[i] / d.kn;
+    const double h = X[i] / d.K;
     ax.scale = 4.0 / (h * h);
-    S->per_rhs *= (size_t)d.mu;
-    S->per_ext *= (size_t)d.m;
+    S->per_rhs *= (size_t)d.m;
     ax.hA = d.A;
     ax.hC = d.C;
     const unsigned char* b = P->dev;
     const PlanOff& o = P->off;
     const double* lam = reinterpret_cast<const double*>(b + o.lam);
-    ax.t64 = AxisTab{b + o.blk64, b + o.E64, b + o.tw64, b + o.sn64, lam, ax.n, ax.K, ax.m};
-    ax.t32 = AxisTab{b + o.blk32, b + o.E32, b + o.tw32, b + o.sn32, lam, ax.n, ax.K, ax.m};
+    const double* band = d.bc == 2 ? reinterpret_cast<const double*>(b + o.band) : nullptr;
+    ax.t64 = AxisTab{b + o.blk64, b + o.E64, b + o.tw64, b + o.sn64, lam, ax.n, ax.K, ax.m, band};
+    ax.t32 = AxisTab{b + o.blk32, b + o.E32, b + o.tw32, b + o.sn32, lam, ax.n, ax.K, ax.m, band};
     ax.A = reinterpret_cast<const double*>(b + o.A);
     ax.C = reinterpret_cast<const double*>(b + o.C);
     ax.B = reinterpret_cast<const double*>(b + o.B);
@@ -1007,7 +986,7 @@ int hofem_solver_workspace_bytes(hofem_solver solver, int mode, int nrhs, size_t
   if (!solver || !bytes || nrhs < 1) return HOFEM_EINVAL;
   switch (mode) {
     case HOFEM_MODE_FP64:
-      *bytes = (has_neumann(solver) ? neumann_bytes(solver, nrhs) : 0) + dense_bytes(solver, nrhs);
+      *bytes = dense_bytes(solver, nrhs);
       return HOFEM_OK;
     case HOFEM_MODE_FP32:
     case HOFEM_MODE_FP64_B: *bytes = 0; return HOFEM_OK;
@@ -1021,11 +1000,9 @@ int hofem_solve(hofem_solver S, int mode, const void* f_dev, void* u_dev, int nr
                 size_t ws_bytes, int max_iter, double tol, void* stream, hofem_info* info) {
   if (!S || !f_dev || !u_dev || nrhs < 1) return HOFEM_EINVAL;
   if (mode != HOFEM_MODE_FP64 && (!all_dirichlet(S) || has_dense(S))) return HOFEM_EUNSUPPORTED;
-  const size_t ext_b = has_neumann(S) ? neumann_bytes(S, nrhs) : 0;
-  if (mode == HOFEM_MODE_FP64 && (ext_b || has_dense(S))) {
-    if (!ws_dev || ws_bytes < ext_b + dense_bytes(S, nrhs)) return HOFEM_EINVAL;
-    S->dense_tmp = has_dense(S) ? reinterpret_cast<double*>(static_cast<unsigned char*>(ws_dev) + ext_b)
-                                : nullptr;
+  if (mode == HOFEM_MODE_FP64 && has_dense(S)) {
+    if (!ws_dev || ws_bytes < dense_bytes(S, nrhs)) return HOFEM_EINVAL;
+    S->dense_tmp = static_cast<double*>(ws_dev);
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
   // graph replay: solves without host synchronisation, on a stream that can
@@ -1085,18 +1062,6 @@ int hofem_solve(hofem_solver S, int mode, const void* f_dev, void* u_dev, int nr
     return HOFEM_OK;
   }
   const std::vector<PassSpec> list = solve_list(S, mode == HOFEM_MODE_FP64, nrhs);
-  if (mode == HOFEM_MODE_FP64 && has_neumann(S)) {
-    // Neumann axes: reflect f^h (boundary rows doubled) into the workspace,
-    // solve the periodic problem there in place, keep the caller's half
-    double* e = static_cast<double*>(ws_dev);
-    const EvenArgs ea = even_args(S, nrhs);
-    HIPCHK(launch_even_extend(ea, static_cast<const double*>(f_dev), e, st));
-    const int rc = run_list(S, list, true, e, e, e, 0, 0, 0, 0, nrhs, st);
-    if (rc != HOFEM_OK) return rc;
-    HIPCHK(launch_even_restrict(ea, e, static_cast<double*>(u_dev), st));
-    if (info) *info = hofem_info{0, 0.0, 0.0};
-    return HOFEM_OK;
-  }
   if (mode == HOFEM_MODE_FP64 || mode == HOFEM_MODE_FP32) {
     const bool f64 = mode == HOFEM_MODE_FP64;
     const int dt = f64 ? 0 : 1;
@@ -1212,7 +1177,7 @@ int hofem_forward(hofem_solver S, int mode, const void* in_dev, void* out_dev, i
   if (!S || !in_dev || !out_dev || nrhs < 1) return HOFEM_EINVAL;
   if (mode != HOFEM_MODE_FP64 && !all_dirichlet(S)) return HOFEM_EUNSUPPORTED;
   if (mode != HOFEM_MODE_FP64 && mode != HOFEM_MODE_FP32) return HOFEM_EINVAL;
-  if (has_neumann(S) || has_dense(S)) return HOFEM_EUNSUPPORTED;   // no workspace argument
+  if (has_dense(S)) return HOFEM_EUNSUPPORTED;   // no workspace argument
   const bool f64 = mode == HOFEM_MODE_FP64;
   const int dt = f64 ? 0 : 1;
   std::vector<PassSpec> l;
@@ -1226,7 +1191,7 @@ int hofem_inverse(hofem_solver S, int mode, const void* in_dev, void* out_dev, i
   if (!S || !in_dev || !out_dev || nrhs < 1) return HOFEM_EINVAL;
   if (mode != HOFEM_MODE_FP64 && !all_dirichlet(S)) return HOFEM_EUNSUPPORTED;
   if (mode != HOFEM_MODE_FP64 && mode != HOFEM_MODE_FP32) return HOFEM_EINVAL;
-  if (has_neumann(S) || has_dense(S)) return HOFEM_EUNSUPPORTED;   // no workspace argument
+  if (has_dense(S)) return HOFEM_EUNSUPPORTED;   // no workspace argument
   const bool f64 = mode == HOFEM_MODE_FP64;
   const int dt = f64 ? 0 : 1;
   std::vector<PassSpec> l;

@@ -32,6 +32,7 @@ struct AxisTab {
   const void* sn;      // sin(pi t / K), t < K
   const double* lam;   // scaled eigenvalues in coefficient order (FP64)
   int n, K, m;
+  const double* band;  // Neumann axes: the n + 1 band-edge vectors (cells of n values)
 };
 
 // PASS_INV_ACC: the inverse pass adding its result to a double output
@@ -154,21 +155,14 @@ hipError_t launch_banded(const BandArgs& a, hipStream_t s);
 // eigenvalues in the periodic coefficient order.
 hipError_t launch_periodic(int kind, const PassArgs& a, hipStream_t s);
 
-// Neumann axes by even reflection.  Axis i of the caller's grid has mu[i]
-// points (n K + 1 on a Neumann axis: g = 0..nK), of the reflected grid me[i]
-// (2 n K: g' = 0..2nK-1, point g' = 2nK - g' of the mirror half).  extend:
-// e(g') = prod_i d_i f(g), g = g' or its mirror, d_i = 2 at the boundary
-// nodes g = 0, nK of a Neumann axis (the reflected pencil counts their rows
-// twice), else 1.  restrict: u(g) = e(g) on the caller's grid.  C order,
-// nrhs grids in sequence.
-struct EvenArgs {
-  int N;
-  long long me[3], mu[3];
-  int neu[3];
-  int nrhs;
-};
-hipError_t launch_even_extend(const EvenArgs& a, const double* f, double* e, hipStream_t s);
-hipError_t launch_even_restrict(const EvenArgs& a, const double* e, double* u, hipStream_t s);
+// Line passes along Neumann axes (FP64; kind PASS_FWD, PASS_INV or
+// PASS_FUSED).  A line holds the m = nK + 1 values of the axis (node j at
+// q = n j, j = 0..K; interior point s of element e at q = n (e-1) + s);
+// coefficients in the Neumann order q = (l-1)(K-1) + (k-1) for k = 1..K-1,
+// then n(K-1) + b for the band-edge vectors b = 0..n.  tab: the Dirichlet
+// tables of (n, K) (blocked p and 1/||s||^2, twiddles, sines), tab.lam the
+// eigenvalues in the Neumann order, tab.band the band-edge vectors.
+hipError_t launch_neumann(int kind, const PassArgs& a, hipStream_t s);
 
 // C_b = op(A_b) op(B_b) in FP64 on the matrix cores (dense transforms of
 // axes whose K is not a power of two): row-major M x K, K x N, M x N after

@@ -97,20 +97,32 @@ __global__ __launch_bounds__(kPerMaxThreads) void periodic_pass(PassArgs a) {
     }
   };
   const int items_m = cfast ? cb * m : cv * m;
+  // kIO global accesses in flight per lane in the load and the scatter
+  constexpr int kIO = 16;
 
   if (MODE == PASS_FWD || MODE == PASS_FUSED) {
-    for (int i = tid; i < items_m; i += nthr) {
-      int c, q;
-      split(i, m, c, q);
-      if (c >= cv) continue;
-      const int j = q / n, s = q - j * n;
-      const double v = src[lbase(c) + (long long)q * inner];
-      cx<double>& e = slot(c, s >> 1, j);
-      if (s & 1) {
-        e.y = v;
-      } else {
-        e.x = v;
-        if (s == n - 1) e.y = 0.0;   // odd n: the last pair has one component
+    for (int i0 = tid; i0 < items_m; i0 += kIO * nthr) {
+      double r[kIO];
+#pragma unroll
+      for (int u = 0; u < kIO; ++u) {
+        int c, q;
+        split(i0 + u * nthr, m, c, q);
+        const bool ok = i0 + u * nthr < items_m && c < cv;
+        r[u] = ok ? src[lbase(c) + (long long)q * inner] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kIO; ++u) {
+        int c, q;
+        split(i0 + u * nthr, m, c, q);
+        if (!(i0 + u * nthr < items_m && c < cv)) continue;
+        const int j = q / n, s = q - j * n;
+        cx<double>& e = slot(c, s >> 1, j);
+        if (s & 1) {
+          e.y = r[u];
+        } else {
+          e.x = r[u];
+          if (s == n - 1) e.y = 0.0;   // odd n: the last pair has one component
+        }
       }
     }
   }
@@ -225,13 +237,25 @@ __global__ __launch_bounds__(kPerMaxThreads) void periodic_pass(PassArgs a) {
   __syncthreads();
   transforms();   // FFT of conj(Z) = conj of the inverse transform
   __syncthreads();
-  for (int i = tid; i < items_m; i += nthr) {
-    int c, q;
-    split(i, m, c, q);
-    if (c >= cv) continue;
-    const int j = q / n, s = q - j * n;
-    const cx<double> e = slot(c, s >> 1, j);
-    dst[lbase(c) + (long long)q * inner] = (s & 1) ? -e.y : e.x;
+  for (int i0 = tid; i0 < items_m; i0 += kIO * nthr) {
+    double r[kIO];
+#pragma unroll
+    for (int u = 0; u < kIO; ++u) {
+      int c, q;
+      split(i0 + u * nthr, m, c, q);
+      r[u] = 0.0;
+      if (i0 + u * nthr < items_m && c < cv) {
+        const int j = q / n, s = q - j * n;
+        const cx<double> e = slot(c, s >> 1, j);
+        r[u] = (s & 1) ? -e.y : e.x;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kIO; ++u) {
+      int c, q;
+      split(i0 + u * nthr, m, c, q);
+      if (i0 + u * nthr < items_m && c < cv) dst[lbase(c) + (long long)q * inner] = r[u];
+    }
   }
 }
 
@@ -290,69 +314,7 @@ hipError_t launch_per_mode(const PassArgs& a, hipStream_t s) {
   }
 }
 
-// One thread per point of the reflected grid: its point in the caller's grid
-// and the boundary weights of the Neumann axes.
-__global__ __launch_bounds__(256) void even_extend_kernel(EvenArgs a, const double* __restrict__ f,
-                                                          double* __restrict__ e, long long total) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  long long r = i, src = 0, mul = 1;
-  double w = 1.0;
-  for (int d = a.N - 1; d >= 0; --d) {
-    long long g = r % a.me[d];
-    r /= a.me[d];
-    if (a.neu[d]) {
-      const long long half = a.me[d] / 2;   // nK: the far boundary node
-      if (g > half) g = a.me[d] - g;
-      if (g == 0 || g == half) w *= 2.0;
-    }
-    src += g * mul;
-    mul *= a.mu[d];
-  }
-  src += r * mul;   // right-hand side
-  e[i] = w * f[src];
-}
-
-__global__ __launch_bounds__(256) void even_restrict_kernel(EvenArgs a, const double* __restrict__ e,
-                                                            double* __restrict__ u, long long total) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  long long r = i, src = 0, mul = 1;
-  for (int d = a.N - 1; d >= 0; --d) {
-    const long long g = r % a.mu[d];
-    r /= a.mu[d];
-    src += g * mul;
-    mul *= a.me[d];
-  }
-  src += r * mul;
-  u[i] = e[src];
-}
-
-long long grid_points(const long long* m, int N, int nrhs) {
-  long long t = nrhs;
-  for (int d = 0; d < N; ++d) t *= m[d];
-  return t;
-}
-
 }  // namespace
-
-hipError_t launch_even_extend(const EvenArgs& a, const double* f, double* e, hipStream_t s) {
-  if (a.N < 1 || a.N > 3 || a.nrhs < 1) return hipErrorInvalidValue;
-  const long long total = grid_points(a.me, a.N, a.nrhs);
-  if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(even_extend_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a, f,
-                     e, total);
-  return hipGetLastError();
-}
-
-hipError_t launch_even_restrict(const EvenArgs& a, const double* e, double* u, hipStream_t s) {
-  if (a.N < 1 || a.N > 3 || a.nrhs < 1) return hipErrorInvalidValue;
-  const long long total = grid_points(a.mu, a.N, a.nrhs);
-  if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(even_restrict_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a, e,
-                     u, total);
-  return hipGetLastError();
-}
 
 hipError_t launch_periodic(int kind, const PassArgs& a, hipStream_t s) {
   if (a.nlines == 0) return hipSuccess;

@@ -295,8 +295,6 @@ int plan1d_build(int n, int K, Plan1DData* out) {
   out->n = n;
   out->K = K;
   out->m = m;
-  out->kn = K;
-  out->mu = m;
   out->A.assign(nb * nb, 0);
   out->C.assign(nb * nb, 0);
   for (int i = 0; i < nb * nb; ++i) {
@@ -511,8 +509,6 @@ int plan1d_build_periodic(int n, int K, Plan1DData* out) {
       }
     }
   }
-  out->kn = K;
-  out->mu = m;
   return 0;
 }
 
@@ -560,11 +556,92 @@ int plan1d_build_dense(Plan1DData* d) {
 }
 
 int plan1d_build_neumann(int n, int K, Plan1DData* out) {
-  if (K < 2 || K > 512 || (K & (K - 1)) != 0) return -1;
-  if (plan1d_build_periodic(n, 2 * K, out) != 0) return -1;
+  if (K < 2 || K > 1024 || (K & (K - 1)) != 0) return -1;
+  // the Dirichlet tables of (n, K): p_k^(l), 1 / ||s_k^(l)||^2, the
+  // eigenvalues of k = 1..K-1, twiddles, sines, local and Gauss tables
+  if (plan1d_build(n, K, out) != 0) return -1;
+  const int nb = n + 1, m = n * K + 1;
+  std::vector<q128> A, C, gx, gw, Bq, Dq;
+  local_matrices(n, A, C, gx, gw, Bq, Dq);
+  std::vector<double> lam(m, 0.0);
+  for (int l = 0; l < n; ++l)
+    for (int k = 1; k < K; ++k)
+      lam[(size_t)l * (K - 1) + (k - 1)] = out->lam[(size_t)(n - 1) + (size_t)l * (K - 1) + (k - 1)];
+  // Band edges theta = 0 (sg = 1) and theta = pi (sg = -1): a cell
+  // (node a, interior points w_1..w_{n-1}) repeated with the factor sg^j
+  // maps to the element values (a, w, sg a); the Neumann vectors among them
+  // are the even ones, w_s = sg w_{n-s} (the reflection about a node maps
+  // point s of one element to point n-s of its neighbour).
+  out->band.assign((size_t)(n + 1) * n, 0.0);
+  int b = 0;
+  for (int edge = 0; edge < 2; ++edge) {
+    const int sg = edge == 0 ? 1 : -1;
+    auto cell = [&](const std::vector<q128>& M) {
+      std::vector<q128> X((size_t)n * n, 0);
+      for (int r = 0; r < n; ++r)
+        for (int c = 0; c < n; ++c) {
+          q128 v = M[r * nb + c];
+          if (c == 0) v += sg * M[r * nb + n];
+          if (r == 0) v += sg * M[n * nb + c];
+          if (r == 0 && c == 0) v += M[n * nb + n];
+          X[r * n + c] = v;
+        }
+      return X;
+    };
+    const std::vector<q128> Ac = cell(A), Cc = cell(C);
+    // basis of the even cells: the node, then e_s + sg e_{n-s} (s < n-s),
+    // then the middle point for even n at theta = 0
+    std::vector<std::vector<q128>> basis;
+    {
+      std::vector<q128> e(n, 0);
+      e[0] = 1;
+      basis.push_back(e);
+    }
+    for (int s2 = 1; s2 < n; ++s2) {
+      std::vector<q128> e(n, 0);
+      if (2 * s2 < n) {
+        e[s2] = 1;
+        e[n - s2] = sg;
+        basis.push_back(e);
+      } else if (2 * s2 == n && sg == 1) {
+        e[s2] = 1;
+        basis.push_back(e);
+      }
+    }
+    const int ne = (int)basis.size();
+    std::vector<q128> Ar((size_t)ne * ne, 0), Cr((size_t)ne * ne, 0);
+    for (int i = 0; i < ne; ++i)
+      for (int j = 0; j < ne; ++j) {
+        q128 sa = 0, sc = 0;
+        for (int r = 0; r < n; ++r)
+          for (int c = 0; c < n; ++c) {
+            sa += basis[i][r] * Ac[r * n + c] * basis[j][c];
+            sc += basis[i][r] * Cc[r * n + c] * basis[j][c];
+          }
+        Ar[i * ne + j] = sa;
+        Cr[i * ne + j] = sc;
+      }
+    std::vector<q128> lr, Er;
+    interior_eigen(ne, Ar, Cr, lr, Er);   // ascending, y^T Cr y = 1, so w^T Cc w = 1
+    for (int col = 0; col < ne; ++col, ++b) {
+      std::vector<q128> w(n, 0);
+      for (int i = 0; i < ne; ++i)
+        for (int s2 = 0; s2 < n; ++s2) w[s2] += basis[i][s2] * Er[i * ne + col];
+      // sign: the lowest-index entry of at least half the largest magnitude is positive
+      q128 big = 0;
+      for (int s2 = 0; s2 < n; ++s2) big = fmaxq(big, fabsq(w[s2]));
+      int at = 0;
+      while (fabsq(w[at]) < big / 2) ++at;
+      const q128 sgn = w[at] < 0 ? -1 : 1;
+      for (int s2 = 0; s2 < n; ++s2) out->band[(size_t)b * n + s2] = (double)(sgn * w[s2]);
+      // the constants span the kernel of A: lambda = 0 exactly
+      lam[(size_t)n * (K - 1) + b] = edge == 0 && col == 0 ? 0.0 : (double)lr[col];
+    }
+    if (edge == 0) out->nb0 = ne;
+  }
+  out->lam = lam;
   out->bc = 2;
-  out->kn = K;
-  out->mu = n * K + 1;
+  out->m = m;
   return 0;
 }
 

@@ -12,10 +12,6 @@ namespace hofem {
 struct Plan1DData {
   int bc = 0;                    // 0: Dirichlet, 1: periodic, 2: Neumann
   int n = 0, K = 0, m = 0;
-  // Neumann axes carry the tables of the periodic axis of 2K elements (K, m
-  // above are 2K, 2nK): kn is the axis's own element count, mu its number of
-  // unknowns nK + 1.  Otherwise kn = K and mu = m.
-  int kn = 0, mu = 0;
   std::vector<double> A, C;      // local stiffness / mass on [-1,1], (n+1)^2 row major
   std::vector<double> lam;       // scaled eigenvalues in coefficient order (m)
   std::vector<double> p;         // p_k^(l): [(k-1) n + (l-1)] * (n-1) + i, i = 0..n-2
@@ -39,6 +35,13 @@ struct Plan1DData {
   int dense = 0;
   std::vector<double> S, St;
 
+  // Neumann axes (m = nK + 1, lam in the Neumann coefficient order): the
+  // n + 1 band-edge eigenvectors as cells (node value, interior points
+  // 1..n-1), band[b n + s]; b < nb0 at theta = 0, the rest at theta = pi;
+  // w^T C_cell w = 1, so that the axis vector has ||v||_C^2 = K
+  std::vector<double> band;
+  int nb0 = 0;
+
   // periodic axes: Bloch eigenvectors w_{k,l} (cell components s = 0..n-1:
   // node j, interior points of element j+1) for k = 0..K/2, index
   // (k n + l) n + s, real and imaginary parts; w^H C^(k) w = 1
@@ -59,8 +62,13 @@ int plan1d_build_dense(Plan1DData* d);
 // Returns 0 on success, -1 for unsupported (n, K).
 int plan1d_build_periodic(int n, int K, Plan1DData* out);
 // Neumann axis of K elements (m = nK + 1 unknowns, the points g h / n,
-// g = 0..nK, boundary nodes included): its even reflection is the periodic
-// axis of 2K elements on [-X, X), whose tables it carries (K <= 512).
+// g = 0..nK, boundary nodes included).  For k = 1..K-1 its eigenvectors are
+// the cosine counterparts of Theorem 1's (node j: cos(pi k j / K); point s
+// of element e: cos(pi k (e-1) / K) p_s + cos(pi k e / K) p_{n-s}) with the
+// Dirichlet eigenvalues, p and norms of wave number k; the other n + 1 are
+// the even band-edge cells at theta = 0 and pi.  Coefficient order:
+// q = (l-1)(K-1) + (k-1) for k = 1..K-1, l = 1..n, then the band-edge
+// vectors, q = n(K-1) + b.  Returns 0 on success, -1 for unsupported (n, K).
 int plan1d_build_neumann(int n, int K, Plan1DData* out);
 
 }  // namespace hofem

@@ -176,28 +176,86 @@ def test_periodic_plan_rejects_bad_bc():
     assert lib.hofem_plan1d_create_bc(2, 6, 1, ctypes.byref(h)) == -2
 
 
-def test_neumann_plan_dims_and_tables():
-    # a Neumann plan has nK + 1 unknowns and carries the periodic tables of
-    # 2K elements (its even reflection); K above 512 is refused
-    P = H.Plan1D(3, 8, "neumann")
+def neumann_basis(P):
+    """The Neumann eigenvectors the plan's tables define (columns, in the
+    Neumann coefficient order), their eigenvalues and C-norms: for k =
+    1..K-1 the cosine counterparts of Theorem 1's vectors with the Dirichlet
+    p_k^(l), then the n + 1 band-edge cells repeated along the axis."""
+    n, K = P.n, P.K
+    m = n * K + 1
+    lam, p, inorm, band = P.table("lam"), P.table("p"), P.table("inorm"), P.table("band")
+    V = np.zeros((m, m))
+    nrm = np.zeros(m)
+    for l in range(n):
+        for k in range(1, K):
+            q = l * (K - 1) + (k - 1)
+            pk = p[((k - 1) * n + l) * (n - 1):((k - 1) * n + l + 1) * (n - 1)]
+            V[0::n, q] = np.cos(np.pi * k * np.arange(K + 1) / K)
+            for e in range(1, K + 1):
+                for s in range(1, n):
+                    V[n * (e - 1) + s, q] = (np.cos(np.pi * k * (e - 1) / K) * pk[s - 1]
+                                             + np.cos(np.pi * k * e / K) * pk[n - s - 1])
+            nrm[q] = 1.0 / inorm[(k - 1) * n + l]
+    nb0 = n // 2 + 1
+    for b in range(n + 1):
+        q = n * (K - 1) + b
+        sg = 1.0 if b < nb0 else -1.0
+        w = band[b * n:(b + 1) * n]
+        V[0::n, q] = w[0] * sg ** np.arange(K + 1)
+        for e in range(1, K + 1):
+            for s in range(1, n):
+                V[n * (e - 1) + s, q] = w[s] * sg ** (e - 1)
+        nrm[q] = K
+    return V, lam, nrm
+
+
+@pytest.mark.parametrize("n,K", [(1, 8), (2, 8), (3, 16), (4, 8), (8, 16), (9, 32)])
+def test_neumann_plan_eigenbasis_matches_oracle(n, K):
+    # the tables define a complete C-orthogonal eigenbasis of the oracle's
+    # assembled Neumann pencil: A V = C V diag(lam), V^T C V = diag(norms)
+    from oracle import periodic
+    P = H.Plan1D(n, K, "neumann")
     try:
-        assert P.m == 3 * 8 + 1
-        lam = P.table("lam")
-        assert lam.size == 3 * 16 and lam[0] == 0.0
-        Q = H.Plan1D(3, 16, "periodic")
-        try:
-            assert np.array_equal(lam, Q.table("lam"))
-            assert np.array_equal(P.table("wr"), Q.table("wr"))
+        assert P.m == n * K + 1
+        V, lam, nrm = neumann_basis(P)
+        D = H.Plan1D(n, K)
+        try:   # p and 1/||s||^2 are those of the Dirichlet plan
+            assert np.array_equal(P.table("p"), D.table("p"))
+            assert np.array_equal(P.table("inorm"), D.table("inorm"))
         finally:
-            Q.close()
+            D.close()
     finally:
         P.close()
+    A, C = [M.toarray() for M in periodic.axis_matrices(n, K, "neumann")]
+    scale = np.abs(A).max()
+    assert np.abs(A @ V - (C @ V) * lam).max() < 1e-11 * scale * np.abs(V).max()
+    G = V.T @ C @ V
+    assert np.abs(G - np.diag(nrm)).max() < 1e-12 * nrm.max()
+    assert lam[n * (K - 1)] == 0.0 and lam.min() == 0.0   # the constants
+    assert np.sort(lam)[1] > 0                             # nothing else in the kernel
+
+
+def test_neumann_plan_tables_and_limits():
+    P = H.Plan1D(3, 8, "neumann")
+    try:
+        assert P.table("band").size == 4 * 3
+        assert P.table("lam").size == 25
+        with pytest.raises(H.HofemError):
+            P.table("wr")                     # Bloch vectors: periodic plans only
+    finally:
+        P.close()
+    D = H.Plan1D(3, 8)
+    try:
+        with pytest.raises(H.HofemError):
+            D.table("band")                   # band-edge cells: Neumann plans only
+    finally:
+        D.close()
     h = ctypes.c_void_p()
     lib = ctypes.CDLL(H.LIB_PATH)
-    assert lib.hofem_plan1d_create_bc(2, 1024, 2, ctypes.byref(h)) == -2
-    assert lib.hofem_plan1d_create_bc(2, 512, 2, ctypes.byref(h)) == 0
+    assert lib.hofem_plan1d_create_bc(9, 1024, 2, ctypes.byref(h)) == 0
     lib.hofem_plan1d_destroy(h)
-
+    assert lib.hofem_plan1d_create_bc(2, 2048, 2, ctypes.byref(h)) == -2
+    assert lib.hofem_plan1d_create_bc(2, 12, 2, ctypes.byref(h)) == -2   # K a power of two
 
 
 def test_non_power_of_two_plans():

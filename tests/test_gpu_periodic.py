@@ -1,5 +1,5 @@
-"""GPU parity of periodic and Neumann axes (Bloch-wave line passes, FP64)
-against the oracle.
+"""GPU parity of periodic axes (Bloch-wave line passes, FP64) and Neumann
+axes (cosine transforms with band-edge blocks, FP64) against the oracle.
 
 Small grids: the sparse direct solve of the assembled operator
 (oracle.periodic), relative l2 <= 1e-12, in 1D, 2D and 3D with every mix of
@@ -181,13 +181,21 @@ def test_periodic_full_size_backward_error():
     assert eta < 1e-15
 
 
-# Neumann axes (even reflection onto the periodic axis of 2K elements)
+# Neumann axes (direct cosine passes: every order, K = 2 up to 1024, mixed
+# with Dirichlet and periodic axes)
 NEUMANN = [
     ((1,), (4,), (1.0,), 0.5, (NM,)),
     ((2,), (8,), (1.0,), 2.0, (NM,)),
     ((3,), (16,), (2.0,), 1.0, (NM,)),
     ((9,), (512,), (1.0,), 1.0, (NM,)),
+    ((9,), (1024,), (1.0,), 1.0, (NM,)),
+    ((8,), (1024,), (1.0,), 0.5, (NM,)),
+    ((6,), (32,), (1.0,), 1.0, (NM,)),
+    ((7,), (64,), (3.0,), 1.0, (NM,)),
     ((5,), (2,), (1.0,), 0.25, (NM,)),
+    ((1,), (2,), (1.0,), 1.0, (NM,)),
+    ((4, 9), (8, 1024), (1.0, 1.0), 0.0, (D, NM)),
+    ((9, 2), (256, 16), (1.0, 1.0), 0.0, (NM, D)),
     ((3, 2), (8, 16), (1.0, 1.0), 0.0, (NM, D)),
     ((2, 4), (16, 8), (1.0, 0.5), 0.0, (D, NM)),
     ((4, 3), (8, 8), (1.0, 1.0), 1.0, (NM, NM)),
@@ -211,32 +219,35 @@ def test_neumann_solve_matches_oracle(orders, Ks, X, alpha, bcs):
     assert rel(u, want) < 1e-12
 
 
-def test_neumann_several_rhs_and_workspace():
+def test_neumann_several_rhs_round_trip_and_refusals():
     orders, Ks, X, alpha, bcs = (3, 2), (8, 16), (1.0, 1.0), 0.0, (NM, D)
     shp = grid(orders, Ks, bcs)
     f = workloads.uniform_rhs((2,) + shp, seed=4)
     S = H.Solver(orders, Ks, X, alpha, bcs=bcs)
     try:
+        assert H.hofem_solver_workspace_bytes(S.handle, "fp64", 2) == 0   # the passes run on the grid itself
         fd = torch.from_numpy(f).to(DEV).reshape(-1)
         u = torch.empty_like(fd)
-        with pytest.raises(H.HofemError) as e:   # the reflected grid is required
-            H.hofem_solve(S.handle, "fp64", fd, u, 2, None, 0, 0.0, None, False, True)
-        assert e.value.status == -1
-        u = S.solve(fd, nrhs=2).cpu().numpy().reshape(f.shape)
-        with pytest.raises(H.HofemError) as e:
-            S.forward(fd)
-        assert e.value.status == -2
+        H.hofem_solve(S.handle, "fp64", fd, u, 2, None, 0, 0.0, None, False, True)
+        u = u.cpu().numpy().reshape(f.shape)
+        c = S.forward(fd, nrhs=2)                  # forward then inverse: C^-1 (V V^T = C^-1)
+        back = S.inverse(c, nrhs=2).cpu().numpy().reshape(f.shape)
+        for mode, x in (("fp32", fd.float()), ("fp32_ir", fd)):
+            with pytest.raises(H.HofemError) as e:
+                S.solve(x, mode=mode, nrhs=2)
+            assert e.value.status == -2
     finally:
         S.close()
+    Cs = [periodic.axis_matrices(n, K, b)[1] for n, K, b in zip(orders, Ks, bcs)]
     for r in range(2):
+        assert rel(Cs[0] @ (Cs[1] @ back[r].T).T, f[r]) < 1e-13
         assert rel(u[r], periodic.solve(f[r], orders, Ks, X, alpha, bcs)) < 1e-12
 
 
 @pytest.mark.slow
 def test_neumann_full_size_backward_error():
-    # n = 9, K = 512 on both Neumann axes (21,242,881 unknowns; the passes run
-    # on the reflected 9216 x 9216 grid)
-    orders, Ks, X, alpha, bcs = (9, 9), (512, 512), (1.0, 1.0), 1.0, (NM, NM)
+    # n = 9, K = 1024 on both Neumann axes (9217 x 9217 = 84,953,089 unknowns)
+    orders, Ks, X, alpha, bcs = (9, 9), (1024, 1024), (1.0, 1.0), 1.0, (NM, NM)
     shp = grid(orders, Ks, bcs)
     f = workloads.uniform_rhs(shp, seed=9)
     S = H.Solver(orders, Ks, X, alpha, bcs=bcs)
