@@ -2,7 +2,8 @@
 transforms on the FP64 matrix cores) against the oracle's exact dense solve.
 
 Relative l2 <= 1e-12 in 1D, 2D and 3D, odd and even K, mixed with
-power-of-two (FFT) axes, two right-hand sides; the scaled mass product
+power-of-two (FFT) axes and with Neumann and periodic axes, two right-hand
+sides; the scaled mass product
 against the oracle; the workspace required and the unsupported modes
 refused.
 """
@@ -59,6 +60,28 @@ def test_dense_solve_matches_oracle(orders, Ks, X, alpha):
     f = workloads.uniform_rhs(shp, seed=11)
     got = solve_gpu(orders, Ks, X, alpha, f)
     assert rel(got, osolve.solve(f, orders, Ks, X, alpha)) < 1e-12
+
+
+# a dense (K not a power of two) Dirichlet axis beside Neumann and periodic axes
+MIXED = [
+    ((3, 2), (12, 8), (1.0, 1.0), 1.0, ("dirichlet", "neumann")),
+    ((2, 4), (8, 6), (1.0, 0.5), 0.5, ("neumann", "dirichlet")),
+    ((2, 3), (10, 8), (1.0, 1.0), 1.0, ("dirichlet", "periodic")),
+    ((2, 2, 3), (6, 8, 4), (1.0, 1.0, 1.0), 1.0, ("dirichlet", "neumann", "periodic")),
+]
+
+
+@pytest.mark.parametrize("orders,Ks,X,alpha,bcs", MIXED)
+def test_dense_axis_with_neumann_and_periodic_axes(orders, Ks, X, alpha, bcs):
+    from oracle import periodic
+    shp = tuple(periodic.axis_dim(n, K, b) for n, K, b in zip(orders, Ks, bcs))
+    f = workloads.uniform_rhs(shp, seed=15)
+    S = H.Solver(orders, Ks, X, alpha, bcs=bcs)
+    try:
+        u = S.solve(torch.from_numpy(f).to(DEV).reshape(-1)).cpu().numpy().reshape(shp)
+    finally:
+        S.close()
+    assert rel(u, periodic.solve(f, orders, Ks, X, alpha, bcs)) < 1e-12
 
 
 def test_dense_two_rhs():
