@@ -162,6 +162,14 @@ def bench_headline(args, torch, H, np, workloads, dev):
         return {"value": M / (ms64 * 1e-3), "ms_per_step": ms64,
                 "config": {"workload": "large_2d", "profile_fp64_only": True}}
 
+    # attainable HBM bandwidth on this GPU: a plain 1 GiB device copy (read
+    # and write), beside the 8 TB/s specification peak
+    ca = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+    cb = torch.empty_like(ca)
+    ms_copy = time_calls(torch, lambda: cb.copy_(ca), 10, 2)
+    copy_gbs = 2.0 * ca.numel() * 8 / (ms_copy * 1e-3) / 1e9
+    del ca, cb
+
     log("large_2d: algorithm (b)")
     ub = torch.empty_like(f64)
     S.set_timing(True)
@@ -274,7 +282,11 @@ def bench_headline(args, torch, H, np, workloads, dev):
         "ms_per_step": ms64,
         "hbm_all_passes": {"algorithmic_bytes_per_solve": tot_bytes / max(1, args.steps),
                            "gbs": tot_bytes / (tot_ms * 1e-3) / 1e9,
-                           "frac": tot_bytes / (tot_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                           "frac": tot_bytes / (tot_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                           "frac_of_copy": tot_bytes / (tot_ms * 1e-3) / 1e9 / copy_gbs},
+        "hbm_copy": {"bytes_per_copy": 2 * (1 << 30), "ms": ms_copy, "gbs": copy_gbs,
+                     "frac_of_peak": copy_gbs / HBM_PEAK_GBS,
+                     "note": "plain 1 GiB device-to-device copy: the attainable HBM rate"},
         "algorithm_b": {"unknowns_per_s": M / (ms_b * 1e-3), "ms_per_step": ms_b,
                         "passes": [dict(p, avg_ms=p["ms"] / p["launches"]) for p in passes_b]},
         "autotune_fp64": {"ms_default": ms64, "ms_tuned": ms64_tuned, "passes": tune},

@@ -1,6 +1,7 @@
 /*
  * hofem.h -- C ABI of the MI355X (gfx950) fast direct solver for nth-order
- * Lagrange finite elements on rectangular boxes with Dirichlet data.
+ * Lagrange finite elements on rectangular boxes with Dirichlet data (and,
+ * per axis, periodic or Neumann conditions; see enum hofem_bc).
  *
  * The method is that of A. Zlotnik and I. Zlotnik, "A direct fast FFT-based
  * implementation for high order finite element method on rectangular
@@ -16,10 +17,10 @@
  *
  * Conventions shared by all calls
  * ------------------------------
- * Grid layout.  Per axis i the unknowns are the values at the m_i = n_i K_i - 1
- * interior points q h_i / n_i (q = 1..m_i, h_i = X_i / K_i): mesh nodes and
- * element-interior Lagrange nodes, in physical order; the Dirichlet zeros are
- * implicit.  An N-D grid is dense C order [nrhs][m_0]...[m_{N-1}] (the last
+ * Grid layout.  Per Dirichlet axis i the unknowns are the values at the
+ * m_i = n_i K_i - 1 interior points q h_i / n_i (q = 1..m_i, h_i = X_i / K_i):
+ * mesh nodes and element-interior Lagrange nodes, in physical order; the
+ * Dirichlet zeros are implicit (periodic and Neumann axes: enum hofem_bc).  An N-D grid is dense C order [nrhs][m_0]...[m_{N-1}] (the last
  * axis is contiguous).  The right-hand side is the algebraic f^h of
  * eq. (bvp glob 2): the load vector int f phi divided by prod_i (h_i / 2).
  *
@@ -356,8 +357,11 @@ int hofem_dirichlet_rhs(hofem_solver solver, const double* b_ext_dev, const doub
  *                      (u^{n+1} - 2u^n + u^{n-1})/dt^2 - Lap u^{n+1} = f,
  *                      alpha = 1/dt^2:
  *                      L u^{n+1} = f^h + alpha ((x)_i C_i)(2u^n - u^{n-1})
- * A step is one mass product by the operator kernels and one FP64 solve by
- * algorithm (a) (plus one vector kernel for the wave scheme). */
+ * A step is one mass product (by the operator kernels, or one kernel per
+ * axis when an axis is periodic or Neumann) and one FP64 solve by algorithm
+ * (a) (plus one vector kernel for the wave scheme).  Any boundary conditions
+ * of enum hofem_bc; axes whose K is not a power of two are refused
+ * (HOFEM_EUNSUPPORTED). */
 enum hofem_scheme { HOFEM_SCHEME_HEAT = 0, HOFEM_SCHEME_WAVE = 1 };
 
 typedef struct hofem_stepper_s* hofem_stepper;
@@ -368,7 +372,8 @@ int hofem_stepper_create(hofem_solver solver, int scheme, hofem_stepper* out);
 void hofem_stepper_destroy(hofem_stepper stepper);
 
 /* Workspace of hofem_stepper_run for nrhs right-hand sides: one FP64 grid
- * (two for the wave scheme) and the operator's workspace. */
+ * (two for the wave scheme) and the operator's workspace (with a periodic or
+ * Neumann axis in 2D and 3D: one more grid instead). */
 int hofem_stepper_workspace_bytes(hofem_stepper stepper, int nrhs, size_t* bytes);
 
 /* Advances u_dev (in: u^n, out: u^{n+nsteps}) by nsteps steps.  f_dev: the

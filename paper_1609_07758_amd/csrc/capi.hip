@@ -727,6 +727,23 @@ namespace hofem {
 
 size_t solver_unknowns(const hofem_solver_s* S) { return S->per_rhs; }
 bool solver_all_dirichlet(const hofem_solver_s* S) { return all_dirichlet(S) && !has_dense(S); }
+int solver_dims(const hofem_solver_s* S) { return S->N; }
+bool solver_has_dense(const hofem_solver_s* S) { return has_dense(S); }
+int solver_axis_mass(const hofem_solver_s* S, int axis, AxisMass* out) {
+  if (axis < 0 || axis >= S->N) return HOFEM_EINVAL;
+  const DevAxis& X = S->ax[axis];
+  const size_t nb = (size_t)X.n + 1;
+  if (nb * nb > 100 || X.hC.size() != nb * nb) return HOFEM_EINVAL;
+  out->bc = X.bc;
+  out->n = X.n;
+  out->K = X.K;
+  out->m = X.m;
+  long long inner = 1;
+  for (int b = axis + 1; b < S->N; ++b) inner *= S->ax[b].m;
+  out->inner = inner;
+  for (size_t i = 0; i < nb * nb; ++i) out->C[i] = X.hC[i];
+  return HOFEM_OK;
+}
 double solver_alpha(const hofem_solver_s* S) { return S->alpha; }
 int solver_device(const hofem_solver_s* S) { return S->device; }
 size_t solver_op_elem_bytes(const hofem_solver_s* S) { return op_elem_bytes(S); }

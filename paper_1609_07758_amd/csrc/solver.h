@@ -14,13 +14,26 @@ namespace hofem {
 size_t solver_unknowns(const hofem_solver_s* S);
 double solver_alpha(const hofem_solver_s* S);
 int solver_device(const hofem_solver_s* S);
-// Every axis has Dirichlet data and K a power of two (time stepping needs the
-// Dirichlet operator and the FFT passes).
+// Every axis has Dirichlet data and K a power of two (the operator kernels
+// of the FP32 refinement, CG and the Dirichlet mass update need them).
 bool solver_all_dirichlet(const hofem_solver_s* S);
 // Bytes of the operator's element buffer (0 where it needs none; a multiple of 256).
 size_t solver_op_elem_bytes(const hofem_solver_s* S);
 // FP64 solve by algorithm (a) of nrhs right-hand sides, in -> out (in == out allowed).
 int solver_solve_fp64(hofem_solver_s* S, const double* in, double* out, int nrhs, hipStream_t st);
+// Axes, and whether one has K not a power of two (dense transforms).
+int solver_dims(const hofem_solver_s* S);
+bool solver_has_dense(const hofem_solver_s* S);
+// One axis of the grid for the mass product of any boundary condition:
+// condition (0 Dirichlet, 1 periodic, 2 Neumann), order, elements, unknowns
+// m, stride of the axis in the C-order grid of one right-hand side, and the
+// local mass matrix on [-1, 1] (row major, (n+1)^2 <= 100 values).
+struct AxisMass {
+  int bc, n, K, m;
+  long long inner;
+  double C[100];
+};
+int solver_axis_mass(const hofem_solver_s* S, int axis, AxisMass* out);
 // out = f + coef ((x)_i C_i) w (f == NULL: out = coef (x)C w), FP64, by the
 // operator kernels with the stiffness scales set to zero; elem: element
 // buffer of solver_op_elem_bytes.  w != out.

@@ -8,10 +8,11 @@
 // Wave equation u_tt - Lap u = f, the implicit three-level scheme
 // (u^{n+1} - 2u^n + u^{n-1}) / dt^2 - Lap u^{n+1} = f with alpha = 1/dt^2:
 //   L u^{n+1} = f^h + alpha ((x)_i C_i) (2u^n - u^{n-1}).
-// A step is one mass update by the operator kernels (stiffness scales set to
-// zero), one FP64 solve by algorithm (a) (2N - 1 passes) and, for the wave
-// scheme, one vector kernel.  A step is captured once into a HIP graph and
-// replayed.
+// A step is one mass update (with Dirichlet axes only: by the operator
+// kernels with the stiffness scales set to zero; with periodic or Neumann
+// axes: one mass kernel per axis), one FP64 solve by algorithm (a) (2N - 1
+// passes) and, for the wave scheme, one vector kernel.  A step is captured
+// once into a HIP graph and replayed.
 
 #include <hip/hip_runtime.h>
 
@@ -52,9 +53,77 @@ __global__ void wave_shift(const double* __restrict__ u, double* __restrict__ up
   }
 }
 
+// out = coef (C_axis (x) I) in + add (add may be NULL) along one axis of a
+// C-order grid of `total` points, for any boundary condition of the axis:
+// each point sums the local mass rows of the one or two elements that hold
+// it.  Global point g = 0..nK of the axis (element e = 1..K holds the points
+// n(e-1)..ne, local index g - n(e-1)); the unknowns are g = 1..nK-1
+// (Dirichlet; the boundary values are zero), g = 0..nK-1 with nK = 0
+// (periodic) or g = 0..nK (Neumann).
+__global__ __launch_bounds__(256) void mass_axis_kernel(AxisMass a, const double* __restrict__ in,
+                                                        double* __restrict__ out,
+                                                        const double* __restrict__ add, double coef,
+                                                        long long total) {
+  const int n = a.n, K = a.K, nb = n + 1, nK = n * K;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int q = (int)((i / a.inner) % a.m);
+    const long long base = i - (long long)q * a.inner;   // point 0 of this line
+    const int g = a.bc == 0 ? q + 1 : q;
+    const int j = g / n, s = g - j * n;
+    auto val = [&](int h) -> double {
+      int qq = h;
+      if (a.bc == 0) {
+        if (h <= 0 || h >= nK) return 0.0;
+        qq = h - 1;
+      } else if (a.bc == 1 && h == nK) {
+        qq = 0;
+      }
+      return in[base + (long long)qq * a.inner];
+    };
+    double acc = 0.0;
+    auto elem = [&](int e, int loc) {
+      for (int r = 0; r < nb; ++r) acc += a.C[loc * nb + r] * val(n * (e - 1) + r);
+    };
+    if (s == 0) {   // node j: the end of element j and the start of element j + 1
+      if (j >= 1) elem(j, n);
+      else if (a.bc == 1) elem(K, n);   // periodic: node 0 also ends element K
+      if (j <= K - 1) elem(j + 1, 0);
+    } else {
+      elem(j + 1, s);
+    }
+    out[i] = coef * acc + (add ? add[i] : 0.0);
+  }
+}
+
+// out = f + coef ((x)_i C_i) w, one axis after another (w != out; tmp: one
+// grid, used when there are two or more axes).
+int mass_chain(hofem_stepper_s* T, const double* f, const double* w, double* out, double coef,
+               double* tmp, int nrhs, hipStream_t st) {
+  const int N = solver_dims(T->S);
+  const long long total = (long long)solver_unknowns(T->S) * nrhs;
+  const unsigned blocks = (unsigned)std::min<long long>((total + 255) / 256, 8192);
+  const double* src = w;
+  for (int ax = 0; ax < N; ++ax) {
+    AxisMass am;
+    const int rc = solver_axis_mass(T->S, ax, &am);
+    if (rc != HOFEM_OK) return rc;
+    double* dst = ((N - 1 - ax) % 2 == 0) ? out : tmp;
+    const bool last = ax == N - 1;
+    hipLaunchKernelGGL(mass_axis_kernel, dim3(blocks), dim3(256), 0, st, am, src, dst,
+                       last ? f : nullptr, last ? coef : 1.0, total);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return record_hip_error(e);
+    src = dst;
+  }
+  return HOFEM_OK;
+}
+
 size_t ws_bytes_of(const hofem_stepper_s* T, int nrhs) {
   const size_t grid = al256(solver_unknowns(T->S) * (size_t)nrhs * sizeof(double));
-  return grid * (T->scheme == HOFEM_SCHEME_WAVE ? 2 : 1) + solver_op_elem_bytes(T->S);
+  const size_t levels = grid * (T->scheme == HOFEM_SCHEME_WAVE ? 2 : 1);
+  if (solver_all_dirichlet(T->S)) return levels + solver_op_elem_bytes(T->S);
+  return levels + (solver_dims(T->S) >= 2 ? grid : 0);   // the mass chain's second grid
 }
 
 int one_step(hofem_stepper_s* T, const double* f, double* u, double* up, int nrhs, void* ws,
@@ -74,8 +143,11 @@ int one_step(hofem_stepper_s* T, const double* f, double* u, double* up, int nrh
     if (e != hipSuccess) return record_hip_error(e);
     w = wb;
   }
-  const int rc = solver_mass_update(T->S, f, w, rhs, solver_alpha(T->S),
-                                    reinterpret_cast<double*>(p), nrhs, st);
+  const int rc = solver_all_dirichlet(T->S)
+                     ? solver_mass_update(T->S, f, w, rhs, solver_alpha(T->S),
+                                          reinterpret_cast<double*>(p), nrhs, st)
+                     : mass_chain(T, f, w, rhs, solver_alpha(T->S), reinterpret_cast<double*>(p),
+                                  nrhs, st);
   if (rc != HOFEM_OK) return rc;
   return solver_solve_fp64(T->S, rhs, u, nrhs, st);
 }
@@ -93,7 +165,7 @@ int hofem_stepper_create(hofem_solver solver, int scheme, hofem_stepper* out) {
   if (!solver || !out) return HOFEM_EINVAL;
   if (scheme != HOFEM_SCHEME_HEAT && scheme != HOFEM_SCHEME_WAVE) return HOFEM_EINVAL;
   if (!(solver_alpha(solver) > 0)) return HOFEM_EINVAL;   // alpha = 1/dt or 1/dt^2
-  if (!solver_all_dirichlet(solver)) return HOFEM_EUNSUPPORTED;
+  if (solver_has_dense(solver)) return HOFEM_EUNSUPPORTED;   // K not a power of two
   hofem_stepper T = new (std::nothrow) hofem_stepper_s;
   if (!T) return HOFEM_ENOMEM;
   T->S = solver;

@@ -1,7 +1,8 @@
 """GPU tests of implicit time stepping (hofem_stepper_*): backward Euler for
 the heat equation and the implicit three-level scheme for the wave equation,
-against the oracle's step-by-step solves (relative l2 <= 1e-12), with the
-HIP-graph replays equal to the eager steps on every replay."""
+against the oracle's step-by-step solves (relative l2 <= 1e-12), also with
+periodic and Neumann axes, with the HIP-graph replays equal to the eager
+steps on every replay."""
 import numpy as np
 import pytest
 
@@ -53,6 +54,61 @@ def test_steps_match_oracle(scheme, orders, Ks, X, alpha, nsteps, load):
     T.close()
 
 
+# periodic and Neumann axes: the step's mass product runs axis by axis; the
+# expected steps are the oracle's solves of the same step equations with its
+# assembled mass matrices
+BC_CASES = [
+    # (scheme, orders, Ks, X, alpha, nsteps, with load, bcs)
+    ("heat", (3, 2), (8, 16), (1.0, 1.0), 50.0, 4, True, ("neumann", "dirichlet")),
+    ("heat", (2, 3), (16, 8), (1.0, 1.0), 100.0, 3, False, ("periodic", "periodic")),
+    ("wave", (2, 2), (8, 8), (1.0, 1.0), 400.0, 4, True, ("neumann", "neumann")),
+    ("wave", (3,), (32,), (1.0,), 900.0, 5, False, ("periodic",)),
+    ("heat", (4,), (16,), (2.0,), 20.0, 3, True, ("neumann",)),
+    ("heat", (2, 2, 2), (4, 8, 4), (1.0, 1.0, 1.0), 30.0, 3, True, ("neumann", "periodic", "dirichlet")),
+]
+
+
+def oracle_bc_steps(u0, up0, f, orders, Ks, X, alpha, bcs, scheme, nsteps):
+    from oracle import periodic
+    Cs = [periodic.axis_matrices(n, K, b)[1] for n, K, b in zip(orders, Ks, bcs)]
+
+    def mass(w):
+        for a, C in enumerate(Cs):
+            v = np.moveaxis(w, a, 0)
+            w = np.moveaxis((C @ v.reshape(v.shape[0], -1)).reshape(v.shape), 0, a)
+        return w
+
+    u, up = u0.copy(), None if up0 is None else up0.copy()
+    for _ in range(nsteps):
+        w = u if scheme == "heat" else 2.0 * u - up
+        rhs = alpha * mass(w) + (f if f is not None else 0.0)
+        un = periodic.solve(rhs, orders, Ks, X, alpha, bcs)
+        if scheme == "wave":
+            up = u
+        u = un
+    return u, up
+
+
+@pytest.mark.parametrize("scheme,orders,Ks,X,alpha,nsteps,load,bcs", BC_CASES)
+def test_steps_with_periodic_and_neumann_axes(scheme, orders, Ks, X, alpha, nsteps, load, bcs):
+    S = H.Solver(orders, Ks, X, alpha, bcs=bcs)
+    u0 = workloads.uniform_rhs(S.shape, seed=83)
+    up0 = workloads.uniform_rhs(S.shape, seed=84) if scheme == "wave" else None
+    f = workloads.uniform_rhs(S.shape, seed=85) if load else None
+    T = H.Stepper(S, scheme)
+    u = torch.from_numpy(u0).to(DEV)
+    up = torch.from_numpy(up0).to(DEV) if up0 is not None else None
+    fd = torch.from_numpy(f).to(DEV) if f is not None else None
+    T.run(u, nsteps, f=fd, uprev=up, use_graph=True)
+    torch.cuda.synchronize()
+    want, want_prev = oracle_bc_steps(u0, up0, f, orders, Ks, X, alpha, bcs, scheme, nsteps)
+    assert rel(u.cpu().numpy(), want) < 1e-12
+    if scheme == "wave":
+        assert rel(up.cpu().numpy(), want_prev) < 1e-12
+    T.close()
+    S.close()
+
+
 @pytest.mark.parametrize("scheme", ["heat", "wave"])
 def test_graph_replays_equal_eager(scheme):
     orders, Ks, X = (4, 4), (8, 16), (1.0, 1.0)
@@ -98,3 +154,7 @@ def test_stepper_errors():
     with pytest.raises(RuntimeError):
         T.run(u, 2)                              # wave scheme without the previous level
     T.close()
+    Sd = H.Solver((2,), (6,), (1.0,), 10.0)
+    with pytest.raises(RuntimeError):
+        H.Stepper(Sd, "heat")                   # K not a power of two: no FFT passes
+    Sd.close()
