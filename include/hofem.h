@@ -142,9 +142,9 @@ enum hofem_bc { HOFEM_BC_DIRICHLET = 0, HOFEM_BC_PERIODIC = 1, HOFEM_BC_NEUMANN 
  * Coefficient order: q = (l-1)(K-1) + (k-1) for k = 1..K-1, then n(K-1) + b
  * for the band-edge vectors (b < n/2 + 1 at theta = 0, the rest at pi).
  * Neumann axes run in HOFEM_MODE_FP64 only (hofem_solve, hofem_forward,
- * hofem_inverse) and need K a power of two; the other restrictions are
- * those of periodic axes (a solver without a Dirichlet axis needs
- * alpha > 0). */
+ * hofem_inverse; K not a power of two: the dense transforms below, m <= 4095);
+ * the other restrictions are those of periodic axes (a solver without a
+ * Dirichlet axis needs alpha > 0). */
 
 /* hofem_plan1d_create with a boundary condition (enum hofem_bc; else
  * HOFEM_EINVAL).  hofem_plan1d_create(n, K, out) is
@@ -179,14 +179,14 @@ int hofem_plan1d_dim(hofem_plan1d plan, int* m);
  * (HOFEM_EINVAL otherwise); table 0 holds the m eigenvalues in the axis's
  * own coefficient order (periodic and Neumann orders above).
  *
- * K need not be a power of two for a Dirichlet axis: with m = nK - 1 <= 4095
- * the plan then also holds S and its scaled form, and the solver applies
+ * K need not be a power of two for a Dirichlet or Neumann axis: with
+ * m <= 4095 the plan then also holds S (columns in the axis's coefficient
+ * order) and its scaled form, and the solver applies
  * them along that axis as dense products on the FP64 matrix cores (there is
  * no power-of-two FFT); an FP64 solve of such a solver takes a workspace of
  * one grid (hofem_solver_workspace_bytes), and only the FP64 solve, the
  * operators, the mass product and the Dirichlet lift accept it
- * (HOFEM_EUNSUPPORTED elsewhere).  Periodic and Neumann axes need K a
- * power of two.
+ * (HOFEM_EUNSUPPORTED elsewhere).  Periodic axes need K a power of two.
  * The coefficient index of a line is q = l-1 for k = 0 (l = 1..n-1) and
  * q = (n-1) + (l-1)(K-1) + (k-1) for k = 1..K-1 (l = 1..n): for each l the
  * wave numbers are consecutive.  `len` must equal the count; otherwise

@@ -514,19 +514,50 @@ int plan1d_build_periodic(int n, int K, Plan1DData* out) {
 
 int plan1d_build_dense(Plan1DData* d) {
   const int n = d->n, K = d->K, m = d->m;
-  if (d->bc != 0 || m < 1 || m > kDenseMax) return -1;
+  if (d->bc == 1 || m < 1 || m > kDenseMax) return -1;
   d->dense = 1;
   d->S.assign((size_t)m * m, 0.0);
   d->St.assign((size_t)m * m, 0.0);
-  // sin(pi x / K) for an integer x, reduced modulo 2K first
-  auto sine = [&](long long x) -> long double {
-    const long long r = ((x % (2LL * K)) + 2LL * K) % (2LL * K);
-    return sinl(3.14159265358979323846264338327950288L * (long double)r / (long double)K);
-  };
+  // sin and cos of pi x / K for an integer x, reduced modulo 2K first
+  constexpr long double kPi = 3.14159265358979323846264338327950288L;
+  auto red = [&](long long x) { return ((x % (2LL * K)) + 2LL * K) % (2LL * K); };
+  auto sine = [&](long long x) -> long double { return sinl(kPi * (long double)red(x) / (long double)K); };
+  auto cosine = [&](long long x) -> long double { return cosl(kPi * (long double)red(x) / (long double)K); };
   auto put = [&](int q, int c, long double v, double norm) {
     d->S[(size_t)q * m + c] = (double)v;
     d->St[(size_t)q * m + c] = (double)(v * norm);
   };
+  if (d->bc == 2) {
+    // Neumann: k = 1..K-1, l = 1..n (column (l-1)(K-1) + k-1): cos(pi k j / K)
+    // at node j = 0..K (point n j), cos(pi k (e-1)/K) p_s + cos(pi k e/K) p_{n-s}
+    // in element e; then the band-edge cells repeated with the factor 1 or
+    // (-1)^j, norm K
+    for (int k = 1; k < K; ++k)
+      for (int l = 1; l <= n; ++l) {
+        const int c = (l - 1) * (K - 1) + (k - 1);
+        const double norm = d->inorm[(size_t)(k - 1) * n + (l - 1)];
+        const double* p = d->p.data() + ((size_t)(k - 1) * n + (l - 1)) * (n - 1);
+        for (int j = 0; j <= K; ++j) put(n * j, c, cosine((long long)k * j), norm);
+        for (int e = 1; e <= K; ++e)
+          for (int s = 1; s < n; ++s) {
+            const long double v = cosine((long long)k * (e - 1)) * (long double)p[s - 1] +
+                                  cosine((long long)k * e) * (long double)p[n - s - 1];
+            put(n * (e - 1) + s, c, v, norm);
+          }
+      }
+    const int nb0 = n / 2 + 1;
+    for (int b = 0; b <= n; ++b) {
+      const int c = n * (K - 1) + b;
+      const long double sg = b < nb0 ? 1.0L : -1.0L;
+      const double* w = d->band.data() + (size_t)b * n;
+      long double f = 1.0L;   // sg^j
+      for (int j = 0; j <= K; ++j, f *= sg) put(n * j, c, f * (long double)w[0], 1.0 / K);
+      f = 1.0L;
+      for (int e = 1; e <= K; ++e, f *= sg)
+        for (int s = 1; s < n; ++s) put(n * (e - 1) + s, c, f * (long double)w[s], 1.0 / K);
+    }
+    return 0;
+  }
   // k = 0, l = 1..n-1: zero at the nodes, ((-P)^(e-1) e^(l))_s in element e
   for (int l = 1; l < n; ++l) {
     const int c = l - 1;
@@ -556,7 +587,7 @@ int plan1d_build_dense(Plan1DData* d) {
 }
 
 int plan1d_build_neumann(int n, int K, Plan1DData* out) {
-  if (K < 2 || K > 1024 || (K & (K - 1)) != 0) return -1;
+  if (K < 2 || K > 1024) return -1;
   // the Dirichlet tables of (n, K): p_k^(l), 1 / ||s_k^(l)||^2, the
   // eigenvalues of k = 1..K-1, twiddles, sines, local and Gauss tables
   if (plan1d_build(n, K, out) != 0) return -1;

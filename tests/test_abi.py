@@ -209,7 +209,7 @@ def neumann_basis(P):
     return V, lam, nrm
 
 
-@pytest.mark.parametrize("n,K", [(1, 8), (2, 8), (3, 16), (4, 8), (8, 16), (9, 32)])
+@pytest.mark.parametrize("n,K", [(1, 8), (2, 8), (3, 16), (4, 8), (8, 16), (9, 32), (3, 12), (2, 5)])
 def test_neumann_plan_eigenbasis_matches_oracle(n, K):
     # the tables define a complete C-orthogonal eigenbasis of the oracle's
     # assembled Neumann pencil: A V = C V diag(lam), V^T C V = diag(norms)
@@ -235,6 +235,21 @@ def test_neumann_plan_eigenbasis_matches_oracle(n, K):
     assert np.sort(lam)[1] > 0                             # nothing else in the kernel
 
 
+@pytest.mark.parametrize("n,K", [(3, 12), (2, 5), (9, 6)])
+def test_neumann_dense_tables(n, K):
+    # K not a power of two: the plan also holds the eigenvectors as the dense
+    # S (columns in the Neumann coefficient order) and S diag(1/||v||^2)
+    P = H.Plan1D(n, K, "neumann")
+    try:
+        m = P.m
+        V, lam, nrm = neumann_basis(P)
+        S, St = P.table("S").reshape(m, m), P.table("St").reshape(m, m)
+    finally:
+        P.close()
+    assert np.abs(S - V).max() < 1e-14
+    assert np.abs(St - V / nrm).max() < 1e-14
+
+
 def test_neumann_plan_tables_and_limits():
     P = H.Plan1D(3, 8, "neumann")
     try:
@@ -255,12 +270,14 @@ def test_neumann_plan_tables_and_limits():
     assert lib.hofem_plan1d_create_bc(9, 1024, 2, ctypes.byref(h)) == 0
     lib.hofem_plan1d_destroy(h)
     assert lib.hofem_plan1d_create_bc(2, 2048, 2, ctypes.byref(h)) == -2
-    assert lib.hofem_plan1d_create_bc(2, 12, 2, ctypes.byref(h)) == -2   # K a power of two
+    assert lib.hofem_plan1d_create_bc(9, 455, 2, ctypes.byref(h)) == -2   # dense: m = 4096 > 4095
+    assert lib.hofem_plan1d_create_bc(9, 454, 2, ctypes.byref(h)) == 0    # m = 4087
+    lib.hofem_plan1d_destroy(h)
 
 
 def test_non_power_of_two_plans():
-    # Dirichlet axes whose K is not a power of two take dense transforms
-    # (m = nK - 1 <= 4095); other conditions need the FFT (powers of two)
+    # Dirichlet and Neumann axes whose K is not a power of two take dense
+    # transforms (m <= 4095); periodic axes need the FFT (powers of two)
     P = H.Plan1D(3, 12)
     try:
         assert P.m == 35
@@ -272,7 +289,8 @@ def test_non_power_of_two_plans():
     lib.hofem_plan1d_destroy(h)
     assert lib.hofem_plan1d_create_bc(9, 456, 0, ctypes.byref(h)) == -2   # m = 4103
     assert lib.hofem_plan1d_create_bc(2, 12, 1, ctypes.byref(h)) == -2
-    assert lib.hofem_plan1d_create_bc(2, 12, 2, ctypes.byref(h)) == -2
+    assert lib.hofem_plan1d_create_bc(2, 12, 2, ctypes.byref(h)) == 0
+    lib.hofem_plan1d_destroy(h)
 
 
 @pytest.mark.parametrize("n,K", [(3, 12), (2, 3), (5, 6)])

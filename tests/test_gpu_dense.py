@@ -68,6 +68,10 @@ MIXED = [
     ((2, 4), (8, 6), (1.0, 0.5), 0.5, ("neumann", "dirichlet")),
     ((2, 3), (10, 8), (1.0, 1.0), 1.0, ("dirichlet", "periodic")),
     ((2, 2, 3), (6, 8, 4), (1.0, 1.0, 1.0), 1.0, ("dirichlet", "neumann", "periodic")),
+    ((3,), (12,), (1.0,), 1.0, ("neumann",)),                       # dense Neumann axes
+    ((2, 3), (6, 10), (1.0, 1.0), 1.0, ("neumann", "neumann")),
+    ((2, 4), (6, 16), (1.0, 1.0), 0.0, ("neumann", "dirichlet")),
+    ((5, 2), (16, 12), (2.0, 1.0), 0.5, ("periodic", "neumann")),
 ]
 
 
