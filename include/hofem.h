@@ -120,7 +120,8 @@ int hofem_plan1d_create(int n, int K, hofem_plan1d* out);
  * Coefficients of a periodic axis are real, l-major: q = l K + t with t = 0
  * for k = 0, t = 2k-1 and 2k for the real and imaginary parts of k = 1..K/2-1,
  * t = K-1 for k = K/2; lambda_{k,l} is listed at every t of k.  Periodic axes
- * run in HOFEM_MODE_FP64 only (hofem_solve, hofem_forward, hofem_inverse);
+ * run in HOFEM_MODE_FP64 only (hofem_solve, hofem_forward, hofem_inverse;
+ * K not a power of two: the dense transforms below);
  * every other entry point returns HOFEM_EUNSUPPORTED for a solver with a
  * periodic axis.  An all-periodic solver needs alpha > 0 (the constants have
  * lambda = 0): otherwise hofem_solver_create returns HOFEM_ENOTPOSDEF. */
@@ -186,7 +187,9 @@ int hofem_plan1d_dim(hofem_plan1d plan, int* m);
  * no power-of-two FFT); an FP64 solve of such a solver takes a workspace of
  * one grid (hofem_solver_workspace_bytes), and only the FP64 solve, the
  * operators, the mass product and the Dirichlet lift accept it
- * (HOFEM_EUNSUPPORTED elsewhere).  Periodic axes need K a power of two.
+ * (HOFEM_EUNSUPPORTED elsewhere).  The same holds for periodic axes
+ * (m = nK <= 4095; the columns are the real and imaginary parts of the Bloch
+ * waves, scaled as the periodic coefficients are) and Neumann axes.
  * The coefficient index of a line is q = l-1 for k = 0 (l = 1..n-1) and
  * q = (n-1) + (l-1)(K-1) + (k-1) for k = 1..K-1 (l = 1..n): for each l the
  * wave numbers are consecutive.  `len` must equal the count; otherwise

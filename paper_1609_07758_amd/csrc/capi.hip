@@ -677,6 +677,10 @@ std::vector<unsigned char> pack_plan(const Plan1DData& d, PlanOff* off) {
     off->D = pk.add_f64(d.D);
     off->Dh = pk.add_f64(d.Dh);
     off->gw = pk.add_f64(d.gw);
+    if (d.dense) {
+      off->S = pk.add_f64(d.S);
+      off->St = pk.add_f64(d.St);
+    }
     pk.bytes.resize((pk.bytes.size() + 255) & ~size_t(255), 0);
     return pk.bytes;
   }
@@ -797,9 +801,9 @@ int hofem_plan1d_create_bc(int n, int K, int bc, hofem_plan1d* out) {
   if (bc != HOFEM_BC_DIRICHLET && bc != HOFEM_BC_PERIODIC && bc != HOFEM_BC_NEUMANN) return HOFEM_EINVAL;
   const bool pow2 = (K & (K - 1)) == 0;
   if (n < 1 || n > 9 || K < 2 || K > 1024) return HOFEM_EUNSUPPORTED;
-  // K not a power of two: Dirichlet and Neumann axes, by dense transforms (m <= 4095)
-  if (!pow2 && (bc == HOFEM_BC_PERIODIC || n * K + (bc == HOFEM_BC_NEUMANN ? 1 : -1) > kDenseMax))
-    return HOFEM_EUNSUPPORTED;
+  // K not a power of two: dense transforms (m <= 4095)
+  const int mdim = bc == HOFEM_BC_DIRICHLET ? n * K - 1 : bc == HOFEM_BC_PERIODIC ? n * K : n * K + 1;
+  if (!pow2 && mdim > kDenseMax) return HOFEM_EUNSUPPORTED;
   hofem_plan1d p = new (std::nothrow) hofem_plan1d_s;
   if (!p) return HOFEM_ENOMEM;
   int rc = bc == HOFEM_BC_PERIODIC  ? plan1d_build_periodic(n, K, &p->d)

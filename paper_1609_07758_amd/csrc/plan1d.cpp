@@ -409,7 +409,7 @@ int plan1d_build(int n, int K, Plan1DData* out) {
 // Jacobi in binary128; w is normalised to w^H (T^H C T) w = 1 and rotated
 // so that its largest entry is real and positive (real at k = 0, K/2).
 int plan1d_build_periodic(int n, int K, Plan1DData* out) {
-  if (K < 2 || (K & (K - 1)) != 0) return -1;
+  if (K < 2) return -1;
   if (plan1d_build(n, K, out) != 0) return -1;   // local matrices, Gauss tables, twiddles
   const int nb = n + 1, d2 = 2 * n, m = n * K, nk = K / 2 + 1;
   std::vector<q128> A, C, gx, gw, Bq, Dq;
@@ -514,7 +514,7 @@ int plan1d_build_periodic(int n, int K, Plan1DData* out) {
 
 int plan1d_build_dense(Plan1DData* d) {
   const int n = d->n, K = d->K, m = d->m;
-  if (d->bc == 1 || m < 1 || m > kDenseMax) return -1;
+  if (m < 1 || m > kDenseMax) return -1;
   d->dense = 1;
   d->S.assign((size_t)m * m, 0.0);
   d->St.assign((size_t)m * m, 0.0);
@@ -527,6 +527,42 @@ int plan1d_build_dense(Plan1DData* d) {
     d->S[(size_t)q * m + c] = (double)v;
     d->St[(size_t)q * m + c] = (double)(v * norm);
   };
+  if (d->bc == 1) {
+    // periodic, column l K + t: the Bloch wave v = w_{k,l} e^{i 2 pi k j / K}
+    // (cell j, component s at q = n j + s) as real vectors.  The passes'
+    // coefficients are c = (1/K) v^H y stored as (Re c, Im c) at t = 2k-1, 2k
+    // (0 < k < K/2) and the inverse is y = sum over all k of c v, the
+    // conjugate wave numbers included; so S holds 2 Re v and -2 Im v there, St
+    // Re v / K and -Im v / K, and v itself (real) and v / K at t = 0 (k = 0)
+    // and t = K-1 (k = K/2, even K).
+    const int ne = n * n;
+    for (int k = 0; 2 * k <= K; ++k) {
+      const bool self = k == 0 || 2 * k == K;
+      const int t = k == 0 ? 0 : (2 * k == K ? K - 1 : 2 * k - 1);
+      for (int l = 0; l < n; ++l) {
+        const int c = l * K + t;
+        for (int j = 0; j < K; ++j) {
+          const long double ph = 2.0L * kPi * (long double)(((long long)k * j) % K) / (long double)K;
+          const long double cr = cosl(ph), ci = sinl(ph);
+          for (int s2 = 0; s2 < n; ++s2) {
+            const long double wr = d->wr[(size_t)k * ne + (size_t)l * n + s2];
+            const long double wi = d->wi[(size_t)k * ne + (size_t)l * n + s2];
+            const long double vr = wr * cr - wi * ci, vi = wr * ci + wi * cr;
+            const int q = n * j + s2;
+            if (self) {
+              put(q, c, vr, 1.0 / K);
+            } else {
+              d->S[(size_t)q * m + c] = (double)(2.0L * vr);
+              d->St[(size_t)q * m + c] = (double)(vr / K);
+              d->S[(size_t)q * m + c + 1] = (double)(-2.0L * vi);
+              d->St[(size_t)q * m + c + 1] = (double)(-vi / K);
+            }
+          }
+        }
+      }
+    }
+    return 0;
+  }
   if (d->bc == 2) {
     // Neumann: k = 1..K-1, l = 1..n (column (l-1)(K-1) + k-1): cos(pi k j / K)
     // at node j = 0..K (point n j), cos(pi k (e-1)/K) p_s + cos(pi k e/K) p_{n-s}

@@ -53,8 +53,9 @@ constexpr int kDenseMax = 4095;
 
 // Returns 0 on success, -1 for unsupported (n, K).
 int plan1d_build(int n, int K, Plan1DData* out);
-// Fills S and St of a Dirichlet or Neumann plan (m <= kDenseMax; columns in
-// the plan's coefficient order); 0 on success.
+// Fills S and St of a plan (m <= kDenseMax; columns in the plan's
+// coefficient order, so that the coefficients are St^T y and the inverse
+// S c); 0 on success.
 int plan1d_build_dense(Plan1DData* d);
 // Periodic axis (m = nK unknowns: node j at q = n j, interior point s of
 // element j+1 at q = n j + s, j = 0..K-1): eigenvalues in the coefficient

@@ -173,7 +173,7 @@ def test_periodic_plan_rejects_bad_bc():
     h = ctypes.c_void_p()
     lib = ctypes.CDLL(H.LIB_PATH)
     assert lib.hofem_plan1d_create_bc(2, 8, 3, ctypes.byref(h)) == -1
-    assert lib.hofem_plan1d_create_bc(2, 6, 1, ctypes.byref(h)) == -2
+    assert lib.hofem_plan1d_create_bc(2, 2048, 1, ctypes.byref(h)) == -2
 
 
 def neumann_basis(P):
@@ -250,6 +250,23 @@ def test_neumann_dense_tables(n, K):
     assert np.abs(St - V / nrm).max() < 1e-14
 
 
+@pytest.mark.parametrize("n,K", [(2, 6), (3, 5), (1, 7), (4, 12)])
+def test_periodic_dense_tables_match_oracle(n, K):
+    # K not a power of two, periodic: S holds the real eigenvectors (real and
+    # imaginary parts of the Bloch waves), A S = C S diag(lam); St^T C S = I
+    from oracle import periodic
+    P = H.Plan1D(n, K, "periodic")
+    try:
+        m = P.m
+        lam = P.table("lam")
+        S, St = P.table("S").reshape(m, m), P.table("St").reshape(m, m)
+    finally:
+        P.close()
+    A, C = [M.toarray() for M in periodic.axis_matrices(n, K, "periodic")]
+    assert np.abs(A @ S - (C @ S) * lam).max() < 1e-11 * np.abs(A).max() * np.abs(S).max()
+    assert np.abs(St.T @ C @ S - np.eye(m)).max() < 1e-12
+
+
 def test_neumann_plan_tables_and_limits():
     P = H.Plan1D(3, 8, "neumann")
     try:
@@ -276,8 +293,7 @@ def test_neumann_plan_tables_and_limits():
 
 
 def test_non_power_of_two_plans():
-    # Dirichlet and Neumann axes whose K is not a power of two take dense
-    # transforms (m <= 4095); periodic axes need the FFT (powers of two)
+    # axes whose K is not a power of two take dense transforms (m <= 4095)
     P = H.Plan1D(3, 12)
     try:
         assert P.m == 35
@@ -288,9 +304,12 @@ def test_non_power_of_two_plans():
     assert lib.hofem_plan1d_create_bc(9, 455, 0, ctypes.byref(h)) == 0   # m = 4094
     lib.hofem_plan1d_destroy(h)
     assert lib.hofem_plan1d_create_bc(9, 456, 0, ctypes.byref(h)) == -2   # m = 4103
-    assert lib.hofem_plan1d_create_bc(2, 12, 1, ctypes.byref(h)) == -2
-    assert lib.hofem_plan1d_create_bc(2, 12, 2, ctypes.byref(h)) == 0
+    for bc in (1, 2):                            # periodic and Neumann axes too
+        assert lib.hofem_plan1d_create_bc(2, 12, bc, ctypes.byref(h)) == 0
+        lib.hofem_plan1d_destroy(h)
+    assert lib.hofem_plan1d_create_bc(9, 455, 1, ctypes.byref(h)) == 0    # periodic m = 4095
     lib.hofem_plan1d_destroy(h)
+    assert lib.hofem_plan1d_create_bc(9, 456, 1, ctypes.byref(h)) == -2   # m = 4104
 
 
 @pytest.mark.parametrize("n,K", [(3, 12), (2, 3), (5, 6)])

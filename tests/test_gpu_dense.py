@@ -72,6 +72,10 @@ MIXED = [
     ((2, 3), (6, 10), (1.0, 1.0), 1.0, ("neumann", "neumann")),
     ((2, 4), (6, 16), (1.0, 1.0), 0.0, ("neumann", "dirichlet")),
     ((5, 2), (16, 12), (2.0, 1.0), 0.5, ("periodic", "neumann")),
+    ((2,), (6,), (1.0,), 1.0, ("periodic",)),                        # dense periodic axes
+    ((3,), (5,), (1.0,), 0.5, ("periodic",)),                        # odd K
+    ((2, 3), (10, 7), (1.0, 1.0), 0.0, ("periodic", "dirichlet")),
+    ((4, 2), (12, 6), (1.0, 1.0), 1.0, ("periodic", "neumann")),
 ]
 
 
