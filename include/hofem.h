@@ -440,8 +440,11 @@ int hofem_batch_offsets(hofem_batch batch, size_t* out_host, size_t len);
 /* Number of groups (distinct (solver, nrhs) pairs). */
 int hofem_batch_groups(hofem_batch batch, int* groups);
 
-/* Device workspace for hofem_batch_solve in `mode` (FP64, FP32 or FP32_IR;
- * 0 for the direct modes). */
+/* Device workspace for hofem_batch_solve in `mode` (FP64, FP32 or FP32_IR):
+ * the sum of the groups' hofem_solver_workspace_bytes (0 for the direct
+ * modes unless a group's solver has an axis whose K is not a power of two).
+ * Every group runs hofem_solve on its slab, so each mode accepts the solvers
+ * hofem_solve accepts in it (FP64: any boundary conditions and K). */
 int hofem_batch_workspace_bytes(hofem_batch batch, int mode, size_t* bytes);
 
 /* Solves every problem of the batch: f_dev, u_dev are packed buffers (double

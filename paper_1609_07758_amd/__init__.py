@@ -465,7 +465,7 @@ class Batch:
         for name, t in (("f", f), ("u", u)):
             if not t.is_cuda or not t.is_contiguous() or t.dtype != dt or t.numel() != self.total:
                 raise ValueError(f"{name} must be a contiguous {dt} device tensor of {self.total}")
-        if ws is None and mode == "fp32_ir":
+        if ws is None and hofem_batch_workspace_bytes(self.handle, mode) > 0:
             ws = self.workspace(mode, f.device)
         hofem_batch_solve(self.handle, mode, f, u, ws, max_iter, use_graph, stream)
         return u

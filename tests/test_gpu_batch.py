@@ -150,6 +150,41 @@ def test_3d_solver_shared_by_two_groups_graph():
             assert rel(batch.view(u, p)[j].cpu().numpy(), want) < 1e-12, (p, j)
 
 
+def test_batch_with_periodic_neumann_and_dense_groups():
+    # groups of periodic, Neumann, non-power-of-two (dense) and plain solvers
+    # in one FP64 batch, eager and from the graph, against the oracle
+    from oracle import periodic
+    X = (1.0, 1.0)
+    specs = [((2, 3), (8, 16), 1.0, ("neumann", "dirichlet")),
+             ((3, 2), (16, 8), 1.0, ("periodic", "periodic")),
+             ((2, 2), (6, 12), 0.0, ("dirichlet", "dirichlet")),
+             ((3, 3), (8, 8), 0.0, ("dirichlet", "dirichlet")),
+             ((2, 2), (6, 8), 1.0, ("neumann", "periodic"))]
+    solvers = [H.Solver(o, K, X, a, bcs=b) for o, K, a, b in specs]
+    probs = [(solvers[0], 2), (solvers[1], 1), (solvers[2], 1), (solvers[3], 2), (solvers[4], 1),
+             (solvers[0], 1)]
+    batch = H.Batch(probs)
+    rng = np.random.default_rng(13)
+    rhs = [rng.uniform(-1, 1, (r,) + s.shape) for s, r in probs]
+    f = fill(batch, rhs, torch.float64)
+    u_eager = torch.zeros_like(f)
+    batch.solve(f, u_eager, mode="fp64", use_graph=False)
+    torch.cuda.synchronize()
+    st = torch.cuda.Stream()
+    u = torch.zeros_like(f)
+    with torch.cuda.stream(st):
+        for rep in range(2):
+            u.zero_()
+            batch.solve(f, u, mode="fp64", use_graph=True, stream=st.cuda_stream)
+            st.synchronize()
+            assert torch.equal(u, u_eager), rep
+    for p, (s_, r) in enumerate(probs):
+        o, K, a, b = specs[solvers.index(s_)]
+        for j in range(r):
+            want = periodic.solve(rhs[p][j], o, K, X, a, b)
+            assert rel(batch.view(u, p)[j].cpu().numpy(), want) < 1e-12, (p, j)
+
+
 def test_batch_errors():
     batch, _ = make_batch(SMALL[:2], NRHS[:2])
     f = torch.zeros(batch.total, dtype=torch.float64, device=DEV)
