@@ -311,16 +311,20 @@ int hofem_apply_coef_operator(hofem_solver solver, const hofem_coef* coef, const
 
 /* Workspace bytes of hofem_apply_operator and hofem_apply_mass: for N = 3
  * with equal orders two grids of one right-hand side (the planes' stiffness
- * and mass products), 2 prod m_i doubles (rounded up to 256 bytes); 0
- * otherwise. */
+ * and mass products), 2 prod m_i doubles (rounded up to 256 bytes); with a
+ * periodic or Neumann axis N - 1 grids of one right-hand side (each rounded
+ * up to 256 bytes); 0 otherwise. */
 int hofem_operator_workspace_bytes(hofem_solver solver, size_t* bytes);
 
 /* out = L u with L the operator of eq. (bvp glob 2), FP64, matrix-free
  * (sum-factorised products of the 1D element matrices), the stiffness
  * factors in difference form sum_{l != k} A_kl (v_l - v_k) so that
- * constants are exactly in their kernel.  u_dev != out_dev.  ws_dev: at least
- * hofem_operator_workspace_bytes (may be NULL when that is 0); HOFEM_EINVAL
- * otherwise. */
+ * constants are exactly in their kernel.  Any boundary conditions: with a
+ * periodic or Neumann axis the products run one kernel per axis and term
+ * (assembled along each axis from the local matrices, wrapping around on a
+ * periodic axis, boundary nodes included on a Neumann axis).  u_dev !=
+ * out_dev.  ws_dev: at least hofem_operator_workspace_bytes (may be NULL
+ * when that is 0); HOFEM_EINVAL otherwise. */
 int hofem_apply_operator(hofem_solver solver, const double* u_dev, double* out_dev, int nrhs,
                          void* ws_dev, size_t ws_bytes, void* stream);
 

@@ -733,11 +733,11 @@ size_t solver_unknowns(const hofem_solver_s* S) { return S->per_rhs; }
 bool solver_all_dirichlet(const hofem_solver_s* S) { return all_dirichlet(S) && !has_dense(S); }
 int solver_dims(const hofem_solver_s* S) { return S->N; }
 bool solver_has_dense(const hofem_solver_s* S) { return has_dense(S); }
-int solver_axis_mass(const hofem_solver_s* S, int axis, AxisMass* out) {
+int solver_axis_local(const hofem_solver_s* S, int axis, AxisLocal* out) {
   if (axis < 0 || axis >= S->N) return HOFEM_EINVAL;
   const DevAxis& X = S->ax[axis];
   const size_t nb = (size_t)X.n + 1;
-  if (nb * nb > 100 || X.hC.size() != nb * nb) return HOFEM_EINVAL;
+  if (nb * nb > 100 || X.hC.size() != nb * nb || X.hA.size() != nb * nb) return HOFEM_EINVAL;
   out->bc = X.bc;
   out->n = X.n;
   out->K = X.K;
@@ -745,9 +745,13 @@ int solver_axis_mass(const hofem_solver_s* S, int axis, AxisMass* out) {
   long long inner = 1;
   for (int b = axis + 1; b < S->N; ++b) inner *= S->ax[b].m;
   out->inner = inner;
-  for (size_t i = 0; i < nb * nb; ++i) out->C[i] = X.hC[i];
+  for (size_t i = 0; i < nb * nb; ++i) {
+    out->C[i] = X.hC[i];
+    out->A[i] = X.hA[i];
+  }
   return HOFEM_OK;
 }
+
 double solver_alpha(const hofem_solver_s* S) { return S->alpha; }
 int solver_device(const hofem_solver_s* S) { return S->device; }
 size_t solver_op_elem_bytes(const hofem_solver_s* S) { return op_elem_bytes(S); }
@@ -1279,9 +1283,16 @@ int hofem_apply_coef_operator(hofem_solver S, const hofem_coef* coef, const doub
   return HOFEM_OK;
 }
 
+// With a periodic or Neumann axis the operator and the mass product run one
+// kernel per axis (and per term), one right-hand side at a time, through
+// N - 1 grids of one right-hand side.
+static size_t axes_op_bytes(const hofem_solver_s* S) {
+  return (size_t)(S->N - 1) * ((S->per_rhs * sizeof(double) + 255) & ~size_t(255));
+}
+
 int hofem_operator_workspace_bytes(hofem_solver S, size_t* bytes) {
   if (!S || !bytes) return HOFEM_EINVAL;
-  *bytes = op_elem_bytes(S);
+  *bytes = all_dirichlet(S) ? op_elem_bytes(S) : axes_op_bytes(S);
   return HOFEM_OK;
 }
 
@@ -1290,10 +1301,51 @@ namespace {
 // out = L u, or with mass_only the mass product (x)_i C_i u (the operator's
 // stiffness scales set to 0 and alpha to 1: the stiffness terms then vanish
 // exactly).
+// Any boundary conditions: L u = sum_i T_i u with T_0 = (s_0 A_0 + alpha C_0)
+// (x) C_1 ... and T_i = C_0 (x) .. s_i A_i .. (x) C_{N-1} (mass only: one term
+// of mass factors), each term a chain of one kernel per axis ending in out.
+int apply_op_axes(hofem_solver S, const double* u, double* out, int nrhs, double* ws, hipStream_t st,
+                  bool mass_only) {
+  const int N = S->N;
+  const long long M = (long long)S->per_rhs;
+  const size_t grid = ((size_t)M * sizeof(double) + 255) & ~size_t(255);
+  double* tmp[2] = {ws, ws ? ws + grid / sizeof(double) : nullptr};
+  AxisLocal al[3];
+  for (int a = 0; a < N; ++a) {
+    const int rc = solver_axis_local(S, a, &al[a]);
+    if (rc != HOFEM_OK) return rc;
+  }
+  const int terms = mass_only ? 1 : N;
+  for (int r = 0; r < nrhs; ++r) {
+    const double* ur = u + (size_t)r * M;
+    double* orr = out + (size_t)r * M;
+    for (int i = 0; i < terms; ++i) {
+      const double* src = ur;
+      for (int a = 0; a < N; ++a) {
+        double cc = 1.0, ca = 0.0;
+        if (!mass_only && a == i) {
+          cc = i == 0 ? S->alpha : 0.0;
+          ca = S->ax[a].scale;
+        }
+        const bool last = a == N - 1;
+        double* dst = last ? orr : tmp[a % 2];
+        HIPCHK(launch_axis_local(al[a], src, dst, (last && i > 0) ? orr : nullptr, cc, ca, M, st));
+        src = dst;
+      }
+    }
+  }
+  return HOFEM_OK;
+}
+
 int apply_op(hofem_solver S, const double* u_dev, double* out_dev, int nrhs, void* ws_dev,
              size_t ws_bytes, void* stream, bool mass_only) {
   if (!S || !u_dev || !out_dev || nrhs < 1 || u_dev == out_dev) return HOFEM_EINVAL;
-  if (!all_dirichlet(S)) return HOFEM_EUNSUPPORTED;
+  if (!all_dirichlet(S)) {
+    const size_t need = axes_op_bytes(S);
+    if (need && (!ws_dev || ws_bytes < need)) return HOFEM_EINVAL;
+    return apply_op_axes(S, u_dev, out_dev, nrhs, static_cast<double*>(ws_dev),
+                         static_cast<hipStream_t>(stream), mass_only);
+  }
   const size_t need = op_elem_bytes(S);
   if (need && (!ws_dev || ws_bytes < need)) return HOFEM_EINVAL;
   OpArgs o;

@@ -1,7 +1,10 @@
 // FP64 operator of eq. (bvp glob 2) and the small kernels of the refinement
 // loop (update with norms, reduction).
 
+#include <algorithm>
+
 #include "kernels.h"
+#include "solver.h"
 
 namespace hofem {
 namespace {
@@ -865,6 +868,62 @@ hipError_t launch_dirichlet_lift(const OpArgs& a, const double* bext, const doub
     case 3: hipLaunchKernelGGL(dirichlet_lift_kernel<3>, dim3(blocks), dim3(256), 0, s, a, bext, f, out, total); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+namespace {
+
+// One axis of any boundary condition: global point g = 0..nK of the axis
+// (element e = 1..K holds the points n(e-1)..ne, local index g - n(e-1));
+// the unknowns are g = 1..nK-1 (Dirichlet; the boundary values are zero),
+// g = 0..nK-1 with nK identified with 0 (periodic) or g = 0..nK (Neumann).
+__global__ __launch_bounds__(256) void axis_local_kernel(AxisLocal a, const double* __restrict__ in,
+                                                         double* out, const double* add, double cc,
+                                                         double ca, long long total) {
+  const int n = a.n, K = a.K, nb = n + 1, nK = n * K;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int q = (int)((i / a.inner) % a.m);
+    const long long base = i - (long long)q * a.inner;   // point 0 of this line
+    const int g = a.bc == 0 ? q + 1 : q;
+    const int j = g / n, s = g - j * n;
+    auto val = [&](int h) -> double {
+      int qq = h;
+      if (a.bc == 0) {
+        if (h <= 0 || h >= nK) return 0.0;
+        qq = h - 1;
+      } else if (a.bc == 1 && h == nK) {
+        qq = 0;
+      }
+      return in[base + (long long)qq * a.inner];
+    };
+    const double vg = in[i];
+    double acc = 0.0;
+    auto elem = [&](int e, int loc) {
+      for (int r = 0; r < nb; ++r) {
+        const double v = val(n * (e - 1) + r);
+        acc += cc * a.C[loc * nb + r] * v;
+        if (r != loc) acc += ca * a.A[loc * nb + r] * (v - vg);
+      }
+    };
+    if (s == 0) {   // node j: the end of element j and the start of element j + 1
+      if (j >= 1) elem(j, n);
+      else if (a.bc == 1) elem(K, n);   // periodic: node 0 also ends element K
+      if (j <= K - 1) elem(j + 1, 0);
+    } else {
+      elem(j + 1, s);
+    }
+    out[i] = acc + (add ? add[i] : 0.0);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_axis_local(const AxisLocal& a, const double* in, double* out, const double* add,
+                             double cc, double ca, long long total, hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<long long>((total + 255) / 256, 8192);
+  hipLaunchKernelGGL(axis_local_kernel, dim3(blocks), dim3(256), 0, s, a, in, out, add, cc, ca, total);
   return hipGetLastError();
 }
 

@@ -24,16 +24,24 @@ int solver_solve_fp64(hofem_solver_s* S, const double* in, double* out, int nrhs
 // Axes, and whether one has K not a power of two (dense transforms).
 int solver_dims(const hofem_solver_s* S);
 bool solver_has_dense(const hofem_solver_s* S);
-// One axis of the grid for the mass product of any boundary condition:
+// One axis of the grid for the per-axis products of any boundary condition:
 // condition (0 Dirichlet, 1 periodic, 2 Neumann), order, elements, unknowns
 // m, stride of the axis in the C-order grid of one right-hand side, and the
-// local mass matrix on [-1, 1] (row major, (n+1)^2 <= 100 values).
-struct AxisMass {
+// local mass and stiffness matrices on [-1, 1] (row major, (n+1)^2 <= 100
+// values each).
+struct AxisLocal {
   int bc, n, K, m;
   long long inner;
   double C[100];
+  double A[100];
 };
-int solver_axis_mass(const hofem_solver_s* S, int axis, AxisMass* out);
+int solver_axis_local(const hofem_solver_s* S, int axis, AxisLocal* out);
+// out = cc (C_axis (x) I) in + ca (A_axis (x) I) in + add (add may be NULL or
+// out itself) along one axis of `total` points (several right-hand sides in
+// sequence), each point summing the local rows of the one or two elements
+// that hold it, the stiffness in difference form sum_{r != l} A_lr (v_r - v_l).
+hipError_t launch_axis_local(const AxisLocal& a, const double* in, double* out, const double* add,
+                             double cc, double ca, long long total, hipStream_t s);
 // out = f + coef ((x)_i C_i) w (f == NULL: out = coef (x)C w), FP64, by the
 // operator kernels with the stiffness scales set to zero; elem: element
 // buffer of solver_op_elem_bytes.  w != out.

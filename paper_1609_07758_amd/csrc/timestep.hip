@@ -53,66 +53,20 @@ __global__ void wave_shift(const double* __restrict__ u, double* __restrict__ up
   }
 }
 
-// out = coef (C_axis (x) I) in + add (add may be NULL) along one axis of a
-// C-order grid of `total` points, for any boundary condition of the axis:
-// each point sums the local mass rows of the one or two elements that hold
-// it.  Global point g = 0..nK of the axis (element e = 1..K holds the points
-// n(e-1)..ne, local index g - n(e-1)); the unknowns are g = 1..nK-1
-// (Dirichlet; the boundary values are zero), g = 0..nK-1 with nK = 0
-// (periodic) or g = 0..nK (Neumann).
-__global__ __launch_bounds__(256) void mass_axis_kernel(AxisMass a, const double* __restrict__ in,
-                                                        double* __restrict__ out,
-                                                        const double* __restrict__ add, double coef,
-                                                        long long total) {
-  const int n = a.n, K = a.K, nb = n + 1, nK = n * K;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
-       i += (long long)gridDim.x * blockDim.x) {
-    const int q = (int)((i / a.inner) % a.m);
-    const long long base = i - (long long)q * a.inner;   // point 0 of this line
-    const int g = a.bc == 0 ? q + 1 : q;
-    const int j = g / n, s = g - j * n;
-    auto val = [&](int h) -> double {
-      int qq = h;
-      if (a.bc == 0) {
-        if (h <= 0 || h >= nK) return 0.0;
-        qq = h - 1;
-      } else if (a.bc == 1 && h == nK) {
-        qq = 0;
-      }
-      return in[base + (long long)qq * a.inner];
-    };
-    double acc = 0.0;
-    auto elem = [&](int e, int loc) {
-      for (int r = 0; r < nb; ++r) acc += a.C[loc * nb + r] * val(n * (e - 1) + r);
-    };
-    if (s == 0) {   // node j: the end of element j and the start of element j + 1
-      if (j >= 1) elem(j, n);
-      else if (a.bc == 1) elem(K, n);   // periodic: node 0 also ends element K
-      if (j <= K - 1) elem(j + 1, 0);
-    } else {
-      elem(j + 1, s);
-    }
-    out[i] = coef * acc + (add ? add[i] : 0.0);
-  }
-}
-
 // out = f + coef ((x)_i C_i) w, one axis after another (w != out; tmp: one
 // grid, used when there are two or more axes).
 int mass_chain(hofem_stepper_s* T, const double* f, const double* w, double* out, double coef,
                double* tmp, int nrhs, hipStream_t st) {
   const int N = solver_dims(T->S);
   const long long total = (long long)solver_unknowns(T->S) * nrhs;
-  const unsigned blocks = (unsigned)std::min<long long>((total + 255) / 256, 8192);
   const double* src = w;
   for (int ax = 0; ax < N; ++ax) {
-    AxisMass am;
-    const int rc = solver_axis_mass(T->S, ax, &am);
+    AxisLocal al;
+    const int rc = solver_axis_local(T->S, ax, &al);
     if (rc != HOFEM_OK) return rc;
     double* dst = ((N - 1 - ax) % 2 == 0) ? out : tmp;
     const bool last = ax == N - 1;
-    hipLaunchKernelGGL(mass_axis_kernel, dim3(blocks), dim3(256), 0, st, am, src, dst,
-                       last ? f : nullptr, last ? coef : 1.0, total);
-    const hipError_t e = hipGetLastError();
+    const hipError_t e = launch_axis_local(al, src, dst, last ? f : nullptr, last ? coef : 1.0, 0.0, total, st);
     if (e != hipSuccess) return record_hip_error(e);
     src = dst;
   }

@@ -117,8 +117,9 @@ def test_periodic_unsupported_paths():
             with pytest.raises(H.HofemError) as e:
                 S.solve(f, mode=mode)
             assert e.value.status == -2
-        with pytest.raises(H.HofemError) as e:
-            S.apply_mass(f)
+        with pytest.raises(H.HofemError) as e:   # the Dirichlet lift
+            H.hofem_dirichlet_rhs(S.handle, torch.zeros(10 * 18, dtype=torch.float64, device=DEV), None,
+                                  f, 1, None)
         assert e.value.status == -2
     finally:
         S.close()
@@ -264,3 +265,37 @@ def test_neumann_full_size_backward_error():
     eta = np.linalg.norm(r) / (Linf * np.linalg.norm(u) + np.linalg.norm(f))
     print(f"Neumann backward error, full size: {eta:.3e}")
     assert eta < 1e-15
+
+# the FP64 operator and mass product with periodic and Neumann axes (one
+# kernel per axis and term): against the oracle's assembled operator
+OP_CASES = [
+    ((3,), (16,), (1.0,), 0.5, (NM,)),
+    ((2,), (8,), (2.0,), 1.0, (P,)),
+    ((3, 2), (8, 16), (1.0, 0.5), 1.0, (NM, D)),
+    ((2, 4), (16, 8), (1.0, 1.0), 1.0, (P, NM)),
+    ((2, 2, 3), (4, 8, 4), (1.0, 1.0, 1.0), 2.0, (NM, P, D)),
+    ((9, 2), (8, 6), (1.0, 1.0), 1.0, (NM, P)),                      # dense periodic axis
+]
+
+
+@pytest.mark.parametrize("orders,Ks,X,alpha,bcs", OP_CASES)
+def test_operator_and_mass_with_periodic_and_neumann_axes(orders, Ks, X, alpha, bcs):
+    shp = grid(orders, Ks, bcs)
+    u = workloads.uniform_rhs((2,) + shp, seed=21)
+    S = H.Solver(orders, Ks, X, alpha, bcs=bcs)
+    try:
+        assert (H.hofem_operator_workspace_bytes(S.handle) > 0) == (len(orders) > 1)
+        ud = torch.from_numpy(u).to(DEV).reshape(-1)
+        Lu = S.apply_operator(ud, nrhs=2).cpu().numpy().reshape(u.shape)
+        Mu = S.apply_mass(ud, nrhs=2).cpu().numpy().reshape(u.shape)
+    finally:
+        S.close()
+    Cs = [periodic.axis_matrices(n, K, b)[1] for n, K, b in zip(orders, Ks, bcs)]
+    for r in range(2):
+        want = periodic.apply_operator(u[r], orders, Ks, X, alpha, bcs)
+        assert rel(Lu[r], want) < 1e-13
+        m = u[r]
+        for a, C in enumerate(Cs):
+            v = np.moveaxis(m, a, 0)
+            m = np.moveaxis((C @ v.reshape(v.shape[0], -1)).reshape(v.shape), 0, a)
+        assert rel(Mu[r], m) < 1e-14
