@@ -316,94 +316,123 @@ __global__ __launch_bounds__(kNeuMaxThreads) void neumann_pass(PassArgs a) {
     cx<double>& e = slot(c, lp::Seq<N>::pair(s), k);
     return lp::Seq<N>::part(s) ? e.y : e.x;
   };
-  const int items_k = cfast ? cb * (K + 1) : cv * (K + 1);
-  for (int i = tid; i < items_k; i += nthr) {
-    int c, k;
-    split(i, K + 1, c, k);
+  // wave numbers k = 1..K-1: one lane per (pair of lines, k), the
+  // eigenvector rows of k read once for both lines
+  const int npc = cb > 1 ? cb / 2 : 1, lnpc = __builtin_ctz(npc);
+  const int items_p = (cfast ? npc : (cv + 1) / 2) * (K - 1);
+  for (int i = tid; i < items_p; i += nthr) {
+    int cp, k;
+    if (cfast) {
+      cp = i & (npc - 1);
+      k = (i >> lnpc) + 1;
+    } else {
+      cp = i / (K - 1);
+      k = i - cp * (K - 1) + 1;
+    }
+    const int c0 = 2 * cp, c1 = c0 + 1;
+    if (c0 >= cv) continue;
+    const bool two = c1 < cv;
+    const long long ob[2] = {lbase(c0), two ? lbase(c1) : 0};
+    const lp::tgrp<double>* tb = lp::blk_at<N>(BLK, k);
+    double x[2][N], y[2][N];
+    if (MODE != PASS_INV) {
+#pragma unroll
+      for (int s = 0; s < N; ++s) {
+        x[0][s] = comp(c0, s, k);
+        x[1][s] = two ? comp(c1, s, k) : 0.0;
+      }
+    }
+    if (MODE == PASS_FUSED) {
+      const double dl[2] = {line_den(c0), two ? line_den(c1) : 1.0};
+      lp::fused_lines<double, N, 2>(tb, LAM + (k - 1), K - 1, dl, sc, x, y);
+    } else {
+#pragma unroll
+      for (int s = 0; s < N; ++s) y[0][s] = y[1][s] = 0.0;
+#pragma unroll
+      for (int l = 0; l < N; ++l) {
+        double p[N > 1 ? N - 1 : 1];
+#pragma unroll
+        for (int s = 1; s < N; ++s) p[s - 1] = lp::tab_e(tb, l * (N - 1) + s - 1);
+        const long long qo = ((long long)l * (K - 1) + (k - 1)) * inner;
+        if (MODE == PASS_FWD) {
+          const double nrm = lp::tab_e(tb, N * (N - 1) + l);
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            double acc = x[u][0];
+#pragma unroll
+            for (int s = 1; s < N; ++s) acc += p[s - 1] * x[u][s];
+            if (u == 0 || two) dst[ob[u] + qo] = acc * nrm;
+          }
+        } else {
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const double w = (u == 0 || two) ? src[ob[u] + qo] : 0.0;
+            y[u][0] += w;
+#pragma unroll
+            for (int s = 1; s < N; ++s) y[u][s] += w * p[s - 1];
+          }
+        }
+      }
+    }
+    if (MODE != PASS_FWD) {
+#pragma unroll
+      for (int s = 0; s < N; ++s) {
+        comp(c0, s, k) = y[0][s];
+        if (two) comp(c1, s, k) = y[1][s];
+      }
+    }
+  }
+  // band edges: theta = 0 (k = 0, entry 0 .x) and theta = pi (k = K, .y),
+  // one lane per (line, edge)
+  const int items_b = (cfast ? cb : cv) * 2;
+  for (int i = tid; i < items_b; i += nthr) {
+    int c, e;
+    split(i, 2, c, e);
     if (c >= cv) continue;
     const long long ob = lbase(c);
     const double dline = MODE == PASS_FUSED ? line_den(c) : 0.0;
-    if (k >= 1 && k < K) {
-      const lp::tgrp<double>* tb = lp::blk_at<N>(BLK, k);
-      double x[1][N], y[1][N];
-      if (MODE != PASS_INV) {
+    const bool hi = e == 1;
+    const int b0 = hi ? NB0 : 0, b1 = hi ? N + 1 : NB0;
+    cx<double>& nodee = slot(c, NP - 1, 0);
+    const double t0 = hi ? nodee.y : nodee.x;
+    double zp[NP > 1 ? NP - 1 : 1];   // Z^s_0 + Z^{n-s}_0 or Z^s_K - Z^{n-s}_K, s = p + 1
 #pragma unroll
-        for (int s = 0; s < N; ++s) x[0][s] = comp(c, s, k);
-      }
-      if (MODE == PASS_FUSED) {
-        const double dl[1] = {dline};
-        lp::fused_lines<double, N, 1>(tb, LAM + (k - 1), K - 1, dl, sc, x, y);
+    for (int p = 0; p < NP - 1; ++p) zp[p] = hi ? slot(c, p, 0).y : slot(c, p, 0).x;
+    const double zmid = (kEven && !hi) ? side[c] : 0.0;
+    double wsum = 0.0, hp[NP > 1 ? NP - 1 : 1], hmid = 0.0;
+#pragma unroll
+    for (int p = 0; p < NP - 1; ++p) hp[p] = 0.0;
+    for (int b = b0; b < b1; ++b) {
+      const double* w = BAND + (size_t)b * N;
+      const long long qa = ob + ((long long)N * (K - 1) + b) * inner;
+      double cf;
+      if (MODE == PASS_INV) {
+        cf = src[qa];
       } else {
+        double acc = w[0] * t0;
 #pragma unroll
-        for (int s = 0; s < N; ++s) y[0][s] = 0.0;
-#pragma unroll
-        for (int l = 0; l < N; ++l) {
-          double p[N > 1 ? N - 1 : 1];
-#pragma unroll
-          for (int s = 1; s < N; ++s) p[s - 1] = lp::tab_e(tb, l * (N - 1) + s - 1);
-          const long long qa = ob + ((long long)l * (K - 1) + (k - 1)) * inner;
-          if (MODE == PASS_FWD) {
-            double acc = x[0][0];
-#pragma unroll
-            for (int s = 1; s < N; ++s) acc += p[s - 1] * x[0][s];
-            dst[qa] = acc * lp::tab_e(tb, N * (N - 1) + l);
-          } else {
-            const double w = src[qa];
-            y[0][0] += w;
-#pragma unroll
-            for (int s = 1; s < N; ++s) y[0][s] += w * p[s - 1];
-          }
+        for (int p = 0; p < NP - 1; ++p) acc += 0.5 * w[p + 1] * zp[p];
+        if constexpr (kEven) acc += 0.5 * w[N / 2] * zmid;
+        cf = acc / K;
+        if (MODE == PASS_FWD) {
+          dst[qa] = cf;
+          continue;
         }
+        cf /= dline + sc * LAM[(size_t)N * (K - 1) + b];
       }
-      if (MODE != PASS_FWD) {
+      wsum += cf * w[0];
 #pragma unroll
-        for (int s = 0; s < N; ++s) comp(c, s, k) = y[0][s];
+      for (int p = 0; p < NP - 1; ++p) hp[p] += 0.5 * cf * w[p + 1];
+      if constexpr (kEven) hmid += 0.5 * cf * w[N / 2];
+    }
+    if (MODE != PASS_FWD) {
+      if (hi) nodee.y = wsum; else nodee.x = wsum;
+#pragma unroll
+      for (int p = 0; p < NP - 1; ++p) {
+        if (hi) slot(c, p, 0).y = hp[p]; else slot(c, p, 0).x = hp[p];
       }
-    } else {
-      // band edge: theta = 0 (k = 0, entry 0 .x) or theta = pi (k = K, .y)
-      const bool hi = k == K;
-      const int b0 = hi ? NB0 : 0, b1 = hi ? N + 1 : NB0;
-      cx<double>& nodee = slot(c, NP - 1, 0);
-      const double t0 = hi ? nodee.y : nodee.x;
-      double zp[NP > 1 ? NP - 1 : 1];   // Z^s_0 + Z^{n-s}_0 or Z^s_K - Z^{n-s}_K, s = p + 1
-#pragma unroll
-      for (int p = 0; p < NP - 1; ++p) zp[p] = hi ? slot(c, p, 0).y : slot(c, p, 0).x;
-      const double zmid = (kEven && !hi) ? side[c] : 0.0;
-      double wsum = 0.0, hp[NP > 1 ? NP - 1 : 1], hmid = 0.0;
-#pragma unroll
-      for (int p = 0; p < NP - 1; ++p) hp[p] = 0.0;
-      for (int b = b0; b < b1; ++b) {
-        const double* w = BAND + (size_t)b * N;
-        const long long qa = ob + ((long long)N * (K - 1) + b) * inner;
-        double cf;
-        if (MODE == PASS_INV) {
-          cf = src[qa];
-        } else {
-          double acc = w[0] * t0;
-#pragma unroll
-          for (int p = 0; p < NP - 1; ++p) acc += 0.5 * w[p + 1] * zp[p];
-          if constexpr (kEven) acc += 0.5 * w[N / 2] * zmid;
-          cf = acc / K;
-          if (MODE == PASS_FWD) {
-            dst[qa] = cf;
-            continue;
-          }
-          cf /= dline + sc * LAM[(size_t)N * (K - 1) + b];
-        }
-        wsum += cf * w[0];
-#pragma unroll
-        for (int p = 0; p < NP - 1; ++p) hp[p] += 0.5 * cf * w[p + 1];
-        if constexpr (kEven) hmid += 0.5 * cf * w[N / 2];
-      }
-      if (MODE != PASS_FWD) {
-        if (hi) nodee.y = wsum; else nodee.x = wsum;
-#pragma unroll
-        for (int p = 0; p < NP - 1; ++p) {
-          if (hi) slot(c, p, 0).y = hp[p]; else slot(c, p, 0).x = hp[p];
-        }
-        if constexpr (kEven) {
-          if (!hi) side[c] = hmid;
-        }
+      if constexpr (kEven) {
+        if (!hi) side[c] = hmid;
       }
     }
   }
