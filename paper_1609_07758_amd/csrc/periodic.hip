@@ -152,69 +152,86 @@ __global__ __launch_bounds__(kPerMaxThreads) void periodic_pass(PassArgs a) {
   const double invK = 1.0 / K;
   const double sc = a.scale;
   constexpr int ne = N * N;
-  // the n x n block of wave number k of line c
-  auto block = [&](int c, int k, double dline) {
+  // the n x n blocks of wave number k of lines c0 and (when two) c0 + 1:
+  // each Bloch vector is read once for both lines
+  auto block = [&](int c0, bool two, int k, const double (&dline)[2]) {
     const int kk = (K - k) & (K - 1);
     const int tre = k == 0 ? 0 : (2 * k == K ? K - 1 : 2 * k - 1);   // the real part's t
     const bool cplx = k != 0 && 2 * k != K;
     const cx<double>* __restrict__ wk = W + (size_t)(k >> 6) * ne * 64 + (k & 63);
-    cx<double> X[2 * NP], U[N];
+    cx<double> X[2][2 * NP], U[2][N];
     if (MODE == PASS_FWD || MODE == PASS_FUSED) {
 #pragma unroll
-      for (int p = 0; p < NP; ++p) {
-        const cx<double> u = slot(c, p, k), w = slot(c, p, kk);
-        X[2 * p] = {0.5 * (u.x + w.x), 0.5 * (u.y - w.y)};
-        X[2 * p + 1] = {0.5 * (u.y + w.y), -0.5 * (u.x - w.x)};
+      for (int v = 0; v < 2; ++v) {
+        const int c = two ? c0 + v : c0;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+          const cx<double> u = slot(c, p, k), w = slot(c, p, kk);
+          X[v][2 * p] = {0.5 * (u.x + w.x), 0.5 * (u.y - w.y)};
+          X[v][2 * p + 1] = {0.5 * (u.y + w.y), -0.5 * (u.x - w.x)};
+        }
       }
     }
 #pragma unroll
-    for (int s = 0; s < N; ++s) U[s] = {0.0, 0.0};
-    const long long ob = MODE != PASS_FUSED ? lbase(c) : 0;
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int s = 0; s < N; ++s) U[v][s] = {0.0, 0.0};
+    const long long ob[2] = {MODE != PASS_FUSED ? lbase(c0) : 0,
+                             MODE != PASS_FUSED && two ? lbase(c0 + 1) : 0};
     // one eigenvector per iteration (n complex entries in registers)
 #pragma unroll 1
     for (int l = 0; l < N; ++l) {
       cx<double> wl[N];
 #pragma unroll
       for (int s = 0; s < N; ++s) wl[s] = wk[(size_t)(l * N + s) * 64];
-      double cr, ci;
-      if (MODE == PASS_INV) {
-        // (in place is safe: a workgroup reads only its own lines, all of
-        // them before the barrier that precedes its stores)
-        cr = src[ob + ((long long)l * K + tre) * inner];
-        ci = cplx ? src[ob + ((long long)l * K + tre + 1) * inner] : 0.0;
-      } else {
-        cr = 0.0;
-        ci = 0.0;
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        if (v == 1 && !two) break;
+        double cr, ci;
+        if (MODE == PASS_INV) {
+          // (in place is safe: a workgroup reads only its own lines, all of
+          // them before the barrier that precedes its stores)
+          cr = src[ob[v] + ((long long)l * K + tre) * inner];
+          ci = cplx ? src[ob[v] + ((long long)l * K + tre + 1) * inner] : 0.0;
+        } else {
+          cr = 0.0;
+          ci = 0.0;
+#pragma unroll
+          for (int s = 0; s < N; ++s) {
+            cr += wl[s].x * X[v][s].x + wl[s].y * X[v][s].y;   // conj(w) X
+            ci += wl[s].x * X[v][s].y - wl[s].y * X[v][s].x;
+          }
+          cr *= invK;
+          ci = cplx ? ci * invK : 0.0;
+          if (MODE == PASS_FWD) {
+            dst[ob[v] + ((long long)l * K + tre) * inner] = cr;
+            if (cplx) dst[ob[v] + ((long long)l * K + tre + 1) * inner] = ci;
+            continue;
+          }
+          const double den = dline[v] + sc * a.tab.lam[(size_t)l * K + tre];
+          cr /= den;
+          ci /= den;
+        }
 #pragma unroll
         for (int s = 0; s < N; ++s) {
-          cr += wl[s].x * X[s].x + wl[s].y * X[s].y;   // conj(w) X
-          ci += wl[s].x * X[s].y - wl[s].y * X[s].x;
+          U[v][s].x += cr * wl[s].x - ci * wl[s].y;
+          U[v][s].y += cr * wl[s].y + ci * wl[s].x;
         }
-        cr *= invK;
-        ci = cplx ? ci * invK : 0.0;
-        if (MODE == PASS_FWD) {
-          dst[ob + ((long long)l * K + tre) * inner] = cr;
-          if (cplx) dst[ob + ((long long)l * K + tre + 1) * inner] = ci;
-          continue;
-        }
-        const double den = dline + sc * a.tab.lam[(size_t)l * K + tre];
-        cr /= den;
-        ci /= den;
-      }
-#pragma unroll
-      for (int s = 0; s < N; ++s) {
-        U[s].x += cr * wl[s].x - ci * wl[s].y;
-        U[s].y += cr * wl[s].y + ci * wl[s].x;
       }
     }
     if (MODE == PASS_FWD) return;
     // inverse-FFT input as conj(Z), Z = U_s + i U_{s+1}, at entries k and K - k
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      const cx<double> U0 = U[2 * p];
-      const cx<double> U1 = 2 * p + 1 < N ? U[2 * p + 1] : cx<double>{0.0, 0.0};
-      slot(c, p, k) = {U0.x - U1.y, -(U0.y + U1.x)};
-      if (kk != k) slot(c, p, kk) = {U0.x + U1.y, U0.y - U1.x};
+    for (int v = 0; v < 2; ++v) {
+      if (v == 1 && !two) break;
+      const int c = c0 + v;
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        const cx<double> U0 = U[v][2 * p];
+        const cx<double> U1 = 2 * p + 1 < N ? U[v][2 * p + 1] : cx<double>{0.0, 0.0};
+        slot(c, p, k) = {U0.x - U1.y, -(U0.y + U1.x)};
+        if (kk != k) slot(c, p, kk) = {U0.x + U1.y, U0.y - U1.x};
+      }
     }
   };
   // denominator part of line c from the other axes (fused pass)
@@ -224,14 +241,25 @@ __global__ __launch_bounds__(kPerMaxThreads) void periodic_pass(PassArgs a) {
     for (int i = 0; i < a.nother; ++i) d += a.oscale[i] * a.olam[i][(t / a.odiv[i]) % a.omod[i]];
     return d;
   };
-  const int items_k = cfast ? cb * H : cv * H;
+  // one lane per (pair of lines, wave number k and its mirror K - k)
+  const int npc = cb > 1 ? cb / 2 : 1, lnpc = __builtin_ctz(npc);
+  const int items_k = (cfast ? npc : (cv + 1) / 2) * H;
   for (int i = tid; i < items_k; i += nthr) {
-    int c, k;
-    split(i, H, c, k);
-    if (c >= cv) continue;
-    const double dline = MODE == PASS_FUSED ? line_den(c) : 0.0;
-    block(c, k, dline);
-    if (k == 0) block(c, H, dline);   // the other self-conjugate wave number
+    int cp, k;
+    if (cfast) {
+      cp = i & (npc - 1);
+      k = i >> lnpc;
+    } else {
+      cp = i / H;
+      k = i - cp * H;
+    }
+    const int c0 = 2 * cp;
+    if (c0 >= cv) continue;
+    const bool two = c0 + 1 < cv;
+    const double dline[2] = {MODE == PASS_FUSED ? line_den(c0) : 0.0,
+                             MODE == PASS_FUSED && two ? line_den(c0 + 1) : 0.0};
+    block(c0, two, k, dline);
+    if (k == 0) block(c0, two, H, dline);   // the other self-conjugate wave number
   }
   if (MODE == PASS_FWD) return;
   __syncthreads();
