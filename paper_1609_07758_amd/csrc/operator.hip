@@ -353,7 +353,13 @@ __global__ __launch_bounds__(kOpSfThreads) __attribute__((amdgpu_waves_per_eu(4)
   double* P = reinterpret_cast<double*>(smem);   // [R][W]
   double* D = P + R * W;                         // [R][W]
   const int K0 = a.K[0], K1 = a.K[1], m0 = a.m[0], m1 = a.m[1];
-  const int t0 = blockIdx.x / nt1, t1 = blockIdx.x - t0 * nt1;
+  // Workgroups are dealt to the eight XCDs in turn; give each XCD a
+  // contiguous run of tiles (row-major), so that the halo rows and columns a
+  // tile shares with its neighbours are read once into that XCD's L2.
+  const int nblk = (int)gridDim.x, qx = nblk >> 3, rx = nblk & 7;
+  const int xcd = (int)blockIdx.x & 7, jx = (int)blockIdx.x >> 3;
+  const int tile = xcd * qx + (xcd < rx ? xcd : rx) + jx;
+  const int t0 = tile / nt1, t1 = tile - t0 * nt1;
   const long long roff = (long long)blockIdx.y * m0 * m1;
   const int E0 = t0 * TE0, E1 = t1 * TE1;   // elements before the tile
   const int tid = threadIdx.x;
@@ -522,9 +528,14 @@ hipError_t launch_op2_sf(const OpArgs& a, hipStream_t s) {
 // (2 grids of one right-hand side); every output has one writer.
 // ---------------------------------------------------------------------------
 
-// One lane per (point of the axis-1/2 plane, element e along axis 0): the
-// element's outputs at positions n(e-1)+r, r = 1..n (the node n e also takes
-// the first row of element e+1).
+// One lane per (point of the axis-1/2 plane, run of kOp3Run elements along
+// axis 0): element e's outputs at positions n(e-1)+r, r = 1..n (the node n e
+// also takes the first row of element e+1).  The lane walks its run and keeps
+// the next element's values for the following one, so every position of Z1
+// and Z2 is read about once (a lane per element read its neighbour's rows
+// again, from HBM: the lane that owns them runs a plane's worth of work later).
+constexpr int kOp3Run = 16;
+
 template <int NO>
 __global__ __launch_bounds__(256) void op3_axis0_kernel(const double* __restrict__ Z1,
                                                         const double* __restrict__ Z2,
@@ -532,45 +543,64 @@ __global__ __launch_bounds__(256) void op3_axis0_kernel(const double* __restrict
                                                         int out_f32, int K0, int m0, long long plane,
                                                         double s0, OpMats mt) {
   constexpr int B = NO + 1;
+  const int nrun = (K0 + kOp3Run - 1) / kOp3Run;
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= plane * K0) return;
+  if (t >= plane * nrun) return;
   const long long pt = t % plane;
-  const int e = (int)(t / plane) + 1;
+  const int e0 = (int)(t / plane) * kOp3Run + 1;
+  const int e1 = e0 + kOp3Run - 1 < K0 ? e0 + kOp3Run - 1 : K0;
   auto zat = [&](const double* Z, int g) -> double {   // position g = 0..nK0 (0 and nK0: boundary)
     return (g >= 1 && g <= m0) ? Z[(long long)(g - 1) * plane + pt] : 0.0;
   };
+  const double* A0 = mt.A0;
+  const double* C0 = mt.C0;
   double z1[B], z2[B], z1n[B], z2n[B];
 #pragma unroll
   for (int q = 0; q < B; ++q) {
-    const int g = NO * (e - 1) + q;
+    const int g = NO * (e0 - 1) + q;
     z1[q] = zat(Z1, g);
     z2[q] = zat(Z2, g);
-    z1n[q] = e < K0 ? zat(Z1, g + NO) : 0.0;
-    z2n[q] = e < K0 ? zat(Z2, g + NO) : 0.0;
   }
-  const double* A0 = mt.A0;
-  const double* C0 = mt.C0;
+  for (int e = e0; e <= e1; ++e) {
+    z1n[0] = z1[NO];
+    z2n[0] = z2[NO];
 #pragma unroll
-  for (int r = 1; r <= NO; ++r) {
-    const int g = NO * (e - 1) + r;
-    if (g > m0) break;
-    double ap = 0.0, cd = 0.0;
+    for (int q = 1; q < B; ++q) {
+      const int g = NO * e + q;
+      z1n[q] = e < K0 ? zat(Z1, g) : 0.0;
+      z2n[q] = e < K0 ? zat(Z2, g) : 0.0;
+    }
+    if (e == K0) {   // no element e+1: its row 0 (the boundary) contributes nothing
+      z1n[0] = 0.0;
+      z2n[0] = 0.0;
+    }
+#pragma unroll
+    for (int r = 1; r <= NO; ++r) {
+      const int g = NO * (e - 1) + r;
+      if (g > m0) break;
+      double ap = 0.0, cd = 0.0;
+#pragma unroll
+      for (int q = 0; q < B; ++q) {
+        if (q != r) ap += A0[r * B + q] * (z1[q] - z1[r]);
+        cd += C0[r * B + q] * z2[q];
+      }
+      if (r == NO) {   // the node also takes row 0 of element e+1
+#pragma unroll
+        for (int q = 1; q < B; ++q) ap += A0[q] * (z1n[q] - z1n[0]);
+#pragma unroll
+        for (int q = 0; q < B; ++q) cd += C0[q] * z2n[q];
+      }
+      const long long idx = (long long)(g - 1) * plane + pt;
+      const double lu = s0 * ap + cd;
+      const double res = f ? f[idx] - lu : lu;
+      if (out_f32) static_cast<float*>(out)[idx] = (float)res;
+      else static_cast<double*>(out)[idx] = res;
+    }
 #pragma unroll
     for (int q = 0; q < B; ++q) {
-      if (q != r) ap += A0[r * B + q] * (z1[q] - z1[r]);
-      cd += C0[r * B + q] * z2[q];
+      z1[q] = z1n[q];
+      z2[q] = z2n[q];
     }
-    if (r == NO) {   // the node also takes row 0 of element e+1
-#pragma unroll
-      for (int q = 1; q < B; ++q) ap += A0[q] * (z1n[q] - z1n[0]);
-#pragma unroll
-      for (int q = 0; q < B; ++q) cd += C0[q] * z2n[q];
-    }
-    const long long idx = (long long)(g - 1) * plane + pt;
-    const double lu = s0 * ap + cd;
-    const double res = f ? f[idx] - lu : lu;
-    if (out_f32) static_cast<float*>(out)[idx] = (float)res;
-    else static_cast<double*>(out)[idx] = res;
   }
 }
 
@@ -601,7 +631,8 @@ hipError_t launch_op3_order(const OpArgs& a, hipStream_t s) {
     b.hA[i] = a.hA[i + 1];
     b.hC[i] = a.hC[i + 1];
   }
-  const unsigned blocks = (unsigned)((plane * a.K[0] + 255) / 256);
+  const long long lanes = plane * ((a.K[0] + kOp3Run - 1) / kOp3Run);
+  const unsigned blocks = (unsigned)((lanes + 255) / 256);
   b.scale[0] = a.scale[1];
   b.scale[1] = a.scale[2];
   b.alpha = a.alpha;
