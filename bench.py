@@ -507,6 +507,42 @@ def bench_varcoef(args, torch, H, np, workloads, dev):
     return rec
 
 
+def profile_operator(args, torch, H, workloads):
+    """FP64 operator L u (the kernels of the FP32 forms' residual) on the
+    large 2D and the cube workloads, for profiler counter runs."""
+    out = {}
+    for name in ("large_2d", "cube_3d"):
+        cfg = workloads.CONFIGS[name]
+        shp = workloads.shape(cfg["orders"], cfg["Ks"])
+        u = torch.from_numpy(workloads.uniform_rhs(shp, seed=0)).cuda()
+        S = H.Solver(cfg["orders"], cfg["Ks"], cfg["X"], cfg["alpha"])
+        ws = S.operator_workspace(u.device)
+        r = torch.empty_like(u)
+        ms = time_calls(torch, lambda: S.apply_operator(u, out=r, ws=ws), args.steps, args.warmup)
+        out[name] = {"ms_per_apply": ms, "unknowns": u.numel()}
+        S.close()
+        del u, r, ws
+        torch.cuda.empty_cache()
+    import numpy as np
+    cfg = workloads.CONFIGS["varcoef_3d"]
+    shp = workloads.shape(cfg["orders"], cfg["Ks"])
+    S = H.Solver(cfg["orders"], cfg["Ks"], cfg["X"], cfg["alpha"])
+    c0, c1, ts = workloads.sine_coefficient(workloads.wavenumbers(3, seed=0))
+    tabs = []
+    for i, (n, K, X) in enumerate(zip(cfg["orders"], cfg["Ks"], cfg["X"])):
+        gx = H.Plan1D(n, K).table("gx")
+        pts = (np.arange(K)[:, None] + (gx[None, :] + 1.0) / 2.0) * (X / K)
+        tabs.append(torch.from_numpy(ts[i](pts)).cuda())
+    coef = H.make_coef(1, c0, c1, t=tuple(tabs))
+    u = torch.from_numpy(workloads.uniform_rhs(shp, seed=0)).cuda()
+    r = torch.empty_like(u)
+    ws = S.pcg_workspace(coef)
+    ms = time_calls(torch, lambda: S.apply_coef_operator(u, coef, out=r, ws=ws), args.steps, args.warmup)
+    out["varcoef_3d"] = {"ms_per_apply": ms, "unknowns": u.numel()}
+    S.close()
+    return {"profile_operator_only": out, "kernel_sha": kernel_sha()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -516,6 +552,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-fp64", action="store_true",
                     help="large_2d FP64 solves only (for profiler counter runs)")
+    ap.add_argument("--profile-operator", action="store_true",
+                    help="FP64 operator applies of large_2d and cube_3d only (for profiler runs)")
     ap.add_argument("--only", default="large_2d,batch_2d,cube_3d,varcoef_3d",
                     help="comma-separated workloads; large_2d is the headline")
     ap.add_argument("--calibration-copy", action="store_true",
@@ -541,6 +579,10 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+
+    if args.profile_operator:
+        print(json.dumps(profile_operator(args, torch, H, workloads)), flush=True)
+        return
 
     only = set(args.only.split(","))
     record = {"metric": "unknowns/s, 2D n=9 K=2^10: FP64 vs FP32+refine @1e-12 rel L2; % HBM peak",

@@ -342,6 +342,19 @@ struct VarShape {
   static constexpr int LDS = 5 * BBB * EPW * 8;
 };
 
+// LDS position of local point (a, b, c) of an element's b^3 block.  For b a
+// power of two the last two indices are XOR-ed with the first: then the b^2
+// lines of one element along any axis start in distinct 8-byte bank slots
+// (b = 4: 16 lines, 16 slots of a 128-byte bank row), where the plain
+// row-major block puts the lines along axes 1 and 2 on a quarter of them.
+template <int B>
+__device__ __forceinline__ int vloc(int a, int b, int c) {
+  if constexpr ((B & (B - 1)) == 0)
+    return a * B * B + B * (b ^ (a & (B - 1))) + (c ^ (a & (B - 1)));
+  else
+    return a * B * B + b * B + c;
+}
+
 // dst[line, q] (+)= sum_r m(q, r) (src[line, r] - ref) along axis ax of the
 // b^3 blocks; m(q, r) = M[q B + r] (or M[r B + q] transposed); ref = src at
 // r = 0 in difference form, 0 otherwise.
@@ -353,13 +366,14 @@ __device__ __forceinline__ void var_contract(const double* src, double* dst, int
   for (int task = tid; task < nel * BB; task += nthr) {
     const int el = task / BB, line = task - el * BB;
     const int i = line / B, j = line - i * B;
-    const int st = ax == 0 ? BB : (ax == 1 ? B : 1);
-    const int base = ax == 0 ? (i * B + j) : (ax == 1 ? (i * BB + j) : (i * BB + j * B));
-    const double* sp = src + el * BBB + base;
-    double* d = dst + el * BBB + base;
+    auto at = [&](int r) {   // point r of the line (i, j) along axis ax
+      return ax == 0 ? vloc<B>(r, i, j) : (ax == 1 ? vloc<B>(i, r, j) : vloc<B>(i, j, r));
+    };
+    const double* sp = src + el * BBB;
+    double* d = dst + el * BBB;
     double v[B];
 #pragma unroll
-    for (int r = 0; r < B; ++r) v[r] = sp[r * st];
+    for (int r = 0; r < B; ++r) v[r] = sp[at(r)];
     if (DIFF) {
 #pragma unroll
       for (int r = B - 1; r >= 0; --r) v[r] -= v[0];
@@ -369,7 +383,7 @@ __device__ __forceinline__ void var_contract(const double* src, double* dst, int
       double t = 0.0;
 #pragma unroll
       for (int r = 0; r < B; ++r) t += (TRANS ? M[r * B + q] : M[q * B + r]) * v[r];
-      if (ACC) d[q * st] += t; else d[q * st] = t;
+      if (ACC) d[at(q)] += t; else d[at(q)] = t;
     }
   }
 }
@@ -386,19 +400,21 @@ __device__ __forceinline__ void var_deriv(const double* src, double* dst, int ax
   for (int task = tid; task < nel * BB; task += nthr) {
     const int el = task / BB, line = task - el * BB;
     const int i = line / B, j = line - i * B;
-    const int st = ax == 0 ? BB : (ax == 1 ? B : 1);
-    const int base = el * BBB + (ax == 0 ? (i * B + j) : (ax == 1 ? (i * BB + j) : (i * BB + j * B)));
+    const int base = el * BBB;
+    auto at = [&](int r) {
+      return base + (ax == 0 ? vloc<B>(r, i, j) : (ax == 1 ? vloc<B>(i, r, j) : vloc<B>(i, j, r)));
+    };
     double v[B];
 #pragma unroll
-    for (int r = 0; r < B; ++r) v[r] = src[base + r * st];
+    for (int r = 0; r < B; ++r) v[r] = src[at(r)];
 #pragma unroll
     for (int q = 0; q < B; ++q) {
       double t = 0.0;
 #pragma unroll
       for (int r = 1; r < B; ++r) t += M[q * B + r] * (v[r] - v[0]);
-      const double wa = WA[base + q * st];
-      dst[base + q * st] = s * wa * t;
-      if (einit) einit[base + q * st] = alpha * wa * v[q];
+      const double wa = WA[at(q)];
+      dst[at(q)] = s * wa * t;
+      if (einit) einit[at(q)] = alpha * wa * v[q];
     }
   }
 }
@@ -430,7 +446,7 @@ __global__ __launch_bounds__(256) void varop3_order_kernel(VarOpArgs a, double* 
     double v = 0.0;
     if (g0 >= 1 && g0 <= m0 && g1 >= 1 && g1 <= m1 && g2 >= 1 && g2 <= m2)
       v = u[(g0 - 1) * a.stride[0] + (g1 - 1) * a.stride[1] + (g2 - 1) * a.stride[2]];
-    U[t] = v;
+    U[el * BBB + vloc<B>(loc / (B * B), (loc / B) % B, loc % B)] = v;
   }
   __syncthreads();
   // quadrature weight times coefficient at every Gauss point of the batch
@@ -446,7 +462,7 @@ __global__ __launch_bounds__(256) void varop3_order_kernel(VarOpArgs a, double* 
     } else if (a.kind == 2) {
       wq *= a.afull[eg * BBB + Q];
     }
-    WA[t] = wq;
+    WA[el * BBB + vloc<B>(q0, q1, q2)] = wq;
   }
 
   // Collocation form: U_q = (B (x) B (x) B) u at the Gauss points, then
@@ -474,7 +490,10 @@ __global__ __launch_bounds__(256) void varop3_order_kernel(VarOpArgs a, double* 
   var_contract<B, true, false, false>(U, E, 2, a.B[2], ne, tid, nthr);
   __syncthreads();
   double* out = elem_out + (rhs * nel + e0) * BBB;
-  for (int t = tid; t < ne * BBB; t += nthr) out[t] = E[t];
+  for (int t = tid; t < ne * BBB; t += nthr) {
+    const int el = t / BBB, loc = t - el * BBB;
+    out[t] = E[el * BBB + vloc<B>(loc / (B * B), (loc / B) % B, loc % B)];
+  }
 }
 
 template <int NO>
