@@ -513,8 +513,27 @@ __global__ __launch_bounds__(256) void varop_gather_kernel(VarOpArgs a, const do
                                                            long long total) {
   const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
   if (idx >= total) return;
-  const long long rhs = idx / a.per_rhs;
-  long long rem = idx - rhs * a.per_rhs;
+  // the point's right-hand side and grid indices: in 32-bit arithmetic when
+  // every index fits (a 64-bit division is a long emulated sequence)
+  long long rhs;
+  int qa[3] = {0, 0, 0};
+  if (total <= 0x7fffffffLL) {
+    const unsigned pr = (unsigned)a.per_rhs, r = (unsigned)idx / pr;
+    unsigned rem = (unsigned)idx - r * pr;
+    rhs = r;
+    for (int i = 0; i < N; ++i) {
+      const unsigned st = (unsigned)a.stride[i], q = rem / st;
+      rem -= q * st;
+      qa[i] = (int)q;
+    }
+  } else {
+    rhs = idx / a.per_rhs;
+    long long rem = idx - rhs * a.per_rhs;
+    for (int i = 0; i < N; ++i) {
+      qa[i] = (int)(rem / a.stride[i]);
+      rem -= (long long)qa[i] * a.stride[i];
+    }
+  }
   int ne[3] = {1, 1, 1}, el[3][2], rl[3][2], b[3];
   long long nel = 1;
   int npts = 1;
@@ -522,30 +541,41 @@ __global__ __launch_bounds__(256) void varop_gather_kernel(VarOpArgs a, const do
     b[i] = a.n[i] + 1;
     nel *= a.K[i];
     npts *= b[i];
-    const int q = (int)(rem / a.stride[i]);
-    rem -= (long long)q * a.stride[i];
-    const int g = q + 1, ni = a.n[i];
-    if (g % ni == 0) {
+    const unsigned g = (unsigned)qa[i] + 1u, ni = (unsigned)a.n[i];
+    const int ge = (int)(g / ni), gr = (int)(g - (unsigned)ge * ni);   // g >= 1, ni >= 1
+    if (gr == 0) {
       ne[i] = 2;
-      el[i][0] = g / ni - 1; rl[i][0] = ni;
-      el[i][1] = g / ni;     rl[i][1] = 0;
+      el[i][0] = ge - 1; rl[i][0] = (int)ni;
+      el[i][1] = ge;     rl[i][1] = 0;
     } else {
-      el[i][0] = g / ni; rl[i][0] = g % ni;
+      el[i][0] = ge; rl[i][0] = gr;
     }
   }
+  // the 1..2^N holding elements, axis 0 slowest (fixed summation order),
+  // unrolled with the second candidate of an axis taken where it exists
+  const double* eo = elem_out + (long long)rhs * nel * npts;
   double acc = 0.0;
-  for (int c0 = 0; c0 < ne[0]; ++c0)
-    for (int c1 = 0; c1 < (N > 1 ? ne[1] : 1); ++c1)
-      for (int c2 = 0; c2 < (N > 2 ? ne[2] : 1); ++c2) {
+#pragma unroll
+  for (int c0 = 0; c0 < 2; ++c0) {
+    if (c0 >= ne[0]) break;
+#pragma unroll
+    for (int c1 = 0; c1 < (N > 1 ? 2 : 1); ++c1) {
+      if (N > 1 && c1 >= ne[1]) break;
+#pragma unroll
+      for (int c2 = 0; c2 < (N > 2 ? 2 : 1); ++c2) {
+        if (N > 2 && c2 >= ne[2]) break;
         const int cs[3] = {c0, c1, c2};
         long long e = 0;
         int loc = 0;
+#pragma unroll
         for (int i = 0; i < N; ++i) {
           e = e * a.K[i] + el[i][cs[i]];
           loc = loc * b[i] + rl[i][cs[i]];
         }
-        acc += elem_out[((long long)rhs * nel + e) * npts + loc];
+        acc += eo[e * npts + loc];
       }
+    }
+  }
   const double res = a.f ? a.f[idx] - acc : acc;
   a.out[idx] = res;
 }
