@@ -512,6 +512,24 @@ def bench_varcoef(args, torch, H, np, workloads, dev):
     return rec
 
 
+def profile_bc(args, torch, H, workloads):
+    """FP64 algorithm-(a) solves of the large 2D mesh (n = 9, K = 1024 per
+    axis, alpha = 1) with both axes periodic, then both Neumann, for profiler
+    counter runs."""
+    cfg = workloads.CONFIGS["large_2d"]
+    out = {}
+    for bc in ("periodic", "neumann"):
+        S = H.Solver(cfg["orders"], cfg["Ks"], cfg["X"], 1.0, bcs=(bc, bc))
+        f = torch.rand(S.size, dtype=torch.float64, device="cuda")
+        u = torch.empty_like(f)
+        ms = time_calls(torch, lambda: S.solve(f, u, mode="fp64"), args.steps, args.warmup)
+        out[bc] = {"ms_per_solve": ms, "unknowns": S.size}
+        S.close()
+        del f, u
+        torch.cuda.empty_cache()
+    return {"profile_bc_only": out, "kernel_sha": kernel_sha()}
+
+
 def profile_operator(args, torch, H, workloads):
     """FP64 operator L u (the kernels of the FP32 forms' residual) on the
     large 2D and the cube workloads, for profiler counter runs."""
@@ -557,6 +575,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-fp64", action="store_true",
                     help="large_2d FP64 solves only (for profiler counter runs)")
+    ap.add_argument("--profile-bc", action="store_true",
+                    help="FP64 solves of large_2d with periodic and with Neumann axes only (for profiler runs)")
     ap.add_argument("--profile-operator", action="store_true",
                     help="FP64 operator applies of large_2d and cube_3d only (for profiler runs)")
     ap.add_argument("--only", default="large_2d,batch_2d,cube_3d,varcoef_3d",
@@ -587,6 +607,9 @@ def main():
 
     if args.profile_operator:
         print(json.dumps(profile_operator(args, torch, H, workloads)), flush=True)
+        return
+    if args.profile_bc:
+        print(json.dumps(profile_bc(args, torch, H, workloads)), flush=True)
         return
 
     only = set(args.only.split(","))
